@@ -1,0 +1,138 @@
+// Internal structures shared by the HIP kernels and the host runtime of the
+// EECMG library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace eecmg {
+
+constexpr int kMaxLevels = 16;
+constexpr int kMaxRadius = 12;
+constexpr int kMaxLaunchJobs = 240;
+constexpr int kNPart = 4;  // doubles per tile in the partial-sum array
+
+// Smoother tiles: one wave spans the tile width, four waves stack kV rows each.
+constexpr int kTW = 64;
+constexpr int kV = 8;
+constexpr int kTH = 4 * kV;
+// Transfer / element-wise tiles: 64 x 16 pixels per 256-thread block.
+constexpr int kXW = 64;
+constexpr int kXH = 16;
+
+// Stop reasons (same values as eecmg_stop_reason).
+enum : int32_t { kStopNone = 0, kStopDiscrepancy = 1, kStopCap = 2, kStopGuard = 3, kStopNonFinite = 4 };
+
+// Device-resident smoother scalars of one job (one per slot).  Every scalar
+// of the Krylov recurrences lives here in FP64 and is only touched by the
+// finalize kernels, so the host never reads them during a level.
+struct SolverState {
+  double gamma, gamma0, alpha, beta;  // CGLS: <s,s>, initial <s,s>, step, direction update
+  double rr, rr0, rq, eta;            // <r,r>, initial <r,r>, <r,q> (MR), <q,q>
+  int32_t k;                          // iterations completed on this level
+  int32_t done;                       // stop reason, 0 while running
+  int32_t par;                        // ping-pong parity of r/p/q buffers
+  int32_t level;                      // level the state belongs to
+  int32_t pending;                    // MR: a step alpha is waiting to be applied
+  int32_t seq;                        // finalize counter (diagnostics)
+  int32_t pad[2];
+};
+
+struct LevelRecord {
+  int32_t iters, reason;
+  double rms;
+};
+
+// Everything a kernel needs about one job at one level.  The host builds one
+// descriptor per (slot, level) when a job is admitted and uploads the table
+// once; kernels find theirs through the launch list.
+struct JobDesc {
+  // smoother on this level
+  void* g;
+  void* u;
+  void* r[2];
+  void* p[2];
+  void* s;
+  void* q[2];
+  const void* taps;    // psf_l, element type of the precision, (2r+1)^2
+  const void* taps_t;  // flipped psf_l (operator H^T)
+  int32_t h, w, pitch, rad;
+  int32_t tiles_x, ntiles;  // smoother tiles (kTH x kTW)
+  int32_t cap, level;
+  int32_t stop_rule, smoother;
+  double cdelta, eps2;
+  SolverState* st;
+  LevelRecord* rec;  // kMaxLevels records of this job
+  double* partials;  // ntiles * kNPart
+  // transfer into this level from level-2 (A) and level-1 (B)
+  const void* uA;
+  const void* uB;
+  void* t1;
+  void* t2;
+  int32_t hA, wA, pA, hB, wB, pB;
+  double pm_k, tau, smooth_h;
+  // restriction of the dense input / copy of the dense output (finest level)
+  const void* g_in;
+  const void* u_in;  // optional initial guess on the finest level (operator calls)
+  void* u_out;
+  int32_t H, W, L, fine_pitch;
+  void* g_lv[kMaxLevels];
+  void* u_lv[kMaxLevels];
+  int32_t lh[kMaxLevels], lw[kMaxLevels], lp[kMaxLevels];
+};
+
+// Kernel-argument list of the jobs one launch covers.  Block b belongs to the
+// entry e with start[e] <= b < start[e+1]; job[e] indexes the JobDesc table.
+struct LaunchList {
+  int32_t n;
+  int32_t total;
+  int32_t job[kMaxLaunchJobs];
+  int32_t start[kMaxLaunchJobs + 1];
+};
+
+// Stages launched by the runtime.
+enum Stage : int32_t {
+  kRestrict = 0,    // dense g -> level pyramid; zero u pyramid (or copy u_in)
+  kCgInit1,         // r = g - H u0
+  kCgInit2,         // s = H^T r, p = s
+  kCgFinInit,
+  kCgA,             // p = s + beta p, q = H p
+  kCgFinA,
+  kCgB,             // r -= alpha q, s = H^T r, u += alpha p
+  kCgFinB,
+  kMrInit,          // r = g - H u0
+  kMrFinInit,
+  kMrPass,          // r -= alpha q, u += alpha r, q = H r
+  kMrFin,
+  kXfExtrap,        // Pi: (uA, uB) -> t2 on grid B
+  kXfQuad,          // P: src (grid B) -> t1 (grid C)
+  kXfLinear,        // L: uB -> t1
+  kXfSmooth,        // S: src -> dst
+  kXfPm,            // D: src -> dst
+  kOutCopy,         // u (finest, pitched) -> dense u_out
+  kNumStages
+};
+
+// Buffer selectors of the transfer stages.
+enum XBuf : int32_t { kBufU = 0, kBufT1 = 1, kBufT2 = 2, kBufUB = 3 };
+
+// Conv implementation families.
+enum ConvKind : int32_t { kConvGeneral = 0 };
+
+// Host-side launchers (defined in eecmg_kernels.hip).
+hipError_t launch_stage(Stage st, bool f64, int rmax_class, const LaunchList& ll, const JobDesc* descs,
+                        int src, int dst, hipStream_t stream);
+int rmax_class_for(int r);
+int blocks_for_stage(Stage st, const JobDesc& d);
+
+// Operator kernels on dense buffers (one image, no job table).
+hipError_t op_conv(const void* x, void* y, int H, int W, const void* taps, int r, bool f64, hipStream_t s);
+hipError_t op_restrict(const void* gf, int Hf, int Wf, void* gc, bool f64, hipStream_t s);
+hipError_t op_extrapolate(const void* uA, const void* uB, int HB, int WB, void* ut, bool f64, hipStream_t s);
+hipError_t op_prolong_quad(const void* ut, int HC, int WC, void* uC, bool f64, hipStream_t s);
+hipError_t op_prolong_linear(const void* uB, int HC, int WC, void* uC, bool f64, hipStream_t s);
+hipError_t op_local_smooth(const void* u, void* out, int H, int W, double h, bool f64, hipStream_t s);
+hipError_t op_pm_step(const void* u, void* out, int H, int W, double k, double tau, bool f64, hipStream_t s);
+
+}  // namespace eecmg

@@ -1,0 +1,1620 @@
+// Host runtime of the EECMG library: level plans, a device memory arena, the
+// job engine that drives every restore (plain, batched and served requests
+// all run through it), the request loop with continuous batching, and the C
+// ABI declared in include/eecmg.h.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/eecmg.h"
+#include "eecmg_internal.h"
+
+namespace eecmg {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define EECMG_HIP(call)                                                                 \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess) return fail(EECMG_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+constexpr size_t kTapsSlotBytes = 32 << 10;  // pinned staging of one job's PSF pyramid
+
+// ---------------------------------------------------------------------------
+// Level plan (Section 2: nested grids, m_l rule; eq. 12-14: restriction and
+// coarse operators)
+// ---------------------------------------------------------------------------
+struct LevelPlan {
+  int h = 0, w = 0, pitch = 0, rad = 0, cap = 0, ntiles = 0, tiles_x = 0;
+  std::vector<double> psf;  // (2 rad + 1)^2, FP64
+};
+
+struct Plan {
+  int H = 0, W = 0, L = 0;
+  bool f64 = false;
+  size_t esz = 4;
+  eecmg_params prm{};
+  double k = 10.0;
+  double eps2 = 0.0;
+  LevelPlan lv[kMaxLevels];
+  std::vector<int> order;  // 0-based levels in solve order
+  bool own_gin = false, own_uout = false;
+  // device layout (byte offsets inside the job allocation)
+  size_t off_gin = 0, off_uout = 0, off_part = 0, taps_bytes = 0;  // taps region at offset 0
+  size_t off_g[kMaxLevels] = {}, off_u[kMaxLevels] = {}, off_taps[kMaxLevels] = {}, off_tapst[kMaxLevels] = {};
+  size_t off_work[7] = {};  // r0 r1 p0 p1 s q0 q1
+  size_t bytes = 0;
+  int max_tiles = 0;
+};
+
+// Economic iteration counts (Section 2): for l > L/2,
+// ceil((L - L/2)^2 4^(L-l)); otherwise ceil((L - 1.5 l) 4^(l-1)); at least 1.
+static int economic_cap(int L, int l) {
+  const double half = 0.5 * L;
+  double t;
+  if (l > half)
+    t = (L - half) * (L - half) * std::ldexp(1.0, 2 * (L - l));
+  else
+    t = (L - 1.5 * l) * std::ldexp(1.0, 2 * (l - 1));
+  const double c = std::ceil(t);
+  return c < 1.0 ? 1 : (int)c;
+}
+
+// psf_c(a, b) = s psf(2a, 2b), radius r/2; s per coarse_psf_mode.
+static int decimate_psf(const std::vector<double>& psf, int r, int mode, std::vector<double>& out) {
+  const int n = 2 * r + 1, rc = r / 2, nc = 2 * rc + 1;
+  double tot = 0.0, sub = 0.0;
+  for (double v : psf) tot += v;
+  for (int a = -rc; a <= rc; ++a)
+    for (int b = -rc; b <= rc; ++b) sub += psf[(2 * a + r) * n + (2 * b + r)];
+  double s;
+  if (mode == 0) {
+    if (sub == 0.0) return fail(EECMG_EINVAL, "coarse PSF: the decimated taps sum to zero (use coarse_psf_mode 1 or 2)");
+    s = tot / sub;
+  } else if (mode == 1) {
+    s = 4.0;
+  } else if (mode == 2) {
+    s = 1.0;
+  } else {
+    return fail(EECMG_EINVAL, "coarse_psf_mode must be 0, 1 or 2");
+  }
+  out.assign((size_t)nc * nc, 0.0);
+  for (int a = -rc; a <= rc; ++a)
+    for (int b = -rc; b <= rc; ++b) out[(a + rc) * nc + (b + rc)] = s * psf[(2 * a + r) * n + (2 * b + r)];
+  return EECMG_OK;
+}
+
+static void default_params(eecmg_params* p) {
+  std::memset(p, 0, sizeof(*p));
+  p->struct_size = sizeof(eecmg_params);
+  p->precision = EECMG_FP32;
+  p->stop_rule = 1;
+  p->delta = 1.0;
+  p->c = 1.1;
+  p->tau = 0.2;
+  p->pm_steps = 1;
+  p->smooth_h = 1.0;
+  p->coarse_psf_mode = 0;
+  p->guard_eps = 0.0;
+  p->smoother = EECMG_SMOOTHER_CGLS;
+  p->cascade = EECMG_CASCADE_EECMG;
+  p->stats = nullptr;
+}
+
+static int build_plan(int H, int W, const double* psf, int r, int L, const int* caps, double k,
+                      const eecmg_params* params, bool own_io, Plan& P) {
+  eecmg_params prm;
+  if (params) {
+    if (params->struct_size != sizeof(eecmg_params)) return fail(EECMG_EINVAL, "params->struct_size mismatch");
+    prm = *params;
+  } else {
+    default_params(&prm);
+  }
+  if (prm.precision < 0 || prm.precision > 2) return fail(EECMG_EINVAL, "precision must be 0, 1 or 2");
+  if (L < 1 || L > kMaxLevels) return fail(EECMG_EINVAL, "n_levels must be in [1, 16]");
+  if (H < 3 || W < 3) return fail(EECMG_EINVAL, "image must be at least 3 x 3");
+  if ((long long)H * W > (1LL << 31)) return fail(EECMG_EINVAL, "image too large");
+  if (r < 0 || r > kMaxRadius) return fail(EECMG_EINVAL, "psf_radius must be in [0, 12]");
+  if (!psf) return fail(EECMG_EINVAL, "psf is NULL");
+  if (!(k > 0.0) || !std::isfinite(k)) return fail(EECMG_EINVAL, "k must be > 0");
+  if (!(prm.tau > 0.0 && prm.tau <= 0.25)) return fail(EECMG_EINVAL, "tau must be in (0, 1/4]");
+  if (prm.pm_steps < 0 || prm.pm_steps > 64) return fail(EECMG_EINVAL, "pm_steps must be in [0, 64]");
+  if (!(prm.smooth_h > 0.0) || !std::isfinite(prm.smooth_h)) return fail(EECMG_EINVAL, "smooth_h must be > 0");
+  if (!(prm.delta >= 0.0) || !std::isfinite(prm.delta)) return fail(EECMG_EINVAL, "delta must be >= 0");
+  if (prm.stop_rule && !(prm.c > 1.0)) return fail(EECMG_EINVAL, "c must be > 1 with the stopping rule");
+  if (!(prm.guard_eps >= 0.0) || prm.guard_eps >= 1.0) return fail(EECMG_EINVAL, "guard_eps must be in [0, 1)");
+  if (prm.smoother < 0 || prm.smoother > 1) return fail(EECMG_EINVAL, "smoother must be 0 (CGLS) or 1 (MR)");
+  if (prm.cascade < 0 || prm.cascade > 2) return fail(EECMG_EINVAL, "cascade must be 0, 1 or 2");
+  const int n = 2 * r + 1;
+  for (int i = 0; i < n * n; ++i)
+    if (!std::isfinite(psf[i])) return fail(EECMG_EINVAL, "psf has a non-finite tap");
+
+  P = Plan();
+  P.H = H;
+  P.W = W;
+  P.L = L;
+  P.f64 = prm.precision == EECMG_FP64;
+  P.esz = P.f64 ? 8 : 4;
+  P.prm = prm;
+  P.prm.stats = nullptr;
+  P.k = k;
+  const double eps = prm.guard_eps > 0.0 ? prm.guard_eps : (P.f64 ? 1e-14 : 1e-6);
+  P.eps2 = eps * eps;
+  P.own_gin = P.own_uout = own_io;
+  // level sizes, coarsest first
+  int hh = H, ww = W;
+  for (int l = L - 1; l >= 0; --l) {
+    P.lv[l].h = hh;
+    P.lv[l].w = ww;
+    hh = (hh + 1) / 2;
+    ww = (ww + 1) / 2;
+  }
+  for (int l = 0; l < L; ++l)
+    if (P.lv[l].h < 3 || P.lv[l].w < 3)
+      return fail(EECMG_EINVAL, "too many levels: every level needs at least 3 nodes per axis");
+  // caps
+  for (int l = 0; l < L; ++l) {
+    const int c = caps ? caps[l] : economic_cap(L, l + 1);
+    if (c < 0) return fail(EECMG_EINVAL, "iters_per_level entries must be >= 0");
+    P.lv[l].cap = c;
+  }
+  // PSF pyramid, finest first
+  P.lv[L - 1].rad = r;
+  P.lv[L - 1].psf.assign(psf, psf + (size_t)n * n);
+  for (int l = L - 2; l >= 0; --l) {
+    const int rc = decimate_psf(P.lv[l + 1].psf, P.lv[l + 1].rad, prm.coarse_psf_mode, P.lv[l].psf);
+    if (rc != EECMG_OK) return rc;
+    P.lv[l].rad = P.lv[l + 1].rad / 2;
+  }
+  // solve order
+  P.order.clear();
+  for (int l = 0; l < L; ++l) P.order.push_back(l);
+  // tiles and layout
+  const size_t pitch_elems = P.f64 ? 32 : 64;  // 256-byte rows
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  for (int l = 0; l < L; ++l) {
+    const size_t nt = (size_t)(2 * P.lv[l].rad + 1) * (2 * P.lv[l].rad + 1);
+    P.off_taps[l] = take(nt * P.esz);
+    P.off_tapst[l] = take(nt * P.esz);
+  }
+  P.taps_bytes = off;
+  if (P.taps_bytes > kTapsSlotBytes) return fail(EECMG_EINVAL, "PSF pyramid too large");
+  if (P.own_gin) P.off_gin = take((size_t)H * W * P.esz);
+  if (P.own_uout) P.off_uout = take((size_t)H * W * P.esz);
+  for (int l = 0; l < L; ++l) {
+    LevelPlan& lp = P.lv[l];
+    lp.pitch = (int)align_up((size_t)lp.w, pitch_elems);
+    lp.tiles_x = (lp.w + kTW - 1) / kTW;
+    lp.ntiles = lp.tiles_x * ((lp.h + kTH - 1) / kTH);
+    P.max_tiles = std::max(P.max_tiles, lp.ntiles);
+    P.off_g[l] = take((size_t)lp.h * lp.pitch * P.esz);
+    P.off_u[l] = take((size_t)lp.h * lp.pitch * P.esz);
+  }
+  const size_t fine = (size_t)P.lv[L - 1].h * P.lv[L - 1].pitch * P.esz;
+  for (int i = 0; i < 7; ++i) P.off_work[i] = take(fine);
+  P.off_part = take((size_t)P.max_tiles * kNPart * sizeof(double));
+  P.bytes = off;
+  return EECMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Device arena: one slab, first-fit free list with coalescing.
+// ---------------------------------------------------------------------------
+class Arena {
+ public:
+  ~Arena() {}
+  int reserve(size_t bytes) {
+    if (bytes <= size_) return EECMG_OK;
+    if (used_ != 0) return fail(EECMG_ENOMEM, "arena busy, cannot grow");
+    if (base_) (void)hipFree(base_);
+    base_ = nullptr;
+    size_ = 0;
+    free_.clear();
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(EECMG_ENOMEM, "hipMalloc of the device arena failed (" + std::to_string(bytes) + " bytes)");
+    }
+    base_ = (char*)p;
+    size_ = bytes;
+    free_[0] = bytes;
+    return EECMG_OK;
+  }
+  void release() {
+    if (base_) (void)hipFree(base_);
+    base_ = nullptr;
+    size_ = used_ = 0;
+    free_.clear();
+  }
+  void* alloc(size_t n) {
+    n = align_up(n, 256);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        const size_t off = it->first, len = it->second;
+        free_.erase(it);
+        if (len > n) free_[off + n] = len - n;
+        used_ += n;
+        return base_ + off;
+      }
+    }
+    return nullptr;
+  }
+  void free(void* p, size_t n) {
+    n = align_up(n, 256);
+    size_t off = (char*)p - base_;
+    used_ -= n;
+    auto nx = free_.lower_bound(off);
+    if (nx != free_.end() && off + n == nx->first) {
+      n += nx->second;
+      nx = free_.erase(nx);
+    }
+    if (nx != free_.begin()) {
+      auto pv = std::prev(nx);
+      if (pv->first + pv->second == off) {
+        pv->second += n;
+        return;
+      }
+    }
+    free_[off] = n;
+  }
+  size_t size() const { return size_; }
+  size_t used() const { return used_; }
+  size_t largest_free() const {
+    size_t m = 0;
+    for (auto& kv : free_) m = std::max(m, kv.second);
+    return m;
+  }
+
+ private:
+  char* base_ = nullptr;
+  size_t size_ = 0, used_ = 0;
+  std::map<size_t, size_t> free_;
+};
+
+
+// ---------------------------------------------------------------------------
+// Kernel timing (diagnostics): HIP events around selected launches.
+// ---------------------------------------------------------------------------
+struct Profiler {
+  std::mutex mu;
+  std::atomic<bool> on{false};
+  int min_blocks = 0;
+  struct Rec {
+    int stage;
+    hipEvent_t a, b;
+    double pixels;
+  };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  int launches[kNumStages] = {};
+  double ms[kNumStages] = {};
+  double pixels[kNumStages] = {};
+
+  hipEvent_t ev() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  void harvest() {
+    for (auto& r : pending) {
+      float t = 0.f;
+      if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+        launches[r.stage] += 1;
+        ms[r.stage] += t;
+        pixels[r.stage] += r.pixels;
+      }
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    pending.clear();
+  }
+};
+
+static Profiler& profiler() {
+  static Profiler* p = new Profiler();
+  return *p;
+}
+
+static bool profiled_stage(Stage st) {
+  return st == kCgInit1 || st == kCgInit2 || st == kCgA || st == kCgB || st == kMrInit || st == kMrPass ||
+         st == kXfExtrap || st == kXfQuad || st == kXfLinear || st == kXfSmooth || st == kXfPm;
+}
+
+// ---------------------------------------------------------------------------
+// Jobs and the engine
+// ---------------------------------------------------------------------------
+constexpr int kMaxSlots = EECMG_MAX_SLOTS;
+static_assert(kMaxSlots <= kMaxLaunchJobs, "one launch must be able to cover every slot");
+
+struct Job {
+  Plan plan;
+  int slot = -1;
+  char* mem = nullptr;
+  const void* g_in_dev = nullptr;
+  const void* u_init_dev = nullptr;
+  void* u_out_dev = nullptr;
+  enum Phase { kNew, kStartLevel, kIter, kOutput, kWaitOut, kFinished } phase = kNew;
+  int oi = 0;
+  int issued = 0;
+  int next_chunk = 1;
+  int confirmed = 0;
+  bool level_done_seen = false;
+  uint64_t level_rb_seq = 0;  // first readback that can describe the current level
+  hipEvent_t done_ev = nullptr;
+  int status = EECMG_OK;
+  LevelRecord rec[kMaxLevels];
+  // served-request extras
+  uint64_t id = 0;
+  void* host_in = nullptr;   // pinned staging of g
+  void* host_out = nullptr;  // pinned staging of u
+  size_t host_bytes = 0;
+  std::atomic<bool> cancelled{false};
+  double t_submit = 0.0, t_done = 0.0;
+  int cur_level() const { return plan.order[oi]; }
+};
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+class Engine {
+ public:
+  explicit Engine(int device) : device_(device) {}
+  ~Engine() {}
+
+  int init(hipStream_t stream) {
+    EECMG_HIP(hipSetDevice(device_));
+    stream_ = stream;
+    EECMG_HIP(hipMalloc(&d_desc_, sizeof(JobDesc) * kMaxSlots * kMaxLevels));
+    EECMG_HIP(hipMalloc(&d_state_, sizeof(SolverState) * kMaxSlots));
+    EECMG_HIP(hipMalloc(&d_rec_, sizeof(LevelRecord) * kMaxSlots * kMaxLevels));
+    EECMG_HIP(hipMemset(d_state_, 0, sizeof(SolverState) * kMaxSlots));
+    EECMG_HIP(hipHostMalloc((void**)&h_desc_, sizeof(JobDesc) * kMaxSlots * kMaxLevels, hipHostMallocDefault));
+    EECMG_HIP(hipHostMalloc((void**)&h_rec_, sizeof(LevelRecord) * kMaxSlots * kMaxLevels, hipHostMallocDefault));
+    EECMG_HIP(hipHostMalloc((void**)&h_taps_, kTapsSlotBytes * kMaxSlots, hipHostMallocDefault));
+    for (auto& r : rb_) {
+      EECMG_HIP(hipHostMalloc((void**)&r.h, sizeof(SolverState) * kMaxSlots, hipHostMallocDefault));
+      EECMG_HIP(hipEventCreateWithFlags(&r.ev, hipEventDisableTiming));
+      r.pending = false;
+    }
+    slots_.assign(kMaxSlots, nullptr);
+    return EECMG_OK;
+  }
+
+  // Free the engine's own device and pinned memory (the arena is released
+  // separately).  No job may be active.
+  void shutdown() {
+    if (d_desc_) (void)hipFree(d_desc_);
+    if (d_state_) (void)hipFree(d_state_);
+    if (d_rec_) (void)hipFree(d_rec_);
+    if (h_desc_) (void)hipHostFree(h_desc_);
+    if (h_rec_) (void)hipHostFree(h_rec_);
+    if (h_taps_) (void)hipHostFree(h_taps_);
+    for (auto& r : rb_) {
+      if (r.h) (void)hipHostFree(r.h);
+      if (r.ev) (void)hipEventDestroy(r.ev);
+      r.h = nullptr;
+      r.ev = nullptr;
+    }
+    d_desc_ = nullptr;
+    d_state_ = nullptr;
+    d_rec_ = nullptr;
+    h_desc_ = nullptr;
+    h_rec_ = nullptr;
+    h_taps_ = nullptr;
+  }
+
+  void set_stream(hipStream_t s) { stream_ = s; }
+  // First HIP error met by an asynchronous call (sticky), and its reset.
+  hipError_t error() const { return err_; }
+  void clear_error() { err_ = hipSuccess; }
+  hipStream_t stream() const { return stream_; }
+  Arena& arena() { return arena_; }
+  int active() const { return n_active_; }
+
+  // Give the job a slot and device memory; upload its per-level descriptors.
+  // EAGAIN when no slot or memory is free right now.
+  int admit(Job* j) {
+    int slot = -1;
+    for (int i = 0; i < kMaxSlots; ++i)
+      if (!slots_[i]) {
+        slot = i;
+        break;
+      }
+    if (slot < 0) return EECMG_EAGAIN;
+    char* mem = (char*)arena_.alloc(j->plan.bytes);
+    if (!mem) return EECMG_EAGAIN;
+    j->slot = slot;
+    j->mem = mem;
+    slots_[slot] = j;
+    ++n_active_;
+    j->phase = Job::kNew;
+    j->oi = 0;
+    // taps (element type of the precision, and flipped for H^T), staged in
+    // this slot's pinned buffer and copied with the descriptors
+    const Plan& P = j->plan;
+    char* tb = h_taps_ + (size_t)slot * kTapsSlotBytes;
+    for (int l = 0; l < P.L; ++l) {
+      const LevelPlan& lp = P.lv[l];
+      const int n = 2 * lp.rad + 1;
+      for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {
+          const double v = lp.psf[a * n + b], vt = lp.psf[(n - 1 - a) * n + (n - 1 - b)];
+          if (P.f64) {
+            ((double*)(tb + P.off_taps[l]))[a * n + b] = v;
+            ((double*)(tb + P.off_tapst[l]))[a * n + b] = vt;
+          } else {
+            ((float*)(tb + P.off_taps[l]))[a * n + b] = (float)v;
+            ((float*)(tb + P.off_tapst[l]))[a * n + b] = (float)vt;
+          }
+        }
+    }
+    chk(hipMemcpyAsync(mem, tb, P.taps_bytes, hipMemcpyHostToDevice, stream_));
+    if (P.own_gin) j->g_in_dev = mem + P.off_gin;
+    if (P.own_uout) j->u_out_dev = mem + P.off_uout;
+    JobDesc* hd = h_desc_ + (size_t)slot * kMaxLevels;
+    for (int l = 0; l < P.L; ++l) fill_desc(j, l, hd[l]);
+    chk(hipMemcpyAsync(d_desc_ + (size_t)slot * kMaxLevels, hd, sizeof(JobDesc) * P.L, hipMemcpyHostToDevice, stream_));
+    return EECMG_OK;
+  }
+
+  // Issue one round of work for every active job.  Returns true if anything
+  // was launched.
+  bool step(std::vector<Job*>& finished) {
+    consume_readbacks(false);
+    finished.clear();
+    // action lists
+    std::vector<Job*> restrict_l, out_l;
+    std::vector<std::pair<Job*, int>> xfer_l;  // job, level
+    std::vector<Job*> init_l;
+    std::vector<std::pair<Job*, int>> iter_l;  // job, chunk
+    bool launched = false;
+    for (int s = 0; s < kMaxSlots; ++s) {
+      Job* j = slots_[s];
+      if (!j) continue;
+      bool again = true, started = false;
+      while (again) {
+        again = false;
+        switch (j->phase) {
+          case Job::kNew:
+            restrict_l.push_back(j);
+            j->phase = Job::kStartLevel;
+            j->oi = 0;
+            again = true;
+            break;
+          case Job::kStartLevel: {
+            // at most one level start per job and step: the launches of one
+            // step are grouped by stage, so a second level would run its
+            // transfer before the first level's initialisation
+            if (started) break;
+            started = true;
+            const int l = j->cur_level();
+            if (needs_transfer(j, l)) xfer_l.push_back({j, l});
+            init_l.push_back(j);
+            j->issued = 0;
+            j->confirmed = 0;
+            j->next_chunk = 1;
+            j->level_done_seen = false;
+            j->level_rb_seq = rb_seq_ + 1;  // the readback issued at the end of this step
+            j->phase = Job::kIter;
+            again = true;
+            break;
+          }
+          case Job::kIter: {
+            const LevelPlan& lp = j->plan.lv[j->cur_level()];
+            if (j->cancelled || j->level_done_seen || j->issued >= lp.cap) {
+              if (!j->cancelled && j->oi + 1 < (int)j->plan.order.size()) {
+                j->oi += 1;
+                j->phase = Job::kStartLevel;
+                again = !started;
+              } else {
+                out_l.push_back(j);
+                j->phase = Job::kOutput;
+              }
+              break;
+            }
+            const int ahead = j->issued - j->confirmed;
+            int chunk = std::min(j->next_chunk, lp.cap - j->issued);
+            chunk = std::min(chunk, kMaxAhead - ahead);
+            if (chunk > 0) {
+              iter_l.push_back({j, chunk});
+              j->issued += chunk;
+              j->next_chunk = std::min(2 * j->next_chunk, kMaxChunk);
+            }
+            break;
+          }
+          case Job::kWaitOut:
+            if (hipEventQuery(j->done_ev) == hipSuccess) {
+              finish(j);
+              finished.push_back(j);
+            }
+            break;
+          default: break;
+        }
+      }
+    }
+    // launches, in dependency order
+    if (!restrict_l.empty()) {
+      launch_group(kRestrict, restrict_l, -1, false, 0, -1, -1);
+      launched = true;
+    }
+    if (!xfer_l.empty()) {
+      issue_transfers(xfer_l);
+      launched = true;
+    }
+    if (!init_l.empty()) {
+      issue_inits(init_l);
+      launched = true;
+    }
+    if (!iter_l.empty()) {
+      issue_iterations(iter_l);
+      launched = true;
+    }
+    for (Job* j : out_l) {
+      std::vector<Job*> one{j};
+      launch_group(kOutCopy, one, j->plan.L - 1, j->plan.f64, 0, -1, -1);
+      chk(hipMemcpyAsync(h_rec_ + (size_t)j->slot * kMaxLevels, d_rec_ + (size_t)j->slot * kMaxLevels,
+                     sizeof(LevelRecord) * kMaxLevels, hipMemcpyDeviceToHost, stream_));
+      if (j->host_out)
+        chk(hipMemcpyAsync(j->host_out, j->u_out_dev, (size_t)j->plan.H * j->plan.W * j->plan.esz,
+                       hipMemcpyDeviceToHost, stream_));
+      if (!j->done_ev) chk(hipEventCreateWithFlags(&j->done_ev, hipEventDisableTiming));
+      chk(hipEventRecord(j->done_ev, stream_));
+      j->phase = Job::kWaitOut;
+      launched = true;
+    }
+    if (!iter_l.empty() || !init_l.empty()) issue_readback();
+    return launched;
+  }
+
+  // Block until some outstanding GPU work has completed (readback or output).
+  void wait_some() {
+    for (auto& r : rb_)
+      if (r.pending && r.seq == oldest_pending_seq()) {
+        chk(hipEventSynchronize(r.ev));
+        consume_readbacks(false);
+        return;
+      }
+    for (Job* j : slots_)
+      if (j && j->phase == Job::kWaitOut) {
+        chk(hipEventSynchronize(j->done_ev));
+        return;
+      }
+  }
+
+  // Release a finished job's slot and memory.
+  void release(Job* j) {
+    if (j->slot >= 0) {
+      slots_[j->slot] = nullptr;
+      --n_active_;
+    }
+    if (j->mem) arena_.free(j->mem, j->plan.bytes);
+    j->mem = nullptr;
+    j->slot = -1;
+    if (j->done_ev) (void)hipEventDestroy(j->done_ev);
+    j->done_ev = nullptr;
+  }
+
+  int device() const { return device_; }
+
+ private:
+  static constexpr int kMaxChunk = 16;
+  static constexpr int kMaxAhead = 48;
+
+  struct Readback {
+    SolverState* h = nullptr;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+    uint64_t seq = 0;
+  };
+
+  uint64_t oldest_pending_seq() const {
+    uint64_t m = UINT64_MAX;
+    for (auto& r : rb_)
+      if (r.pending) m = std::min(m, r.seq);
+    return m;
+  }
+
+  bool needs_transfer(const Job* j, int l) const {
+    return j->plan.prm.cascade == EECMG_CASCADE_EECMG ? l >= 2 : l >= 1;
+  }
+
+  void fill_desc(const Job* j, int l, JobDesc& d) {
+    const Plan& P = j->plan;
+    const LevelPlan& lp = P.lv[l];
+    char* m = j->mem;
+    std::memset(&d, 0, sizeof(d));
+    d.g = m + P.off_g[l];
+    d.u = m + P.off_u[l];
+    d.r[0] = m + P.off_work[0];
+    d.r[1] = m + P.off_work[1];
+    d.p[0] = m + P.off_work[2];
+    d.p[1] = m + P.off_work[3];
+    d.s = m + P.off_work[4];
+    d.q[0] = m + P.off_work[5];
+    d.q[1] = m + P.off_work[6];
+    d.taps = m + P.off_taps[l];
+    d.taps_t = m + P.off_tapst[l];
+    d.h = lp.h;
+    d.w = lp.w;
+    d.pitch = lp.pitch;
+    d.rad = lp.rad;
+    d.tiles_x = lp.tiles_x;
+    d.ntiles = lp.ntiles;
+    d.cap = lp.cap;
+    d.level = l;
+    d.stop_rule = P.prm.stop_rule;
+    d.smoother = P.prm.smoother;
+    d.cdelta = P.prm.c * P.prm.delta;
+    d.eps2 = P.eps2;
+    d.st = d_state_ + j->slot;
+    d.rec = d_rec_ + (size_t)j->slot * kMaxLevels;
+    d.partials = (double*)(m + P.off_part);
+    if (l >= 1) {
+      d.uB = m + P.off_u[l - 1];
+      d.hB = P.lv[l - 1].h;
+      d.wB = P.lv[l - 1].w;
+      d.pB = P.lv[l - 1].pitch;
+    }
+    if (l >= 2) {
+      d.uA = m + P.off_u[l - 2];
+      d.hA = P.lv[l - 2].h;
+      d.wA = P.lv[l - 2].w;
+      d.pA = P.lv[l - 2].pitch;
+    }
+    // transfer temporaries: the smoother's direction buffers are free then
+    d.t1 = m + P.off_work[2];
+    d.t2 = m + P.off_work[3];
+    d.pm_k = P.k;
+    d.tau = P.prm.tau;
+    d.smooth_h = P.prm.smooth_h;
+    d.g_in = j->g_in_dev;
+    d.u_in = j->u_init_dev;
+    d.u_out = j->u_out_dev;
+    d.H = P.H;
+    d.W = P.W;
+    d.L = P.L;
+    d.fine_pitch = P.lv[P.L - 1].pitch;
+    for (int k = 0; k < P.L; ++k) {
+      d.g_lv[k] = m + P.off_g[k];
+      d.u_lv[k] = m + P.off_u[k];
+      d.lh[k] = P.lv[k].h;
+      d.lw[k] = P.lv[k].w;
+      d.lp[k] = P.lv[k].pitch;
+    }
+  }
+
+  // Launch `stage` for jobs at the given level (-1: each job's current level),
+  // splitting by nothing: caller groups jobs of one precision / variant.
+  void launch_group(Stage st, const std::vector<Job*>& jobs, int level, bool f64, int rmax_class, int src, int dst) {
+    LaunchList ll;
+    ll.n = 0;
+    ll.total = 0;
+    for (Job* j : jobs) {
+      const int l = level >= 0 ? level : j->cur_level();
+      const int di = j->slot * kMaxLevels + l;
+      const JobDesc& hd = h_desc_[di];
+      ll.job[ll.n] = di;
+      ll.start[ll.n] = ll.total;
+      ll.total += blocks_for_stage(st, hd);
+      ll.n += 1;
+      f64 = j->plan.f64;
+    }
+    ll.start[ll.n] = ll.total;
+    if (ll.total <= 0) return;
+    Profiler& pr = profiler();
+    if (pr.on.load(std::memory_order_relaxed) && profiled_stage(st) && ll.total >= pr.min_blocks) {
+      double px = 0.0;
+      for (Job* j : jobs) {
+        const int l = level >= 0 ? level : j->cur_level();
+        px += st == kXfExtrap ? (double)j->plan.lv[l - 1].h * j->plan.lv[l - 1].w
+                              : (double)j->plan.lv[l].h * j->plan.lv[l].w;
+      }
+      std::lock_guard<std::mutex> g(pr.mu);
+      hipEvent_t a = pr.ev(), b = pr.ev();
+      chk(hipEventRecord(a, stream_));
+      chk(launch_stage(st, f64, rmax_class, ll, d_desc_, src, dst, stream_));
+      chk(hipEventRecord(b, stream_));
+      pr.pending.push_back({(int)st, a, b, px});
+      return;
+    }
+    chk(launch_stage(st, f64, rmax_class, ll, d_desc_, src, dst, stream_));
+  }
+
+  static int variant_key(const Job* j) {
+    const int l = j->cur_level();
+    return (j->plan.f64 ? 1000 : 0) + rmax_class_for(j->plan.lv[l].rad);
+  }
+
+  void issue_transfers(const std::vector<std::pair<Job*, int>>& xs) {
+    // group by (precision, cascade, pm_steps)
+    std::map<std::tuple<int, int, int>, std::vector<Job*>> groups;
+    for (auto& x : xs) groups[{x.first->plan.f64, x.first->plan.prm.cascade, x.first->plan.prm.pm_steps}].push_back(x.first);
+    for (auto& kv : groups) {
+      const bool f64 = std::get<0>(kv.first);
+      const int cascade = std::get<1>(kv.first), n = std::get<2>(kv.first);
+      auto& js = kv.second;
+      if (cascade == EECMG_CASCADE_EECMG) {
+        launch_group(kXfExtrap, js, -1, f64, 0, -1, kBufT2);
+        launch_group(kXfQuad, js, -1, f64, 0, kBufT2, kBufT1);
+      } else if (cascade == EECMG_CASCADE_IECMG_P) {
+        launch_group(kXfQuad, js, -1, f64, 0, kBufUB, kBufT1);
+      } else {
+        launch_group(kXfLinear, js, -1, f64, 0, kBufUB, kBufT1);
+      }
+      launch_group(kXfSmooth, js, -1, f64, 0, kBufT1, n == 0 ? kBufU : kBufT2);
+      for (int s = 0; s < n; ++s) {
+        const int src = (s % 2 == 0) ? kBufT2 : kBufT1;
+        const int dst = (s == n - 1) ? kBufU : ((s % 2 == 0) ? kBufT1 : kBufT2);
+        launch_group(kXfPm, js, -1, f64, 0, src, dst);
+      }
+    }
+  }
+
+  void issue_inits(const std::vector<Job*>& js) {
+    std::map<std::pair<int, int>, std::vector<Job*>> groups;  // (smoother, variant)
+    for (Job* j : js) groups[{j->plan.prm.smoother, variant_key(j)}].push_back(j);
+    for (auto& kv : groups) {
+      const bool f64 = kv.first.second >= 1000;
+      const int rc = kv.first.second % 1000;
+      if (kv.first.first == EECMG_SMOOTHER_CGLS) {
+        launch_group(kCgInit1, kv.second, -1, f64, rc, -1, -1);
+        launch_group(kCgInit2, kv.second, -1, f64, rc, -1, -1);
+        launch_group(kCgFinInit, kv.second, -1, f64, rc, -1, -1);
+      } else {
+        launch_group(kMrInit, kv.second, -1, f64, rc, -1, -1);
+        launch_group(kMrFinInit, kv.second, -1, f64, rc, -1, -1);
+      }
+    }
+  }
+
+  void issue_iterations(const std::vector<std::pair<Job*, int>>& its) {
+    int maxc = 0;
+    for (auto& x : its) maxc = std::max(maxc, x.second);
+    for (int it = 0; it < maxc; ++it) {
+      std::map<std::pair<int, int>, std::vector<Job*>> groups;
+      for (auto& x : its)
+        if (x.second > it) groups[{x.first->plan.prm.smoother, variant_key(x.first)}].push_back(x.first);
+      for (auto& kv : groups) {
+        const bool f64 = kv.first.second >= 1000;
+        const int rc = kv.first.second % 1000;
+        if (kv.first.first == EECMG_SMOOTHER_CGLS) {
+          launch_group(kCgA, kv.second, -1, f64, rc, -1, -1);
+          launch_group(kCgFinA, kv.second, -1, f64, rc, -1, -1);
+          launch_group(kCgB, kv.second, -1, f64, rc, -1, -1);
+          launch_group(kCgFinB, kv.second, -1, f64, rc, -1, -1);
+        } else {
+          launch_group(kMrPass, kv.second, -1, f64, rc, -1, -1);
+          launch_group(kMrFin, kv.second, -1, f64, rc, -1, -1);
+        }
+      }
+    }
+  }
+
+  void issue_readback() {
+    Readback* r = nullptr;
+    for (auto& x : rb_)
+      if (!x.pending) {
+        r = &x;
+        break;
+      }
+    if (!r) {
+      // all in flight: wait for the oldest
+      uint64_t m = oldest_pending_seq();
+      for (auto& x : rb_)
+        if (x.pending && x.seq == m) {
+          chk(hipEventSynchronize(x.ev));
+          consume_readbacks(false);
+          r = &x;
+          break;
+        }
+      if (!r || r->pending) return;
+    }
+    chk(hipMemcpyAsync(r->h, d_state_, sizeof(SolverState) * kMaxSlots, hipMemcpyDeviceToHost, stream_));
+    chk(hipEventRecord(r->ev, stream_));
+    r->pending = true;
+    r->seq = ++rb_seq_;
+  }
+
+  void consume_readbacks(bool block) {
+    // apply completed readbacks in issue order
+    for (;;) {
+      Readback* r = nullptr;
+      uint64_t m = oldest_pending_seq();
+      if (m == UINT64_MAX) return;
+      for (auto& x : rb_)
+        if (x.pending && x.seq == m) r = &x;
+      if (!r) return;
+      if (block)
+        chk(hipEventSynchronize(r->ev));
+      else if (hipEventQuery(r->ev) != hipSuccess)
+        return;
+      r->pending = false;
+      for (Job* j : slots_) {
+        if (!j || j->phase != Job::kIter) continue;
+        if (r->seq < j->level_rb_seq) continue;  // taken before this level began
+        const SolverState& s = r->h[j->slot];
+        if (s.level != j->cur_level()) continue;
+        j->confirmed = std::max(j->confirmed, std::min(s.k, j->issued));
+        if (s.done != 0) {
+          j->level_done_seen = true;
+          j->confirmed = j->issued;
+        }
+      }
+    }
+  }
+
+  void finish(Job* j) {
+    std::memcpy(j->rec, h_rec_ + (size_t)j->slot * kMaxLevels, sizeof(LevelRecord) * kMaxLevels);
+    int st = EECMG_OK;
+    for (int l = 0; l < j->plan.L; ++l)
+      if (j->rec[l].reason == kStopNonFinite) st = EECMG_ENUMERIC;
+    if (j->cancelled) st = EECMG_ECANCELED;
+    j->status = st;
+    j->phase = Job::kFinished;
+    j->t_done = now_s();
+  }
+
+  void chk(hipError_t e) {
+    if (e != hipSuccess && err_ == hipSuccess) err_ = e;
+  }
+
+  int device_;
+  hipError_t err_ = hipSuccess;
+  hipStream_t stream_ = nullptr;
+  Arena arena_;
+  JobDesc* d_desc_ = nullptr;
+  JobDesc* h_desc_ = nullptr;
+  SolverState* d_state_ = nullptr;
+  LevelRecord* d_rec_ = nullptr;
+  LevelRecord* h_rec_ = nullptr;
+  char* h_taps_ = nullptr;
+  Readback rb_[3];
+  uint64_t rb_seq_ = 0;
+  std::vector<Job*> slots_;
+  int n_active_ = 0;
+};
+
+static void fill_stats(const Job* j, eecmg_stats* s) {
+  if (!s) return;
+  std::memset(s, 0, sizeof(*s));
+  s->struct_size = sizeof(eecmg_stats);
+  s->n_levels = j->plan.L;
+  for (int l = 0; l < j->plan.L; ++l) {
+    s->level_h[l] = j->plan.lv[l].h;
+    s->level_w[l] = j->plan.lv[l].w;
+    s->psf_radius[l] = j->plan.lv[l].rad;
+    s->caps[l] = j->plan.lv[l].cap;
+    s->iters[l] = j->rec[l].iters;
+    s->stop_reason[l] = j->rec[l].reason;
+    s->final_rms[l] = j->rec[l].rms;
+  }
+}
+
+// Run a set of jobs to completion on an engine (admitting as room frees).
+static int run_jobs(Engine& E, std::vector<Job*>& jobs) {
+  size_t next = 0, done = 0;
+  std::vector<Job*> fin;
+  while (done < jobs.size()) {
+    while (next < jobs.size()) {
+      const int rc = E.admit(jobs[next]);
+      if (rc == EECMG_EAGAIN) break;
+      if (rc != EECMG_OK) return rc;
+      ++next;
+    }
+    if (E.active() == 0 && next < jobs.size())
+      return fail(EECMG_ENOMEM, "a job does not fit the device arena");
+    const bool launched = E.step(fin);
+    for (Job* j : fin) {
+      E.release(j);
+      ++done;
+    }
+    if (!launched && fin.empty()) E.wait_some();
+    if (E.error() != hipSuccess) {
+      const hipError_t e = E.error();
+      E.clear_error();
+      return fail(EECMG_EDEVICE, std::string("HIP error in the cascade: ") + hipGetErrorString(e));
+    }
+  }
+  return EECMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Process-wide engines for the plain / batched / operator calls
+// ---------------------------------------------------------------------------
+struct PlainEngine {
+  std::mutex mu;
+  std::unique_ptr<Engine> eng;
+};
+
+static PlainEngine* plain_engine(int device, int* rc) {
+  static std::mutex mu;
+  static std::map<int, PlainEngine*> engines;  // never destroyed: outlives static teardown order
+  std::lock_guard<std::mutex> g(mu);
+  auto it = engines.find(device);
+  if (it != engines.end()) return it->second;
+  PlainEngine* pe = new PlainEngine();
+  pe->eng.reset(new Engine(device));
+  *rc = pe->eng->init(nullptr);
+  if (*rc != EECMG_OK) {
+    delete pe;
+    return nullptr;
+  }
+  engines[device] = pe;
+  return pe;
+}
+
+static int current_device(int* dev) {
+  EECMG_HIP(hipGetDevice(dev));
+  return EECMG_OK;
+}
+
+static int check_dev_ptr(const void* p, const char* what) {
+  if (!p) return fail(EECMG_EINVAL, std::string(what) + " is NULL");
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(EECMG_EINVAL, std::string(what) + " is not device memory");
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+    return fail(EECMG_EINVAL, std::string(what) + " is not device memory");
+  return EECMG_OK;
+}
+
+static size_t arena_target(size_t need) {
+  // keep at least 256 MiB so small calls do not reallocate
+  return std::max(need, (size_t)256 << 20);
+}
+
+static int restore_jobs_on(PlainEngine* pe, std::vector<Job*>& jobs, hipStream_t stream) {
+  Engine& E = *pe->eng;
+  E.set_stream(stream);
+  size_t total = 0, biggest = 0;
+  for (Job* j : jobs) {
+    total += align_up(j->plan.bytes, 256);
+    biggest = std::max(biggest, j->plan.bytes);
+  }
+  size_t free_b = 0, tot_b = 0;
+  if (hipMemGetInfo(&free_b, &tot_b) != hipSuccess) free_b = (size_t)4 << 30;
+  const size_t cap = (size_t)(0.6 * (double)(free_b + E.arena().size()));
+  size_t want = std::min(total, std::max(cap, biggest));
+  int rc = E.arena().reserve(arena_target(want));
+  if (rc != EECMG_OK) return rc;
+  rc = run_jobs(E, jobs);
+  return rc;
+}
+
+}  // namespace eecmg
+
+using namespace eecmg;
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* eecmg_last_error(void) { return g_err.c_str(); }
+
+const char* eecmg_version(void) { return "eecmg-mi355x 0.1 (gfx950)"; }
+
+int eecmg_profile_enable(int enable, int min_blocks) {
+  Profiler& p = profiler();
+  std::lock_guard<std::mutex> g(p.mu);
+  p.min_blocks = min_blocks < 0 ? 0 : min_blocks;
+  p.on.store(enable != 0);
+  return EECMG_OK;
+}
+
+int eecmg_profile_reset(void) {
+  Profiler& p = profiler();
+  std::lock_guard<std::mutex> g(p.mu);
+  p.harvest();
+  for (int i = 0; i < kNumStages; ++i) {
+    p.launches[i] = 0;
+    p.ms[i] = 0.0;
+    p.pixels[i] = 0.0;
+  }
+  return EECMG_OK;
+}
+
+int eecmg_profile_read(int stage, int* launches, double* total_ms, double* total_pixels) {
+  if (stage < 0 || stage >= kNumStages) return fail(EECMG_EINVAL, "unknown stage id");
+  Profiler& p = profiler();
+  std::lock_guard<std::mutex> g(p.mu);
+  p.harvest();
+  if (launches) *launches = p.launches[stage];
+  if (total_ms) *total_ms = p.ms[stage];
+  if (total_pixels) *total_pixels = p.pixels[stage];
+  return EECMG_OK;
+}
+
+int eecmg_params_default(eecmg_params* p) {
+  if (!p) return fail(EECMG_EINVAL, "params is NULL");
+  default_params(p);
+  return EECMG_OK;
+}
+
+int eecmg_restore_dev(const void* g_delta_dev, int H, int W, const double* psf, int psf_radius, int n_levels,
+                      const int* iters_per_level, double k, const eecmg_params* params, void* u_out_dev,
+                      void* hip_stream) {
+  g_err.clear();
+  int rc = check_dev_ptr(g_delta_dev, "g_delta_dev");
+  if (rc) return rc;
+  rc = check_dev_ptr(u_out_dev, "u_out_dev");
+  if (rc) return rc;
+  Job job;
+  rc = build_plan(H, W, psf, psf_radius, n_levels, iters_per_level, k, params, false, job.plan);
+  if (rc) return rc;
+  int dev = 0;
+  rc = current_device(&dev);
+  if (rc) return rc;
+  PlainEngine* pe = plain_engine(dev, &rc);
+  if (!pe) return rc;
+  std::lock_guard<std::mutex> g(pe->mu);
+  job.g_in_dev = g_delta_dev;
+  job.u_out_dev = u_out_dev;
+  std::vector<Job*> jobs{&job};
+  rc = restore_jobs_on(pe, jobs, (hipStream_t)hip_stream);
+  if (rc) return rc;
+  if (params && params->stats) fill_stats(&job, (eecmg_stats*)params->stats);
+  if (job.status != EECMG_OK) return fail(job.status, "non-finite value in the smoother");
+  return EECMG_OK;
+}
+
+int eecmg_restore(const void* g_delta, int H, int W, const double* psf, int psf_radius, int n_levels,
+                  const int* iters_per_level, double k, const eecmg_params* params, void* u_out) {
+  g_err.clear();
+  if (!g_delta || !u_out) return fail(EECMG_EINVAL, "g_delta / u_out is NULL");
+  Job job;
+  int rc = build_plan(H, W, psf, psf_radius, n_levels, iters_per_level, k, params, true, job.plan);
+  if (rc) return rc;
+  int dev = 0;
+  rc = current_device(&dev);
+  if (rc) return rc;
+  PlainEngine* pe = plain_engine(dev, &rc);
+  if (!pe) return rc;
+  std::lock_guard<std::mutex> g(pe->mu);
+  Engine& E = *pe->eng;
+  E.set_stream(nullptr);
+  rc = E.arena().reserve(arena_target(job.plan.bytes));
+  if (rc) return rc;
+  // admit first so the job's own input buffer exists, then copy the input in
+  if (E.admit(&job) != EECMG_OK) return fail(EECMG_ENOMEM, "job does not fit the device arena");
+  const size_t bytes = (size_t)H * W * job.plan.esz;
+  hipError_t he = hipMemcpy((void*)job.g_in_dev, g_delta, bytes, hipMemcpyHostToDevice);
+  if (he != hipSuccess) {
+    E.release(&job);
+    return fail(EECMG_EDEVICE, std::string("hipMemcpy H2D: ") + hipGetErrorString(he));
+  }
+  std::vector<Job*> fin;
+  while (job.phase != Job::kFinished) {
+    const bool launched = E.step(fin);
+    if (!launched && fin.empty()) E.wait_some();
+  }
+  he = hipMemcpy(u_out, job.u_out_dev, bytes, hipMemcpyDeviceToHost);
+  E.release(&job);
+  if (he != hipSuccess) return fail(EECMG_EDEVICE, std::string("hipMemcpy D2H: ") + hipGetErrorString(he));
+  if (params && params->stats) fill_stats(&job, (eecmg_stats*)params->stats);
+  if (job.status != EECMG_OK) return fail(job.status, "non-finite value in the smoother");
+  return EECMG_OK;
+}
+
+int eecmg_restore_batch_dev(int n_images, const void* const* g_delta_dev, const int* H, const int* W,
+                            const double* const* psf, const int* psf_radius, const int* n_levels,
+                            const int* const* iters_per_level, const double* k, const eecmg_params* params,
+                            void* const* u_out_dev, void* hip_stream) {
+  g_err.clear();
+  if (n_images < 0) return fail(EECMG_EINVAL, "n_images < 0");
+  if (n_images == 0) return EECMG_OK;
+  if (!g_delta_dev || !H || !W || !psf || !psf_radius || !n_levels || !k || !u_out_dev)
+    return fail(EECMG_EINVAL, "NULL array argument");
+  std::vector<std::unique_ptr<Job>> owned;
+  std::vector<Job*> jobs;
+  int prec = -1;
+  for (int i = 0; i < n_images; ++i) {
+    std::unique_ptr<Job> j(new Job());
+    const eecmg_params* pi = params ? &params[i] : nullptr;
+    int rc = build_plan(H[i], W[i], psf[i], psf_radius[i], n_levels[i], iters_per_level ? iters_per_level[i] : nullptr,
+                        k[i], pi, false, j->plan);
+    if (rc) return fail(rc, "image " + std::to_string(i) + ": " + g_err);
+    if (prec < 0) prec = j->plan.f64;
+    if (prec != (int)j->plan.f64) return fail(EECMG_EINVAL, "all images of a batch must share one precision");
+    rc = check_dev_ptr(g_delta_dev[i], "g_delta_dev[i]");
+    if (rc) return rc;
+    rc = check_dev_ptr(u_out_dev[i], "u_out_dev[i]");
+    if (rc) return rc;
+    j->g_in_dev = g_delta_dev[i];
+    j->u_out_dev = u_out_dev[i];
+    jobs.push_back(j.get());
+    owned.push_back(std::move(j));
+  }
+  int dev = 0, rc = current_device(&dev);
+  if (rc) return rc;
+  PlainEngine* pe = plain_engine(dev, &rc);
+  if (!pe) return rc;
+  std::lock_guard<std::mutex> g(pe->mu);
+  rc = restore_jobs_on(pe, jobs, (hipStream_t)hip_stream);
+  if (rc) return rc;
+  int first = EECMG_OK;
+  for (int i = 0; i < n_images; ++i) {
+    if (params && params[i].stats) fill_stats(jobs[i], (eecmg_stats*)params[i].stats);
+    if (jobs[i]->status != EECMG_OK && first == EECMG_OK) first = jobs[i]->status;
+  }
+  if (first != EECMG_OK) return fail(first, "an image of the batch failed");
+  return EECMG_OK;
+}
+
+// ------------------------------------------------------------------ operators
+static int op_taps(const double* psf, int r, bool f64, bool flip, void** d_taps) {
+  const int n = 2 * r + 1;
+  std::vector<double> t((size_t)n * n);
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) t[a * n + b] = flip ? psf[(n - 1 - a) * n + (n - 1 - b)] : psf[a * n + b];
+  const size_t bytes = (size_t)n * n * (f64 ? 8 : 4);
+  EECMG_HIP(hipMalloc(d_taps, bytes));
+  if (f64) {
+    EECMG_HIP(hipMemcpy(*d_taps, t.data(), bytes, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> f(t.begin(), t.end());
+    EECMG_HIP(hipMemcpy(*d_taps, f.data(), bytes, hipMemcpyHostToDevice));
+  }
+  return EECMG_OK;
+}
+
+static int check_prec(int precision) {
+  if (precision < 0 || precision > 2) return fail(EECMG_EINVAL, "precision must be 0, 1 or 2");
+  return EECMG_OK;
+}
+
+int eecmg_op_conv_dev(const void* x_dev, void* y_dev, int H, int W, const double* psf, int psf_radius,
+                      int transpose, int precision, void* hip_stream) {
+  g_err.clear();
+  int rc = check_prec(precision);
+  if (rc) return rc;
+  if (H < 1 || W < 1 || psf_radius < 0 || psf_radius > kMaxRadius || !psf)
+    return fail(EECMG_EINVAL, "bad size, radius or psf");
+  if (x_dev == y_dev) return fail(EECMG_EINVAL, "x and y must not alias");
+  if ((rc = check_dev_ptr(x_dev, "x_dev")) || (rc = check_dev_ptr(y_dev, "y_dev"))) return rc;
+  const bool f64 = precision == EECMG_FP64;
+  void* taps = nullptr;
+  rc = op_taps(psf, psf_radius, f64, transpose != 0, &taps);
+  if (rc) return rc;
+  hipError_t e = op_conv(x_dev, y_dev, H, W, taps, psf_radius, f64, (hipStream_t)hip_stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)hip_stream);
+  (void)hipFree(taps);
+  if (e != hipSuccess) return fail(EECMG_EDEVICE, hipGetErrorString(e));
+  return EECMG_OK;
+}
+
+int eecmg_op_smoother_dev(const void* g_dev, void* u_dev, int H, int W, const double* psf, int psf_radius, int cap,
+                          const eecmg_params* params, eecmg_stats* stats_out, void* hip_stream) {
+  g_err.clear();
+  int rc;
+  if ((rc = check_dev_ptr(g_dev, "g_dev")) || (rc = check_dev_ptr(u_dev, "u_dev"))) return rc;
+  if (cap < 0) return fail(EECMG_EINVAL, "cap must be >= 0");
+  Job job;
+  rc = build_plan(H, W, psf, psf_radius, 1, &cap, 10.0, params, false, job.plan);
+  if (rc) return rc;
+  int dev = 0;
+  rc = current_device(&dev);
+  if (rc) return rc;
+  PlainEngine* pe = plain_engine(dev, &rc);
+  if (!pe) return rc;
+  std::lock_guard<std::mutex> g(pe->mu);
+  job.g_in_dev = g_dev;
+  job.u_init_dev = u_dev;
+  job.u_out_dev = u_dev;
+  std::vector<Job*> jobs{&job};
+  rc = restore_jobs_on(pe, jobs, (hipStream_t)hip_stream);
+  if (rc) return rc;
+  EECMG_HIP(hipStreamSynchronize((hipStream_t)hip_stream));
+  if (stats_out) fill_stats(&job, stats_out);
+  if (job.status != EECMG_OK) return fail(job.status, "non-finite value in the smoother");
+  return EECMG_OK;
+}
+
+int eecmg_op_restrict_dev(const void* g_fine_dev, int Hf, int Wf, void* g_coarse_dev, int precision,
+                          void* hip_stream) {
+  g_err.clear();
+  int rc = check_prec(precision);
+  if (rc) return rc;
+  if (Hf < 1 || Wf < 1) return fail(EECMG_EINVAL, "bad size");
+  if ((rc = check_dev_ptr(g_fine_dev, "g_fine_dev")) || (rc = check_dev_ptr(g_coarse_dev, "g_coarse_dev"))) return rc;
+  hipError_t e = op_restrict(g_fine_dev, Hf, Wf, g_coarse_dev, precision == EECMG_FP64, (hipStream_t)hip_stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)hip_stream);
+  if (e != hipSuccess) return fail(EECMG_EDEVICE, hipGetErrorString(e));
+  return EECMG_OK;
+}
+
+int eecmg_op_coarse_psf(const double* psf, int psf_radius, int mode, double* psf_coarse) {
+  g_err.clear();
+  if (!psf || !psf_coarse || psf_radius < 0 || psf_radius > kMaxRadius) return fail(EECMG_EINVAL, "bad psf");
+  const int n = 2 * psf_radius + 1;
+  std::vector<double> in(psf, psf + (size_t)n * n), out;
+  int rc = decimate_psf(in, psf_radius, mode, out);
+  if (rc) return rc;
+  std::memcpy(psf_coarse, out.data(), out.size() * sizeof(double));
+  return EECMG_OK;
+}
+
+#define EECMG_OP_TAIL(expr)                                                     \
+  do {                                                                          \
+    hipError_t e_ = (expr);                                                     \
+    if (e_ == hipSuccess) e_ = hipStreamSynchronize((hipStream_t)hip_stream);   \
+    if (e_ != hipSuccess) return fail(EECMG_EDEVICE, hipGetErrorString(e_));    \
+    return EECMG_OK;                                                            \
+  } while (0)
+
+int eecmg_op_extrapolate_dev(const void* uA_dev, const void* uB_dev, int HB, int WB, void* ut_dev, int precision,
+                             void* hip_stream) {
+  g_err.clear();
+  int rc = check_prec(precision);
+  if (rc) return rc;
+  if (HB < 5 || WB < 5) return fail(EECMG_EINVAL, "the coarser grid needs at least 3 nodes per axis");
+  if ((rc = check_dev_ptr(uA_dev, "uA_dev")) || (rc = check_dev_ptr(uB_dev, "uB_dev")) ||
+      (rc = check_dev_ptr(ut_dev, "ut_dev")))
+    return rc;
+  EECMG_OP_TAIL(op_extrapolate(uA_dev, uB_dev, HB, WB, ut_dev, precision == EECMG_FP64, (hipStream_t)hip_stream));
+}
+
+int eecmg_op_prolong_quad_dev(const void* ut_dev, int HC, int WC, void* uC_dev, int precision, void* hip_stream) {
+  g_err.clear();
+  int rc = check_prec(precision);
+  if (rc) return rc;
+  if (HC < 5 || WC < 5) return fail(EECMG_EINVAL, "the coarser grid needs at least 3 nodes per axis");
+  if ((rc = check_dev_ptr(ut_dev, "ut_dev")) || (rc = check_dev_ptr(uC_dev, "uC_dev"))) return rc;
+  EECMG_OP_TAIL(op_prolong_quad(ut_dev, HC, WC, uC_dev, precision == EECMG_FP64, (hipStream_t)hip_stream));
+}
+
+int eecmg_op_prolong_linear_dev(const void* uB_dev, int HC, int WC, void* uC_dev, int precision, void* hip_stream) {
+  g_err.clear();
+  int rc = check_prec(precision);
+  if (rc) return rc;
+  if (HC < 3 || WC < 3) return fail(EECMG_EINVAL, "the coarser grid needs at least 2 nodes per axis");
+  if ((rc = check_dev_ptr(uB_dev, "uB_dev")) || (rc = check_dev_ptr(uC_dev, "uC_dev"))) return rc;
+  EECMG_OP_TAIL(op_prolong_linear(uB_dev, HC, WC, uC_dev, precision == EECMG_FP64, (hipStream_t)hip_stream));
+}
+
+int eecmg_op_local_smooth_dev(const void* u_dev, void* out_dev, int H, int W, double smooth_h, int precision,
+                              void* hip_stream) {
+  g_err.clear();
+  int rc = check_prec(precision);
+  if (rc) return rc;
+  if (H < 1 || W < 1 || !(smooth_h > 0.0)) return fail(EECMG_EINVAL, "bad size or smooth_h");
+  if ((rc = check_dev_ptr(u_dev, "u_dev")) || (rc = check_dev_ptr(out_dev, "out_dev"))) return rc;
+  if (u_dev == out_dev) return fail(EECMG_EINVAL, "S is out of place: u and out must not alias");
+  EECMG_OP_TAIL(op_local_smooth(u_dev, out_dev, H, W, smooth_h, precision == EECMG_FP64, (hipStream_t)hip_stream));
+}
+
+int eecmg_op_pm_step_dev(const void* u_dev, void* out_dev, int H, int W, double k, double tau, int precision,
+                         void* hip_stream) {
+  g_err.clear();
+  int rc = check_prec(precision);
+  if (rc) return rc;
+  if (H < 1 || W < 1 || !(k > 0.0) || !(tau > 0.0 && tau <= 0.25)) return fail(EECMG_EINVAL, "bad size, k or tau");
+  if ((rc = check_dev_ptr(u_dev, "u_dev")) || (rc = check_dev_ptr(out_dev, "out_dev"))) return rc;
+  if (u_dev == out_dev) return fail(EECMG_EINVAL, "D is out of place: u and out must not alias");
+  EECMG_OP_TAIL(op_pm_step(u_dev, out_dev, H, W, k, tau, precision == EECMG_FP64, (hipStream_t)hip_stream));
+}
+
+
+// ------------------------------------------------------------ request loop
+int eecmg_ctx_config_default(eecmg_ctx_config* cfg) {
+  if (!cfg) return fail(EECMG_EINVAL, "cfg is NULL");
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->struct_size = sizeof(eecmg_ctx_config);
+  cfg->device = 0;
+  cfg->hbm_budget_bytes = (size_t)8 << 30;
+  cfg->max_slots = 64;
+  cfg->max_queue = 4096;
+  return EECMG_OK;
+}
+
+}  // extern "C"
+
+namespace eecmg {
+
+// Pinned host buffers recycled by size class (powers of two), so the
+// request loop never allocates or frees pinned memory on its hot path.
+class PinnedPool {
+ public:
+  ~PinnedPool() {}
+  void* get(size_t bytes, size_t* cls_out) {
+    size_t cls = (size_t)1 << 16;
+    while (cls < bytes) cls <<= 1;
+    *cls_out = cls;
+    std::lock_guard<std::mutex> g(mu_);
+    auto& v = free_[cls];
+    if (!v.empty()) {
+      void* p = v.back();
+      v.pop_back();
+      return p;
+    }
+    void* p = nullptr;
+    if (hipHostMalloc(&p, cls, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return p;
+  }
+  void put(void* p, size_t cls) {
+    if (!p) return;
+    std::lock_guard<std::mutex> g(mu_);
+    free_[cls].push_back(p);
+  }
+  void release_all() {
+    std::lock_guard<std::mutex> g(mu_);
+    for (auto& kv : free_)
+      for (void* p : kv.second) (void)hipHostFree(p);
+    free_.clear();
+  }
+
+ private:
+  std::mutex mu_;
+  std::map<size_t, std::vector<void*>> free_;
+};
+
+struct Request {
+  std::unique_ptr<Job> job;
+  size_t in_cls = 0, out_cls = 0;
+  bool admitted = false;
+  bool finished = false;
+  int status = EECMG_PENDING;
+};
+
+}  // namespace eecmg
+
+struct eecmg_ctx {
+  int device = 0;
+  eecmg_ctx_config cfg{};
+  std::unique_ptr<eecmg::Engine> eng;
+  hipStream_t stream = nullptr;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<uint64_t> queue;
+  std::unordered_map<uint64_t, std::unique_ptr<eecmg::Request>> reqs;
+  uint64_t next_id = 1;
+  bool stopping = false;
+  std::thread th;
+  eecmg::PinnedPool pool;
+  int active = 0;
+};
+
+namespace eecmg {
+
+static void progress_loop(eecmg_ctx* C) {
+  (void)hipSetDevice(C->device);
+  Engine& E = *C->eng;
+  std::vector<Job*> fin;
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(C->mu);
+      // admission: FIFO with a look-ahead window, by slot and device budget
+      int scanned = 0;
+      for (auto it = C->queue.begin(); it != C->queue.end() && scanned < 32;) {
+        Request* r = C->reqs[*it].get();
+        if (r->job->cancelled) {
+          r->finished = true;
+          r->status = EECMG_ECANCELED;
+          it = C->queue.erase(it);
+          C->cv_done.notify_all();
+          continue;
+        }
+        if (C->active >= C->cfg.max_slots) break;
+        if (E.admit(r->job.get()) != EECMG_OK) {
+          ++it;
+          ++scanned;
+          continue;
+        }
+        Job* j = r->job.get();
+        if (hipMemcpyAsync((void*)j->g_in_dev, j->host_in, (size_t)j->plan.H * j->plan.W * j->plan.esz,
+                           hipMemcpyHostToDevice, C->stream) != hipSuccess)
+          j->cancelled = true;
+        r->admitted = true;
+        ++C->active;
+        it = C->queue.erase(it);
+      }
+      if (C->active == 0) {
+        if (C->stopping && C->queue.empty()) return;
+        C->cv_work.wait(lk, [&] { return C->stopping || !C->queue.empty(); });
+        continue;
+      }
+    }
+    const bool launched = E.step(fin);
+    if (!fin.empty()) {
+      std::lock_guard<std::mutex> lk(C->mu);
+      for (Job* j : fin) {
+        E.release(j);
+        --C->active;
+        auto it = C->reqs.find(j->id);
+        if (it != C->reqs.end()) {
+          it->second->finished = true;
+          it->second->status = j->status;
+        }
+      }
+      C->cv_done.notify_all();
+    }
+    if (!launched && fin.empty()) E.wait_some();
+  }
+}
+
+}  // namespace eecmg
+
+extern "C" {
+
+int eecmg_create(const eecmg_ctx_config* cfg, eecmg_ctx** out) {
+  g_err.clear();
+  if (!out) return fail(EECMG_EINVAL, "out is NULL");
+  eecmg_ctx_config c;
+  if (cfg) {
+    if (cfg->struct_size != sizeof(eecmg_ctx_config)) return fail(EECMG_EINVAL, "cfg->struct_size mismatch");
+    c = *cfg;
+  } else {
+    eecmg_ctx_config_default(&c);
+  }
+  if (c.max_slots < 1 || c.max_slots > EECMG_MAX_SLOTS) return fail(EECMG_EINVAL, "max_slots out of range");
+  if (c.max_queue < 1) return fail(EECMG_EINVAL, "max_queue must be >= 1");
+  if (c.hbm_budget_bytes < ((size_t)1 << 20)) return fail(EECMG_EINVAL, "hbm_budget_bytes too small");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || c.device < 0 || c.device >= ndev)
+    return fail(EECMG_EINVAL, "invalid device");
+  std::unique_ptr<eecmg_ctx> C(new eecmg_ctx());
+  C->device = c.device;
+  C->cfg = c;
+  EECMG_HIP(hipSetDevice(c.device));
+  EECMG_HIP(hipStreamCreateWithFlags(&C->stream, hipStreamNonBlocking));
+  C->eng.reset(new Engine(c.device));
+  int rc = C->eng->init(C->stream);
+  if (rc) return rc;
+  rc = C->eng->arena().reserve(c.hbm_budget_bytes);
+  if (rc) return rc;
+  C->th = std::thread(progress_loop, C.get());
+  *out = C.release();
+  return EECMG_OK;
+}
+
+int eecmg_submit(eecmg_ctx* C, const void* g_delta, int H, int W, const double* psf, int psf_radius, int n_levels,
+                 const int* iters_per_level, double k, const eecmg_params* params, uint64_t* request_id) {
+  g_err.clear();
+  if (!C || !g_delta || !request_id) return fail(EECMG_EINVAL, "NULL argument");
+  std::unique_ptr<Request> r(new Request());
+  r->job.reset(new Job());
+  Job* j = r->job.get();
+  int rc = build_plan(H, W, psf, psf_radius, n_levels, iters_per_level, k, params, true, j->plan);
+  if (rc) return rc;
+  if (j->plan.bytes > C->eng->arena().size())
+    return fail(EECMG_ENOMEM, "request needs " + std::to_string(j->plan.bytes) + " bytes, more than the budget");
+  const size_t bytes = (size_t)H * W * j->plan.esz;
+  j->host_in = C->pool.get(bytes, &r->in_cls);
+  j->host_out = C->pool.get(bytes, &r->out_cls);
+  if (!j->host_in || !j->host_out) {
+    C->pool.put(j->host_in, r->in_cls);
+    C->pool.put(j->host_out, r->out_cls);
+    return fail(EECMG_ENOMEM, "pinned host staging allocation failed");
+  }
+  std::memcpy(j->host_in, g_delta, bytes);
+  j->t_submit = now_s();
+  std::lock_guard<std::mutex> lk(C->mu);
+  if ((int)C->queue.size() >= C->cfg.max_queue) {
+    C->pool.put(j->host_in, r->in_cls);
+    C->pool.put(j->host_out, r->out_cls);
+    return fail(EECMG_EAGAIN, "request queue full");
+  }
+  const uint64_t id = C->next_id++;
+  j->id = id;
+  C->reqs[id] = std::move(r);
+  C->queue.push_back(id);
+  *request_id = id;
+  C->cv_work.notify_one();
+  return EECMG_OK;
+}
+
+static int collect(eecmg_ctx* C, uint64_t id, void* u_out, eecmg_stats* stats_out, bool block) {
+  std::unique_lock<std::mutex> lk(C->mu);
+  auto it = C->reqs.find(id);
+  if (it == C->reqs.end()) return fail(EECMG_ENOTFOUND, "unknown request id");
+  if (block) C->cv_done.wait(lk, [&] { return it->second->finished; });
+  Request* r = it->second.get();
+  if (!r->finished) return EECMG_PENDING;
+  Job* j = r->job.get();
+  const int st = r->status;
+  if (st == EECMG_OK && u_out) std::memcpy(u_out, j->host_out, (size_t)j->plan.H * j->plan.W * j->plan.esz);
+  if (stats_out) fill_stats(j, stats_out);
+  C->pool.put(j->host_in, r->in_cls);
+  C->pool.put(j->host_out, r->out_cls);
+  C->reqs.erase(it);
+  if (st != EECMG_OK) return fail(st, st == EECMG_ECANCELED ? "request cancelled" : "request failed");
+  return EECMG_OK;
+}
+
+int eecmg_poll(eecmg_ctx* C, uint64_t request_id, void* u_out, eecmg_stats* stats_out) {
+  g_err.clear();
+  if (!C) return fail(EECMG_EINVAL, "ctx is NULL");
+  return collect(C, request_id, u_out, stats_out, false);
+}
+
+int eecmg_wait(eecmg_ctx* C, uint64_t request_id, void* u_out, eecmg_stats* stats_out) {
+  g_err.clear();
+  if (!C) return fail(EECMG_EINVAL, "ctx is NULL");
+  return collect(C, request_id, u_out, stats_out, true);
+}
+
+int eecmg_cancel(eecmg_ctx* C, uint64_t request_id) {
+  g_err.clear();
+  if (!C) return fail(EECMG_EINVAL, "ctx is NULL");
+  std::lock_guard<std::mutex> lk(C->mu);
+  auto it = C->reqs.find(request_id);
+  if (it == C->reqs.end()) return fail(EECMG_ENOTFOUND, "unknown request id");
+  it->second->job->cancelled = true;
+  C->cv_work.notify_one();
+  return EECMG_OK;
+}
+
+int eecmg_ctx_info(eecmg_ctx* C, int* queued, int* active, size_t* bytes_in_use) {
+  g_err.clear();
+  if (!C) return fail(EECMG_EINVAL, "ctx is NULL");
+  std::lock_guard<std::mutex> lk(C->mu);
+  if (queued) *queued = (int)C->queue.size();
+  if (active) *active = C->active;
+  if (bytes_in_use) *bytes_in_use = C->eng->arena().used();
+  return EECMG_OK;
+}
+
+int eecmg_destroy(eecmg_ctx* C) {
+  g_err.clear();
+  if (!C) return fail(EECMG_EINVAL, "ctx is NULL");
+  {
+    std::lock_guard<std::mutex> lk(C->mu);
+    C->stopping = true;
+    for (auto& kv : C->reqs) kv.second->job->cancelled = true;
+    C->cv_work.notify_all();
+  }
+  if (C->th.joinable()) C->th.join();
+  (void)hipSetDevice(C->device);
+  (void)hipStreamSynchronize(C->stream);
+  for (auto& kv : C->reqs) {
+    C->pool.put(kv.second->job->host_in, kv.second->in_cls);
+    C->pool.put(kv.second->job->host_out, kv.second->out_cls);
+  }
+  C->reqs.clear();
+  C->eng->arena().release();
+  C->eng->shutdown();
+  C->pool.release_all();
+  (void)hipStreamDestroy(C->stream);
+  delete C;
+  return EECMG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,232 @@
+"""GPU parity of the smoothers and the complete cascades against the oracle,
+through the C ABI.  Bars: FP64 mode relative L2 <= 1e-12, FP32 mode <= 1e-4,
+PSNR within 0.01 dB, identical per-level iteration counts (so no stop
+decision differs), and bitwise equality of one image alone, in a batch and
+in the served mix."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2311_03010_amd import eecmg, synth
+
+pytestmark = pytest.mark.gpu
+
+REL = {"f64": 1e-12, "f32": 1e-4}
+GUARD = {"f64": 1e-14, "f32": 1e-6}
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _dt(prec):
+    return np.float64 if prec == "f64" else np.float32
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def _run_both(torch, p, prec, caps=None, stop_rule=True, **kw):
+    g32 = p.g_delta.astype(_dt(prec))
+    g = torch.from_numpy(g32).to("cuda:0")
+    u, st = eecmg.restore_dev(g, p.psf, p.n_levels, caps=caps, precision=prec, delta=p.delta, stop_rule=stop_rule,
+                              **kw)
+    torch.cuda.synchronize()
+    okw = dict(kw)
+    okw["smoother"] = {"cgls": 0, "mr": 1}[okw.pop("smoother", "cgls")]
+    okw["cascade"] = {"eecmg": 0, "iecmg_l": 1, "iecmg_p": 2}[okw.pop("cascade", "eecmg")]
+    u_ref, st_ref = oracle.restore(g32.astype(np.float64), p.psf, p.n_levels, caps=caps, delta=p.delta,
+                                   stop_rule=stop_rule, guard_eps=GUARD[prec], **okw)
+    return u.cpu().numpy(), st, u_ref, st_ref
+
+
+def _check(p, prec, u, st, u_ref, st_ref):
+    print(f"  iters gpu={st['iters']} oracle={st_ref['iters']} reasons={st['reason']}", flush=True)
+    assert st["iters"] == st_ref["iters"]
+    assert st["reason"] == st_ref["reason"]
+    rel = _rel(u, u_ref)
+    dpsnr = abs(oracle.psnr(p.u_true, u.astype(np.float64)) - oracle.psnr(p.u_true, u_ref))
+    print(f"  rel_l2={rel:.3e} dPSNR={dpsnr:.2e}", flush=True)
+    assert rel <= REL[prec]
+    assert dpsnr <= 0.01
+    np.testing.assert_allclose(st["final_rms"], st_ref["final_rms"], rtol=1e-10 if prec == "f64" else 1e-4)
+
+
+# ------------------------------------------------------------------ smoothers
+@pytest.mark.parametrize("smoother", ["cgls", "mr"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("H,W,psfname", [(100, 77, "disk3"), (130, 257, "gauss2"), (16, 16, "id")])
+def test_smoother_parity(torch_cuda, smoother, prec, H, W, psfname):
+    rng = np.random.Generator(np.random.PCG64(H * W))
+    psf = {"disk3": synth.disk_psf(3), "gauss2": synth.gaussian_psf(2.0, 4), "id": np.ones((1, 1))}[psfname]
+    u_true = synth.scene(H, W, 12, rng)
+    g = (synth.blur(u_true, psf) + rng.standard_normal((H, W))).astype(_dt(prec)).astype(np.float64)
+    u0 = synth.blur(g, synth.gaussian_psf(1.0, 2)).astype(_dt(prec)).astype(np.float64)
+    cap = 12
+    t = torch_cuda
+    gd = t.from_numpy(g.astype(_dt(prec))).to("cuda:0")
+    ud = t.from_numpy(u0.astype(_dt(prec))).to("cuda:0")
+    u, st = eecmg.smoother_dev(gd, ud, psf, cap, precision=prec, smoother=smoother, stop_rule=False)
+    fn = oracle.cgls if smoother == "cgls" else oracle.mr
+    u_ref, it, hist, why = fn(g, psf, u0=u0, cap=cap, eps=GUARD[prec])
+    print(f"  iters gpu={st['iters']} oracle={it}", flush=True)
+    assert st["iters"] == it and st["reason"] == why
+    assert _rel(u.cpu().numpy(), u_ref) <= (1e-12 if prec == "f64" else 2e-5)
+    assert abs(st["final_rms"] - hist[-1]) <= (1e-10 if prec == "f64" else 1e-4) * hist[-1] + 1e-12
+
+
+def test_smoother_stop_rule_and_cap_zero(torch_cuda):
+    t = torch_cuda
+    rng = np.random.Generator(np.random.PCG64(3))
+    g = rng.uniform(0, 255, size=(40, 40))
+    gd = t.from_numpy(g).to("cuda:0")
+    ud = t.zeros_like(gd)
+    _, st = eecmg.smoother_dev(gd, ud, synth.disk_psf(2), 0, precision="f64")
+    assert st["iters"] == 0 and st["reason"] == 2
+    ud = t.zeros_like(gd)
+    _, st = eecmg.smoother_dev(gd, ud, synth.disk_psf(2), 10, precision="f64", delta=1e6)
+    assert st["iters"] == 0 and st["reason"] == 1
+    np.testing.assert_array_equal(ud.cpu().numpy(), 0.0)
+
+
+# ------------------------------------------------------------------ cascades
+def test_workload1_f64(torch_cuda):
+    p = synth.workload(1)
+    _check(p, "f64", *_run_both(torch_cuda, p, "f64"))
+
+
+@pytest.mark.parametrize("cascade", ["eecmg", "iecmg_l", "iecmg_p"])
+@pytest.mark.parametrize("smoother", ["cgls", "mr"])
+def test_variants_f64(torch_cuda, cascade, smoother):
+    p = synth.workload(1)
+    _check(p, "f64", *_run_both(torch_cuda, p, "f64", cascade=cascade, smoother=smoother))
+
+
+def test_stop_off_fixed_caps_f64(torch_cuda):
+    p = synth.workload(1)
+    _check(p, "f64", *_run_both(torch_cuda, p, "f64", caps=[3, 5, 4], stop_rule=False))
+
+
+@pytest.mark.parametrize("H,W", [(100, 37), (97, 131), (66, 64)])
+def test_ragged_sizes_f64(torch_cuda, H, W):
+    p = synth.workload(1, H=H, W=W)
+    _check(p, "f64", *_run_both(torch_cuda, p, "f64"))
+
+
+def test_workload2_scaled_f32(torch_cuda):
+    # the 1024^2 Gaussian sigma=3 recipe at 256^2 with 5 levels
+    p = synth.workload(2, H=256, n_levels=5, n_shapes=60)
+    _check(p, "f32", *_run_both(torch_cuda, p, "f32"))
+
+
+def test_workload3_scaled_f32(torch_cuda):
+    # the 4096^2 disk r=6 + texture recipe at 512^2 with 6 levels
+    p = synth.workload(3, H=512, n_levels=6, n_shapes=120, n_textures=12)
+    _check(p, "f32", *_run_both(torch_cuda, p, "f32"))
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_pm_steps_and_smooth_scale(torch_cuda, prec):
+    p = synth.workload(1, H=96, W=80)
+    _check(p, prec, *_run_both(torch_cuda, p, prec, pm_steps=3, smooth_h=2.0, tau=0.25, k=5.0))
+    _check(p, prec, *_run_both(torch_cuda, p, prec, pm_steps=0))
+
+
+def test_coarse_psf_modes(torch_cuda):
+    p = synth.workload(1)
+    for mode in (1, 2):
+        _check(p, "f64", *_run_both(torch_cuda, p, "f64", coarse_psf_mode=mode))
+
+
+def test_host_restore_equals_dev(torch_cuda):
+    p = synth.workload(1, H=80, W=72)
+    u_host, st_h = eecmg.restore(p.g_delta, p.psf, 3, precision="f64", delta=p.delta)
+    g = torch_cuda.from_numpy(p.g_delta).to("cuda:0")
+    u_dev, st_d = eecmg.restore_dev(g, p.psf, 3, precision="f64", delta=p.delta)
+    torch_cuda.cuda.synchronize()
+    np.testing.assert_array_equal(u_host, u_dev.cpu().numpy())
+    assert st_h == st_d
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_batch_equals_alone_bitwise(torch_cuda, prec):
+    t = torch_cuda
+    probs = [synth.workload(1, H=64, W=64), synth.workload(1, H=97, W=50),
+             synth.workload(3, H=130, W=200, n_levels=4, n_shapes=20, n_textures=2)]
+    gs = [t.from_numpy(q.g_delta.astype(_dt(prec))).to("cuda:0") for q in probs]
+    alone = []
+    for q, g in zip(probs, gs):
+        u, st = eecmg.restore_dev(g, q.psf, q.n_levels, precision=prec, delta=q.delta)
+        alone.append((u.clone(), st))
+    outs, sts = eecmg.restore_batch_dev(gs, [q.psf for q in probs], [q.n_levels for q in probs], precision=prec,
+                                        params=[{"delta": q.delta} for q in probs])
+    t.cuda.synchronize()
+    for (ua, sa), ub, sb in zip(alone, outs, sts):
+        np.testing.assert_array_equal(ua.cpu().numpy(), ub.cpu().numpy())
+        assert sa == sb
+
+
+def test_served_mix_equals_alone_bitwise(torch_cuda):
+    t = torch_cuda
+    probs = [synth.workload(1, H=64, W=64), synth.workload(1, H=97, W=50),
+             synth.workload(3, H=130, W=200, n_levels=4, n_shapes=20, n_textures=2),
+             synth.workload(2, H=150, W=120, n_levels=4, n_shapes=20)]
+    alone = []
+    for q in probs:
+        g = t.from_numpy(q.g_delta.astype(np.float32)).to("cuda:0")
+        u, st = eecmg.restore_dev(g, q.psf, q.n_levels, precision="f32", delta=q.delta)
+        alone.append((u.cpu().numpy(), st))
+    with eecmg.Context(hbm_budget_bytes=256 << 20, max_slots=8) as ctx:
+        reqs = [ctx.submit(q.g_delta, q.psf, q.n_levels, precision="f32", delta=q.delta) for q in probs]
+        got = [ctx.wait(r) for r in reqs]
+        info = ctx.info()
+    assert info["active"] == 0 and info["queued"] == 0
+    for (ua, sa), (ub, sb) in zip(alone, got):
+        np.testing.assert_array_equal(ua, ub)
+        assert sa == sb
+
+
+def test_served_budget_admission_and_errors(torch_cuda):
+    p = synth.workload(1, H=64, W=64)
+    with eecmg.Context(hbm_budget_bytes=2 << 20, max_slots=2, max_queue=3) as ctx:
+        big = np.zeros((1024, 1024), np.float32)
+        with pytest.raises(eecmg.EecmgError) as e:
+            ctx.submit(big, p.psf, 3, precision="f32")
+        assert e.value.status == eecmg.ENOMEM
+        reqs = [ctx.submit(p.g_delta, p.psf, 3, precision="f32", delta=p.delta) for _ in range(3)]
+        outs = [ctx.wait(r)[0] for r in reqs]
+        for o in outs[1:]:
+            np.testing.assert_array_equal(o, outs[0])
+        with pytest.raises(eecmg.EecmgError) as e:
+            ctx.poll(reqs[0])
+        assert e.value.status == eecmg.ENOTFOUND
+
+
+def test_invalid_arguments(torch_cuda):
+    t = torch_cuda
+    g = t.zeros((64, 64), dtype=t.float32, device="cuda:0")
+    psf = np.ones((1, 1))
+    with pytest.raises(eecmg.EecmgError) as e:
+        eecmg.restore_dev(g, psf, 6)  # coarsest 2x2
+    assert e.value.status == eecmg.EINVAL
+    with pytest.raises(eecmg.EecmgError):
+        eecmg.restore_dev(g, psf, 3, tau=0.3)
+    with pytest.raises(eecmg.EecmgError):
+        eecmg.restore_dev(g, psf, 3, c=0.9)
+    with pytest.raises(eecmg.EecmgError):
+        eecmg.restore_dev(g, np.ones((27, 27)), 3)
+
+
+def test_nonfinite_input_reports_enumeric(torch_cuda):
+    t = torch_cuda
+    p = synth.workload(1)
+    g = p.g_delta.copy()
+    g[10, 10] = np.nan
+    with pytest.raises(eecmg.EecmgError) as e:
+        eecmg.restore_dev(t.from_numpy(g).to("cuda:0"), p.psf, 3, precision="f64", delta=p.delta)
+    assert e.value.status == eecmg.ENUMERIC

@@ -1,0 +1,109 @@
+"""GPU parity of every operator entry point against the oracle, through the
+C ABI.  FP64 results must match to ~1e-13 relative, FP32 to ~1e-6 (one FP32
+rounding of inputs, taps and outputs); integer/copy work is bit-exact."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2311_03010_amd import eecmg, synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-13, "f32": 2e-6}
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _dt(prec):
+    return np.float64 if prec == "f64" else np.float32
+
+
+def _dev(torch, a, prec):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=_dt(prec))).to("cuda:0")
+
+
+def _close(got, ref, prec, what=""):
+    got = np.asarray(got, dtype=np.float64)
+    scale = max(np.abs(ref).max(), 1e-30)
+    err = np.abs(got - ref).max() / scale
+    assert err <= TOL[prec], f"{what}: max rel err {err:.3e}"
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("H,W,r", [(37, 70, 0), (64, 64, 1), (97, 130, 3), (33, 200, 6), (130, 65, 7), (70, 70, 12),
+                                   (5, 3, 2), (1, 1, 4)])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_conv_parity(torch_cuda, prec, H, W, r, transpose):
+    rng = np.random.Generator(np.random.PCG64(H * 1000 + W * 10 + r))
+    psf = rng.uniform(-0.2, 1.0, size=(2 * r + 1, 2 * r + 1))
+    x = rng.uniform(0, 255, size=(H, W)).astype(_dt(prec)).astype(np.float64)
+    psf_used = psf.astype(_dt(prec)).astype(np.float64)
+    y = eecmg.conv_dev(_dev(torch_cuda, x, prec), psf, transpose=transpose, precision=prec)
+    ref = oracle.conv(x, psf_used, transpose=transpose)
+    # elementwise bound of a recursive/FMA sum of n terms: n u sum |w x|
+    unit = 2.0 ** -53 if prec == "f64" else 2.0 ** -24
+    n = (2 * r + 1) ** 2
+    bound = (n + 1) * unit * oracle.conv(np.abs(x), np.abs(psf_used), transpose=transpose) + 1e-300
+    err = np.abs(y.cpu().numpy().astype(np.float64) - ref)
+    assert np.all(err <= bound), f"conv {H}x{W} r={r} T={transpose}: worst ratio {np.max(err / bound):.3f}"
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("H,W", [(64, 64), (37, 101), (3, 3), (4096, 4096)])
+def test_restrict_bitwise(torch_cuda, prec, H, W):
+    rng = np.random.Generator(np.random.PCG64(7))
+    g = rng.standard_normal((H, W)).astype(_dt(prec))
+    out = eecmg.restrict_dev(_dev(torch_cuda, g, prec), precision=prec).cpu().numpy()
+    np.testing.assert_array_equal(out, g[::2, ::2])
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("HC,WC", [(33, 33), (32, 32), (34, 30), (129, 70), (1026, 515)])
+def test_transfer_operators_parity(torch_cuda, prec, HC, WC):
+    rng = np.random.Generator(np.random.PCG64(HC * 7 + WC))
+    HB, WB = (HC + 1) // 2, (WC + 1) // 2
+    HA, WA = (HB + 1) // 2, (WB + 1) // 2
+    uA = rng.uniform(0, 255, size=(HA, WA)).astype(_dt(prec)).astype(np.float64)
+    uB = rng.uniform(0, 255, size=(HB, WB)).astype(_dt(prec)).astype(np.float64)
+    t = torch_cuda
+    ut = eecmg.extrapolate_dev(_dev(t, uA, prec), _dev(t, uB, prec), precision=prec)
+    _close(ut.cpu().numpy(), oracle.extrapolate(uA, uB), prec, "extrapolate")
+    ut_host = ut.cpu().numpy().astype(np.float64)
+    uC = eecmg.prolong_quad_dev(ut, HC, WC, precision=prec)
+    _close(uC.cpu().numpy(), oracle.prolong_quad(ut_host, HC, WC), prec, "prolong_quad")
+    uL = eecmg.prolong_linear_dev(_dev(t, uB, prec), HC, WC, precision=prec)
+    _close(uL.cpu().numpy(), oracle.prolong_linear(uB, HC, WC), prec, "prolong_linear")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("H,W", [(40, 40), (67, 131), (3, 5), (515, 1030)])
+def test_smooth_and_denoise_parity(torch_cuda, prec, H, W):
+    rng = np.random.Generator(np.random.PCG64(H + 17 * W))
+    u = 100 + 2.0 * rng.standard_normal((H, W))
+    u[H // 4: H // 2, W // 3: W // 2] += 60.0  # edges: weights cut off
+    u = u.astype(_dt(prec)).astype(np.float64)
+    t = torch_cuda
+    for hs in (1.0, 3.0):
+        s = eecmg.local_smooth_dev(_dev(t, u, prec), smooth_h=hs, precision=prec)
+        _close(s.cpu().numpy(), oracle.local_smooth(u, hs), prec, f"local_smooth h={hs}")
+    for k, tau in ((10.0, 0.2), (2.0, 0.25)):
+        d = eecmg.pm_step_dev(_dev(t, u, prec), k=k, tau=tau, precision=prec)
+        _close(d.cpu().numpy(), oracle.pm_step(u, k, tau), prec, f"pm_step k={k}")
+
+
+def test_operator_errors(torch_cuda):
+    t = torch_cuda
+    x = t.zeros((8, 8), dtype=t.float32, device="cuda:0")
+    with pytest.raises(eecmg.EecmgError) as e:
+        eecmg.conv_dev(x, np.ones((27, 27)))  # radius 13 > 12
+    assert e.value.status == eecmg.EINVAL
+    with pytest.raises(eecmg.EecmgError):
+        eecmg.pm_step_dev(x, k=10.0, tau=0.3)
+    with pytest.raises(eecmg.EecmgError):
+        eecmg.local_smooth_dev(x, smooth_h=0.0)
