@@ -533,8 +533,10 @@ class Engine {
             break;
           }
           case Job::kIter: {
-            const LevelPlan& lp = j->plan.lv[j->cur_level()];
-            if (j->cancelled || j->level_done_seen || j->issued >= lp.cap) {
+            // launches per level: CGLS needs cap iterations; MR needs one
+            // more pass, because its first pass only forms q = H r
+            const int limit = j->plan.lv[j->cur_level()].cap + (j->plan.prm.smoother == EECMG_SMOOTHER_MR ? 1 : 0);
+            if (j->cancelled || j->level_done_seen || j->issued >= limit) {
               if (!j->cancelled && j->oi + 1 < (int)j->plan.order.size()) {
                 j->oi += 1;
                 j->phase = Job::kStartLevel;
@@ -546,7 +548,7 @@ class Engine {
               break;
             }
             const int ahead = j->issued - j->confirmed;
-            int chunk = std::min(j->next_chunk, lp.cap - j->issued);
+            int chunk = std::min(j->next_chunk, limit - j->issued);
             chunk = std::min(chunk, kMaxAhead - ahead);
             if (chunk > 0) {
               iter_l.push_back({j, chunk});

@@ -54,7 +54,11 @@ def _check(p, prec, u, st, u_ref, st_ref):
     print(f"  rel_l2={rel:.3e} dPSNR={dpsnr:.2e}", flush=True)
     assert rel <= REL[prec]
     assert dpsnr <= 0.01
-    np.testing.assert_allclose(st["final_rms"], st_ref["final_rms"], rtol=1e-10 if prec == "f64" else 1e-4)
+    # residuals of levels solved to rounding (H_l = I) are ~1e-14 in FP64 and
+    # may be exactly 0 in FP32: absolute floor scaled by the largest residual
+    floor = (1e-12 if prec == "f64" else 1e-5) * max(max(st_ref["final_rms"]), 1.0)
+    np.testing.assert_allclose(st["final_rms"], st_ref["final_rms"], rtol=1e-10 if prec == "f64" else 1e-4,
+                               atol=floor)
 
 
 # ------------------------------------------------------------------ smoothers
