@@ -1,0 +1,522 @@
+// Device-side building blocks of the EECMG kernels (gfx950, wave64):
+// launch-list lookup, fixed-order FP64 reductions, LDS tile staging, the
+// blur-operator policies and the smoother pass kernels templated on them.
+#pragma once
+
+#include <math.h>
+
+#include "eecmg_internal.h"
+
+namespace eecmg {
+
+// ---------------------------------------------------------------------------
+// Launch-list helpers
+// ---------------------------------------------------------------------------
+
+// Blocks are dispatched round-robin over the 8 XCDs.  Remap so that each XCD
+// receives a contiguous run of tiles: vertically adjacent tiles then share
+// their halo rows through the same L2.
+__device__ __forceinline__ int remap_xcd(int b, int nb) {
+  if (nb < 64) return b;
+  const int xcd = b & 7, j = b >> 3, q = nb >> 3, rm = nb & 7;
+  return (xcd < rm) ? xcd * (q + 1) + j : rm * (q + 1) + (xcd - rm) * q + j;
+}
+
+struct Loc {
+  int e;  // entry in the launch list
+  int d;  // descriptor index
+  int t;  // tile within the job
+};
+
+__device__ __forceinline__ Loc locate(const LaunchList& ll, int b) {
+  int lo = 0, hi = ll.n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ll.start[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return Loc{lo, ll.job[lo], b - ll.start[lo]};
+}
+
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+template <typename T>
+__device__ __forceinline__ T to_t(double x) {
+  return (T)x;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum NV per-lane FP64 values over an NT-thread block in a fixed order and
+// store them (thread 0) to out[0..NV).
+template <int NT, int NV>
+__device__ __forceinline__ void block_sum_store(double (&v)[NV], double* __restrict__ out) {
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  if constexpr (NT == 64) {
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) out[i] = v[i];
+    }
+  } else {
+    constexpr int NW = NT / 64;
+    __shared__ double red[NW][NV];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) red[wave][i] = v[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        double s = red[0][i];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) s += red[w][i];
+        out[i] = s;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Blur-operator policies.  Each policy evaluates, for the lane's column
+// x0 + lane of a TH x TW output tile, (H x)(i, j) = sum_{a,b} psf(a,b) x(i-a, j-b)
+// from an LDS tile holding rows [y0 - R, y0 + TH + R) and columns
+// [x0 - R, x0 + TW + R) (zero outside the image), and calls
+// emit(row, value) for each output row of the lane as soon as it is
+// complete.  H^T is the same operator with the flipped PSF (the host passes
+// flipped taps).
+// ---------------------------------------------------------------------------
+
+// General PSF: all (2R+1)^2 taps, R known at run time (R <= RMAX).  Four waves
+// share a 64 x 32 tile, kV = 8 output rows each; for each column offset b a
+// lane loads its column segment once into registers (shifted so that every
+// register index is a compile-time constant) and applies every row offset.
+template <typename T, int RMAX>
+struct ConvGeneral {
+  static constexpr int NT = 256, TW = kTW, TH = kTH, LW = kTW + 2 * RMAX, LH = kTH + 2 * RMAX;
+  static constexpr bool kRuntimeR = true;
+  template <typename Emit>
+  __device__ static __forceinline__ void conv(const T* __restrict__ tile, const T* __restrict__ taps, int R, int wave,
+                                              int lane, Emit emit) {
+    T acc[kV];
+#pragma unroll
+    for (int v = 0; v < kV; ++v) acc[v] = T(0);
+    const int n = 2 * R + 1;
+    for (int b = -R; b <= R; ++b) {
+      T xc[kV + 2 * RMAX];
+      const int col = lane + R - b;
+#pragma unroll
+      for (int t = 0; t < kV + 2 * RMAX; ++t) {
+        const int lr = wave * kV + t - (RMAX - R);
+        xc[t] = (t >= RMAX - R && t < RMAX + R + kV) ? tile[lr * LW + col] : T(0);
+      }
+#pragma unroll
+      for (int a = -RMAX; a <= RMAX; ++a) {
+        if (a >= -R && a <= R) {
+          const T wt = taps[(a + R) * n + (b + R)];
+#pragma unroll
+          for (int v = 0; v < kV; ++v) acc[v] = fma(wt, xc[v + RMAX - a], acc[v]);
+        }
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < kV; ++v) emit(wave * kV + v, acc[v]);
+  }
+};
+
+// Rank-one PSF psf(a,b) = col(a) row(b) (the Gaussian of Section 5 and its
+// coarse levels).  One wave per 64 x 32 tile; the lane slides down its column:
+// for each LDS row it forms the horizontal filter h = sum_b row(b) x(., j-b)
+// once and adds col(a) h to the (at most 2R+1) pending outputs it feeds.
+// Taps: row(-R..R) followed by col(-R..R).
+template <typename T, int R>
+struct ConvSep {
+  static constexpr int NT = 64, TW = kTW, TH = kTH, LW = kTW + 2 * R, LH = kTH + 2 * R;
+  static constexpr bool kRuntimeR = false;
+  template <typename Emit>
+  __device__ static __forceinline__ void conv(const T* __restrict__ tile, const T* __restrict__ taps, int, int,
+                                              int lane, Emit emit) {
+    T rw[2 * R + 1], cl[2 * R + 1];
+#pragma unroll
+    for (int k = 0; k < 2 * R + 1; ++k) {
+      rw[k] = taps[k];
+      cl[k] = taps[2 * R + 1 + k];
+    }
+    T acc[TH];
+#pragma unroll
+    for (int t = 0; t < LH; ++t) {
+      const T* __restrict__ row = tile + t * LW + lane + R;
+      T h = rw[0] * row[R];
+#pragma unroll
+      for (int b = -R + 1; b <= R; ++b) h = fma(rw[b + R], row[-b], h);
+#pragma unroll
+      for (int a = R; a >= -R; --a) {
+        const int v = t - R + a;
+        if (v >= 0 && v < TH) {
+          if (a == R)
+            acc[v] = cl[a + R] * h;
+          else
+            acc[v] = fma(cl[a + R], h, acc[v]);
+        }
+      }
+      const int vd = t - 2 * R;
+      if (vd >= 0 && vd < TH) emit(vd, acc[vd]);
+    }
+  }
+};
+
+// Largest b with a^2 + b^2 <= R^2 (disk support), or R (square support).
+constexpr int sym_span(int R, bool disk, int a) {
+  if (!disk) return R;
+  int b = 0;
+  while ((b + 1) * (b + 1) + a * a <= R * R) ++b;
+  return b;
+}
+constexpr int sym_offset(int R, bool disk, int a) {
+  int o = 0;
+  for (int k = 0; k < a; ++k) o += sym_span(R, disk, k) + 1;
+  return o;
+}
+constexpr int sym_ntaps(int R, bool disk) { return sym_offset(R, disk, R + 1); }
+
+// PSF symmetric under both axis reflections, psf(a,b) = psf(-a,b) = psf(a,-b),
+// with square or disk support (the out-of-focus disk of the 4096^2
+// workload).  Rows a and -a share one horizontal "row filter"
+//   h_a = psf(a,0) x(j) + sum_{b>=1} psf(a,b) (x(j-b) + x(j+b)),
+// computed once per LDS row from the pair sums and added to the outputs a
+// rows below and above: about (R+1)(R+2)/2 + 2R ops per row and pixel
+// instead of (2R+1)^2 FMAs.  Taps: the quadrant a, b >= 0, row by row
+// (b = 0..span(a)).
+template <typename T, int R, bool DISK>
+struct ConvSym {
+  static constexpr int NT = 64, TW = kTW, TH = kTH, LW = kTW + 2 * R, LH = kTH + 2 * R;
+  static constexpr bool kRuntimeR = false;
+  static constexpr int NTAPS = sym_ntaps(R, DISK);
+  template <typename Emit>
+  __device__ static __forceinline__ void conv(const T* __restrict__ tile, const T* __restrict__ taps, int, int,
+                                              int lane, Emit emit) {
+    T wt[NTAPS];
+#pragma unroll
+    for (int k = 0; k < NTAPS; ++k) wt[k] = taps[k];
+    T acc[TH];
+#pragma unroll
+    for (int t = 0; t < LH; ++t) {
+      const T* __restrict__ row = tile + t * LW + lane + R;
+      const T x0 = row[0];
+      T pr[R + 1];
+#pragma unroll
+      for (int b = 1; b <= R; ++b) pr[b] = row[b] + row[-b];
+      T h[R + 1];
+#pragma unroll
+      for (int a = 0; a <= R; ++a) {
+        const bool need = (t - R + a >= 0 && t - R + a < TH) || (t - R - a >= 0 && t - R - a < TH);
+        if (need) {
+          const int o = sym_offset(R, DISK, a);
+          const int span = sym_span(R, DISK, a);
+          T v = wt[o] * x0;
+#pragma unroll
+          for (int b = 1; b <= R; ++b)
+            if (b <= span) v = fma(wt[o + b], pr[b], v);
+          h[a] = v;
+        }
+      }
+#pragma unroll
+      for (int a = R; a >= -R; --a) {
+        const int v = t - R + a;
+        if (v >= 0 && v < TH) {
+          const T hv = h[a >= 0 ? a : -a];
+          if (a == R)
+            acc[v] = hv;
+          else
+            acc[v] = acc[v] + hv;
+        }
+      }
+      const int vd = t - 2 * R;
+      if (vd >= 0 && vd < TH) emit(vd, acc[vd]);
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Tile staging
+// ---------------------------------------------------------------------------
+struct TileGeo {
+  int R, h, w, pitch, y0, x0, wave, lane;
+};
+
+template <typename P>
+__device__ __forceinline__ TileGeo tile_geo(const JobDesc& d, int t) {
+  TileGeo g;
+  g.R = uni(d.rad);
+  g.h = uni(d.h);
+  g.w = uni(d.w);
+  g.pitch = uni(d.pitch);
+  const int tiles_x = uni(d.tiles_x);
+  const int ty = t / tiles_x, tx = t - ty * tiles_x;
+  g.y0 = ty * P::TH;
+  g.x0 = tx * P::TW;
+  g.wave = uni(threadIdx.x >> 6);
+  g.lane = threadIdx.x & 63;
+  return g;
+}
+
+// Load tile + halo through a per-pixel functor f(offset, interior) -> T
+// (interior: the pixel belongs to this tile's output region).  Pixels
+// outside the image are zero (the operator's zero boundary condition).
+template <typename T, typename P, typename F>
+__device__ __forceinline__ void load_tile(T* __restrict__ tile, const TileGeo& g, F f) {
+  const int R = P::kRuntimeR ? g.R : (P::LW - P::TW) / 2;
+  constexpr int NW = P::NT / 64;
+  for (int ly = g.wave; ly < P::TH + 2 * R; ly += NW) {
+    const int gy = g.y0 - R + ly;
+    const bool row_in = gy >= 0 && gy < g.h;
+    const bool row_int = ly >= R && ly < R + P::TH;
+    for (int lx = g.lane; lx < P::TW + 2 * R; lx += 64) {
+      const int gx = g.x0 - R + lx;
+      T v = T(0);
+      if (row_in && gx >= 0 && gx < g.w) {
+        const bool interior = row_int && lx >= R && lx < R + P::TW;
+        v = f((size_t)gy * g.pitch + gx, interior);
+      }
+      tile[ly * P::LW + lx] = v;
+    }
+  }
+}
+
+template <typename P>
+__device__ __forceinline__ int pol_R(const TileGeo& g) {
+  return P::kRuntimeR ? g.R : (P::LW - P::TW) / 2;
+}
+
+// ---------------------------------------------------------------------------
+// Smoother pass kernels, templated on the element type and blur policy.
+// ---------------------------------------------------------------------------
+
+// r = g - H u0, stored in r[0]; partial <r,r> in slot 1.  (CGLS and MR)
+template <typename T, typename P>
+__global__ __launch_bounds__(P::NT) void k_init1(LaunchList ll, const JobDesc* __restrict__ descs) {
+  __shared__ T tile[P::LH * P::LW];
+  const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
+  const JobDesc& d = descs[L.d];
+  const TileGeo g = tile_geo<P>(d, L.t);
+  const T* __restrict__ u = (const T*)d.u;
+  const T* __restrict__ gg = (const T*)d.g;
+  T* __restrict__ r = (T*)d.r[0];
+  load_tile<T, P>(tile, g, [&](size_t o, bool) { return u[o]; });
+  __syncthreads();
+  double part[1] = {0.0};
+  const int gx = g.x0 + g.lane;
+  P::conv(tile, (const T*)d.taps, g.R, g.wave, g.lane, [&](int v, T acc) {
+    const int gy = g.y0 + v;
+    if (gy < g.h && gx < g.w) {
+      const size_t o = (size_t)gy * g.pitch + gx;
+      const T rv = to_t<T>((double)gg[o] - (double)acc);
+      r[o] = rv;
+      part[0] += (double)rv * (double)rv;
+    }
+  });
+  block_sum_store<P::NT, 1>(part, d.partials + (size_t)L.t * kNPart + 1);
+}
+
+// s = H^T r, p[0] = s; partial <s,s> in slot 2.
+template <typename T, typename P>
+__global__ __launch_bounds__(P::NT) void k_cg_init2(LaunchList ll, const JobDesc* __restrict__ descs) {
+  __shared__ T tile[P::LH * P::LW];
+  const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
+  const JobDesc& d = descs[L.d];
+  const TileGeo g = tile_geo<P>(d, L.t);
+  const T* __restrict__ r = (const T*)d.r[0];
+  T* __restrict__ s = (T*)d.s;
+  T* __restrict__ p = (T*)d.p[0];
+  load_tile<T, P>(tile, g, [&](size_t o, bool) { return r[o]; });
+  __syncthreads();
+  double part[1] = {0.0};
+  const int gx = g.x0 + g.lane;
+  P::conv(tile, (const T*)d.taps_t, g.R, g.wave, g.lane, [&](int v, T acc) {
+    const int gy = g.y0 + v;
+    if (gy < g.h && gx < g.w) {
+      const size_t o = (size_t)gy * g.pitch + gx;
+      s[o] = acc;
+      p[o] = acc;
+      part[0] += (double)acc * (double)acc;
+    }
+  });
+  block_sum_store<P::NT, 1>(part, d.partials + (size_t)L.t * kNPart + 2);
+}
+
+// Pass A of iteration k: p_new = s + beta p_old (on tile + halo), q = H p_new;
+// partial <q,q> in slot 0.
+template <typename T, typename P>
+__global__ __launch_bounds__(P::NT) void k_cg_a(LaunchList ll, const JobDesc* __restrict__ descs) {
+  __shared__ T tile[P::LH * P::LW];
+  const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
+  const JobDesc& d = descs[L.d];
+  const SolverState* st = d.st;
+  if (__builtin_amdgcn_readfirstlane(st->done)) return;
+  const TileGeo g = tile_geo<P>(d, L.t);
+  const int par = uni(st->par);
+  const double beta = st->beta;
+  const T* __restrict__ s = (const T*)d.s;
+  const T* __restrict__ po = (const T*)d.p[par];
+  T* __restrict__ pn = (T*)d.p[par ^ 1];
+  T* __restrict__ q = (T*)d.q[0];
+  load_tile<T, P>(tile, g, [&](size_t o, bool interior) {
+    const T v = to_t<T>((double)s[o] + beta * (double)po[o]);
+    if (interior) pn[o] = v;
+    return v;
+  });
+  __syncthreads();
+  double part[1] = {0.0};
+  const int gx = g.x0 + g.lane;
+  P::conv(tile, (const T*)d.taps, g.R, g.wave, g.lane, [&](int v, T acc) {
+    const int gy = g.y0 + v;
+    if (gy < g.h && gx < g.w) {
+      q[(size_t)gy * g.pitch + gx] = acc;
+      part[0] += (double)acc * (double)acc;
+    }
+  });
+  block_sum_store<P::NT, 1>(part, d.partials + (size_t)L.t * kNPart + 0);
+}
+
+// Pass B of iteration k: r_new = r - alpha q (tile + halo), s = H^T r_new,
+// u += alpha p_new; partials <r,r> (slot 1) and <s,s> (slot 2).
+template <typename T, typename P>
+__global__ __launch_bounds__(P::NT) void k_cg_b(LaunchList ll, const JobDesc* __restrict__ descs) {
+  __shared__ T tile[P::LH * P::LW];
+  const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
+  const JobDesc& d = descs[L.d];
+  const SolverState* st = d.st;
+  if (__builtin_amdgcn_readfirstlane(st->done)) return;
+  const TileGeo g = tile_geo<P>(d, L.t);
+  const int par = uni(st->par);
+  const double alpha = st->alpha;
+  const T* __restrict__ ro = (const T*)d.r[par];
+  T* __restrict__ rn = (T*)d.r[par ^ 1];
+  const T* __restrict__ q = (const T*)d.q[0];
+  const T* __restrict__ pn = (const T*)d.p[par ^ 1];
+  T* __restrict__ u = (T*)d.u;
+  T* __restrict__ s = (T*)d.s;
+  double part[2] = {0.0, 0.0};
+  load_tile<T, P>(tile, g, [&](size_t o, bool interior) {
+    const T v = to_t<T>((double)ro[o] - alpha * (double)q[o]);
+    if (interior) {
+      rn[o] = v;
+      part[0] += (double)v * (double)v;
+    }
+    return v;
+  });
+  __syncthreads();
+  const int gx = g.x0 + g.lane;
+  P::conv(tile, (const T*)d.taps_t, g.R, g.wave, g.lane, [&](int v, T acc) {
+    const int gy = g.y0 + v;
+    if (gy < g.h && gx < g.w) {
+      const size_t o = (size_t)gy * g.pitch + gx;
+      s[o] = acc;
+      part[1] += (double)acc * (double)acc;
+      u[o] = to_t<T>((double)u[o] + alpha * (double)pn[o]);
+    }
+  });
+  block_sum_store<P::NT, 2>(part, d.partials + (size_t)L.t * kNPart + 1);
+}
+
+// MR pass: if a step alpha is pending, r_new = r - alpha q and u += alpha r;
+// then q_new = H r_new.  Partials <r_new,q_new> (0), <r_new,r_new> (1), <q,q> (2).
+template <typename T, typename P>
+__global__ __launch_bounds__(P::NT) void k_mr_pass(LaunchList ll, const JobDesc* __restrict__ descs) {
+  __shared__ T tile[P::LH * P::LW];
+  const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
+  const JobDesc& d = descs[L.d];
+  const SolverState* st = d.st;
+  if (__builtin_amdgcn_readfirstlane(st->done)) return;
+  const TileGeo g = tile_geo<P>(d, L.t);
+  const int R = pol_R<P>(g);
+  const int par = uni(st->par);
+  const bool pending = uni(st->pending) != 0;
+  const double alpha = st->alpha;
+  const T* __restrict__ ro = (const T*)d.r[par];
+  const T* __restrict__ qo = (const T*)d.q[par];
+  T* __restrict__ rn = (T*)d.r[par ^ 1];
+  T* __restrict__ qn = (T*)d.q[par ^ 1];
+  T* __restrict__ u = (T*)d.u;
+  double part[3] = {0.0, 0.0, 0.0};
+  load_tile<T, P>(tile, g, [&](size_t o, bool interior) {
+    const T r0 = ro[o];
+    const T v = pending ? to_t<T>((double)r0 - alpha * (double)qo[o]) : r0;
+    if (interior) {
+      rn[o] = v;
+      part[1] += (double)v * (double)v;
+      if (pending) u[o] = to_t<T>((double)u[o] + alpha * (double)r0);
+    }
+    return v;
+  });
+  __syncthreads();
+  const int gx = g.x0 + g.lane;
+  P::conv(tile, (const T*)d.taps, g.R, g.wave, g.lane, [&](int v, T acc) {
+    const int gy = g.y0 + v;
+    if (gy < g.h && gx < g.w) {
+      qn[(size_t)gy * g.pitch + gx] = acc;
+      const T rc = tile[(v + R) * P::LW + g.lane + R];
+      part[0] += (double)rc * (double)acc;
+      part[2] += (double)acc * (double)acc;
+    }
+  });
+  block_sum_store<P::NT, 3>(part, d.partials + (size_t)L.t * kNPart + 0);
+}
+
+// Operator form: y = H x on one dense image with the given taps layout.
+template <typename T, typename P>
+__global__ __launch_bounds__(P::NT) void k_op_conv(const T* __restrict__ x, T* __restrict__ y, int H, int W,
+                                                   const T* __restrict__ taps, int R) {
+  __shared__ T tile[P::LH * P::LW];
+  const int tiles_x = (W + P::TW - 1) / P::TW;
+  TileGeo g;
+  g.R = R;
+  g.h = H;
+  g.w = W;
+  g.pitch = W;
+  g.y0 = (blockIdx.x / tiles_x) * P::TH;
+  g.x0 = (blockIdx.x % tiles_x) * P::TW;
+  g.wave = uni(threadIdx.x >> 6);
+  g.lane = threadIdx.x & 63;
+  load_tile<T, P>(tile, g, [&](size_t o, bool) { return x[o]; });
+  __syncthreads();
+  const int gx = g.x0 + g.lane;
+  P::conv(tile, taps, R, g.wave, g.lane, [&](int v, T acc) {
+    const int gy = g.y0 + v;
+    if (gy < H && gx < W) y[(size_t)gy * W + gx] = acc;
+  });
+}
+
+// Dispatch of one smoother stage for one policy.
+template <typename T, typename P>
+hipError_t launch_policy(Stage st, const LaunchList& ll, const JobDesc* descs, hipStream_t s) {
+  const dim3 grid(ll.total), block(P::NT);
+  switch (st) {
+    case kCgInit1:
+    case kMrInit: hipLaunchKernelGGL((k_init1<T, P>), grid, block, 0, s, ll, descs); break;
+    case kCgInit2: hipLaunchKernelGGL((k_cg_init2<T, P>), grid, block, 0, s, ll, descs); break;
+    case kCgA: hipLaunchKernelGGL((k_cg_a<T, P>), grid, block, 0, s, ll, descs); break;
+    case kCgB: hipLaunchKernelGGL((k_cg_b<T, P>), grid, block, 0, s, ll, descs); break;
+    case kMrPass: hipLaunchKernelGGL((k_mr_pass<T, P>), grid, block, 0, s, ll, descs); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T, typename P>
+hipError_t launch_op_conv(const void* x, void* y, int H, int W, const void* taps, int R, hipStream_t s) {
+  const int blocks = ((H + P::TH - 1) / P::TH) * ((W + P::TW - 1) / P::TW);
+  hipLaunchKernelGGL((k_op_conv<T, P>), dim3(blocks), dim3(P::NT), 0, s, (const T*)x, (T*)y, H, W, (const T*)taps,
+                     R);
+  return hipGetLastError();
+}
+
+}  // namespace eecmg

@@ -117,17 +117,18 @@ enum Stage : int32_t {
 // Buffer selectors of the transfer stages.
 enum XBuf : int32_t { kBufU = 0, kBufT1 = 1, kBufT2 = 2, kBufUB = 3 };
 
-// Conv implementation families.
-enum ConvKind : int32_t { kConvGeneral = 0 };
+// Blur-operator implementation families.  A variant id is kind * 100 + R
+// (for kConvGeneral, R is the radius class 3, 6 or 12).
+enum ConvKind : int32_t { kConvGeneral = 0, kConvSep = 1, kConvSymSquare = 2, kConvSymDisk = 3 };
 
 // Host-side launchers (defined in eecmg_kernels.hip).
-hipError_t launch_stage(Stage st, bool f64, int rmax_class, const LaunchList& ll, const JobDesc* descs,
-                        int src, int dst, hipStream_t stream);
+hipError_t launch_stage(Stage st, bool f64, int variant, const LaunchList& ll, const JobDesc* descs, int src,
+                        int dst, hipStream_t stream);
 int rmax_class_for(int r);
 int blocks_for_stage(Stage st, const JobDesc& d);
 
 // Operator kernels on dense buffers (one image, no job table).
-hipError_t op_conv(const void* x, void* y, int H, int W, const void* taps, int r, bool f64, hipStream_t s);
+hipError_t op_conv(const void* x, void* y, int H, int W, const void* taps, int variant, bool f64, hipStream_t s);
 hipError_t op_restrict(const void* gf, int Hf, int Wf, void* gc, bool f64, hipStream_t s);
 hipError_t op_extrapolate(const void* uA, const void* uB, int HB, int WB, void* ut, bool f64, hipStream_t s);
 hipError_t op_prolong_quad(const void* ut, int HC, int WC, void* uC, bool f64, hipStream_t s);

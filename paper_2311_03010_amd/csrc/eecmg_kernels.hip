@@ -1,82 +1,24 @@
-// HIP kernels (gfx950, wave64) of the EECMG cascade.
+// HIP kernels (gfx950, wave64) of the EECMG cascade, other than the smoother
+// passes: the finalize kernels that run the scalar Krylov recurrences on the
+// device, the level-transfer operators, restriction, output copy, and the
+// top-level launch dispatch.
 //
-// Every kernel works on row-major pitched images in HBM.  Stencils stage a
-// tile plus its halo in LDS; the blur operator is evaluated with a
-// register-blocked sliding column (each lane owns one column and kV output
-// rows, so every LDS value feeds up to kV FMAs); inner products are
-// accumulated per lane in FP64, reduced across the wave with shuffles and
-// across the block in a fixed order, and written as one partial per tile.
-// Small finalize kernels sum the partials of a job in a fixed order and run
-// the scalar part of the Krylov recurrences on the device, so results are
-// deterministic and independent of how many jobs share a launch.
+// Finalize kernels sum the per-tile FP64 partials of one job in a fixed
+// order, so every result is deterministic and independent of how many jobs
+// share a launch.
 #include <math.h>
 
-#include "eecmg_internal.h"
+#include "eecmg_device.h"
 
 namespace eecmg {
 
 // ---------------------------------------------------------------------------
-// Launch-list helpers
+// Finalize kernels: one block per job, scalar recurrences in FP64.
 // ---------------------------------------------------------------------------
-
-// Blocks are dispatched round-robin over the 8 XCDs.  Remap so that each XCD
-// receives a contiguous run of tiles: vertically adjacent tiles then share
-// their halo rows through the same L2.
-__device__ __forceinline__ int remap_xcd(int b, int nb) {
-  if (nb < 64) return b;
-  const int xcd = b & 7, j = b >> 3, q = nb >> 3, rm = nb & 7;
-  return (xcd < rm) ? xcd * (q + 1) + j : rm * (q + 1) + (xcd - rm) * q + j;
-}
-
-struct Loc {
-  int e;  // entry in the launch list
-  int d;  // descriptor index
-  int t;  // tile within the job
-};
-
-__device__ __forceinline__ Loc locate(const LaunchList& ll, int b) {
-  int lo = 0, hi = ll.n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (ll.start[mid] <= b)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return Loc{lo, ll.job[lo], b - ll.start[lo]};
-}
-
-__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
-
-template <typename T>
-__device__ __forceinline__ T to_t(double x) {
-  return (T)x;
-}
-
-// Sum NV per-lane FP64 values over the 256-thread block in a fixed order and
-// store them (thread 0) to out[0..NV).
-template <int NV>
-__device__ __forceinline__ void block_sum_store(double (&v)[NV], double* __restrict__ out) {
-  __shared__ double red[4][NV];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_xor(v[i], off, 64);
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) red[wave][i] = v[i];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) out[i] = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
-  }
-}
+__device__ __forceinline__ bool finite_d(double x) { return isfinite(x); }
 
 // Fixed-order sum of selected components of the tile partials of one job,
-// returned to every thread of the block.
+// returned to every thread of the 256-thread block.
 template <int NV>
 __device__ __forceinline__ void sum_partials(const double* __restrict__ part, int ntiles, const int (&comp)[NV],
                                              double (&out)[NV]) {
@@ -90,10 +32,7 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ part, in
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int i = 0; i < NV; ++i) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc[i] += __shfl_xor(acc[i], off, 64);
-  }
+  for (int i = 0; i < NV; ++i) acc[i] = wave_sum(acc[i]);
   if (lane == 0) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) red[wave][i] = acc[i];
@@ -102,281 +41,6 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ part, in
 #pragma unroll
   for (int i = 0; i < NV; ++i) out[i] = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
 }
-
-// ---------------------------------------------------------------------------
-// Blur operator on an LDS tile.
-//
-// tile holds the input on rows [y0 - R, y0 + kTH + R) and columns
-// [x0 - R, x0 + kTW + R) (zero outside the image), row stride kTW + 2 RMAX.
-// The lane computes, for column x0 + lane and rows y0 + wave*kV + v,
-//   acc[v] = sum_{|a|,|b| <= R} taps[(a+R)(2R+1) + (b+R)] x(row - a, col - b).
-// For each column offset b the lane loads its column segment once into
-// registers (xc, shifted so that every register index is a compile-time
-// constant) and applies all row offsets a to its kV outputs.
-// ---------------------------------------------------------------------------
-template <typename T, int RMAX>
-__device__ __forceinline__ void conv_tile(const T* __restrict__ tile, int R, const T* __restrict__ taps, int wave,
-                                          int lane, T (&acc)[kV]) {
-  constexpr int LW = kTW + 2 * RMAX;
-#pragma unroll
-  for (int v = 0; v < kV; ++v) acc[v] = T(0);
-  const int n = 2 * R + 1;
-  for (int b = -R; b <= R; ++b) {
-    T xc[kV + 2 * RMAX];
-    const int col = lane + R - b;
-#pragma unroll
-    for (int t = 0; t < kV + 2 * RMAX; ++t) {
-      const int lr = wave * kV + t - (RMAX - R);
-      xc[t] = (t >= RMAX - R && t < RMAX + R + kV) ? tile[lr * LW + col] : T(0);
-    }
-#pragma unroll
-    for (int a = -RMAX; a <= RMAX; ++a) {
-      if (a >= -R && a <= R) {
-        const T wt = taps[(a + R) * n + (b + R)];
-#pragma unroll
-        for (int v = 0; v < kV; ++v) acc[v] = fma(wt, xc[v + RMAX - a], acc[v]);
-      }
-    }
-  }
-}
-
-// Tile geometry shared by the smoother kernels.
-struct TileGeo {
-  int R, h, w, pitch, y0, x0, wave, lane;
-};
-
-__device__ __forceinline__ TileGeo tile_geo(const JobDesc& d, int t) {
-  TileGeo g;
-  g.R = uni(d.rad);
-  g.h = uni(d.h);
-  g.w = uni(d.w);
-  g.pitch = uni(d.pitch);
-  const int tiles_x = uni(d.tiles_x);
-  const int ty = t / tiles_x, tx = t - ty * tiles_x;
-  g.y0 = ty * kTH;
-  g.x0 = tx * kTW;
-  g.wave = uni(threadIdx.x >> 6);
-  g.lane = threadIdx.x & 63;
-  return g;
-}
-
-// Load tile + halo through a per-pixel functor f(offset, interior) -> T
-// (interior: the pixel belongs to this tile's output region).  Pixels
-// outside the image are zero (the operator's zero boundary condition).
-template <typename T, int RMAX, typename F>
-__device__ __forceinline__ void load_tile(T* __restrict__ tile, const TileGeo& g, F f) {
-  constexpr int LW = kTW + 2 * RMAX;
-  for (int ly = g.wave; ly < kTH + 2 * g.R; ly += 4) {
-    const int gy = g.y0 - g.R + ly;
-    const bool row_in = gy >= 0 && gy < g.h;
-    const bool row_int = ly >= g.R && ly < g.R + kTH;
-    for (int lx = g.lane; lx < kTW + 2 * g.R; lx += 64) {
-      const int gx = g.x0 - g.R + lx;
-      T v = T(0);
-      if (row_in && gx >= 0 && gx < g.w) {
-        const bool interior = row_int && lx >= g.R && lx < g.R + kTW;
-        v = f((size_t)gy * g.pitch + gx, interior);
-      }
-      tile[ly * LW + lx] = v;
-    }
-  }
-}
-
-// r = g - H u0, stored in r[0]; partial <r,r> in slot 1.  (CGLS and MR)
-template <typename T, int RMAX>
-__global__ __launch_bounds__(256) void k_init1(LaunchList ll, const JobDesc* __restrict__ descs) {
-  __shared__ T tile[(kTH + 2 * RMAX) * (kTW + 2 * RMAX)];
-  const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
-  const JobDesc& d = descs[L.d];
-  const TileGeo g = tile_geo(d, L.t);
-  const T* __restrict__ u = (const T*)d.u;
-  const T* __restrict__ gg = (const T*)d.g;
-  T* __restrict__ r = (T*)d.r[0];
-  load_tile<T, RMAX>(tile, g, [&](size_t o, bool) { return u[o]; });
-  __syncthreads();
-  T acc[kV];
-  conv_tile<T, RMAX>(tile, g.R, (const T*)d.taps, g.wave, g.lane, acc);
-  double part[1] = {0.0};
-  const int gx = g.x0 + g.lane;
-#pragma unroll
-  for (int v = 0; v < kV; ++v) {
-    const int gy = g.y0 + g.wave * kV + v;
-    if (gy < g.h && gx < g.w) {
-      const size_t o = (size_t)gy * g.pitch + gx;
-      const T rv = to_t<T>((double)gg[o] - (double)acc[v]);
-      r[o] = rv;
-      part[0] += (double)rv * (double)rv;
-    }
-  }
-  block_sum_store<1>(part, d.partials + (size_t)L.t * kNPart + 1);
-}
-
-// s = H^T r, p[0] = s; partial <s,s> in slot 2.
-template <typename T, int RMAX>
-__global__ __launch_bounds__(256) void k_cg_init2(LaunchList ll, const JobDesc* __restrict__ descs) {
-  __shared__ T tile[(kTH + 2 * RMAX) * (kTW + 2 * RMAX)];
-  const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
-  const JobDesc& d = descs[L.d];
-  const TileGeo g = tile_geo(d, L.t);
-  const T* __restrict__ r = (const T*)d.r[0];
-  T* __restrict__ s = (T*)d.s;
-  T* __restrict__ p = (T*)d.p[0];
-  load_tile<T, RMAX>(tile, g, [&](size_t o, bool) { return r[o]; });
-  __syncthreads();
-  T acc[kV];
-  conv_tile<T, RMAX>(tile, g.R, (const T*)d.taps_t, g.wave, g.lane, acc);
-  double part[1] = {0.0};
-  const int gx = g.x0 + g.lane;
-#pragma unroll
-  for (int v = 0; v < kV; ++v) {
-    const int gy = g.y0 + g.wave * kV + v;
-    if (gy < g.h && gx < g.w) {
-      const size_t o = (size_t)gy * g.pitch + gx;
-      s[o] = acc[v];
-      p[o] = acc[v];
-      part[0] += (double)acc[v] * (double)acc[v];
-    }
-  }
-  block_sum_store<1>(part, d.partials + (size_t)L.t * kNPart + 2);
-}
-
-// Pass A of iteration k: p_new = s + beta p_old (on tile + halo), q = H p_new;
-// partial <q,q> in slot 0.
-template <typename T, int RMAX>
-__global__ __launch_bounds__(256) void k_cg_a(LaunchList ll, const JobDesc* __restrict__ descs) {
-  __shared__ T tile[(kTH + 2 * RMAX) * (kTW + 2 * RMAX)];
-  const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
-  const JobDesc& d = descs[L.d];
-  const SolverState* st = d.st;
-  if (__builtin_amdgcn_readfirstlane(st->done)) return;
-  const TileGeo g = tile_geo(d, L.t);
-  const int par = uni(st->par);
-  const double beta = st->beta;
-  const T* __restrict__ s = (const T*)d.s;
-  const T* __restrict__ po = (const T*)d.p[par];
-  T* __restrict__ pn = (T*)d.p[par ^ 1];
-  T* __restrict__ q = (T*)d.q[0];
-  load_tile<T, RMAX>(tile, g, [&](size_t o, bool interior) {
-    const T v = to_t<T>((double)s[o] + beta * (double)po[o]);
-    if (interior) pn[o] = v;
-    return v;
-  });
-  __syncthreads();
-  T acc[kV];
-  conv_tile<T, RMAX>(tile, g.R, (const T*)d.taps, g.wave, g.lane, acc);
-  double part[1] = {0.0};
-  const int gx = g.x0 + g.lane;
-#pragma unroll
-  for (int v = 0; v < kV; ++v) {
-    const int gy = g.y0 + g.wave * kV + v;
-    if (gy < g.h && gx < g.w) {
-      const size_t o = (size_t)gy * g.pitch + gx;
-      q[o] = acc[v];
-      part[0] += (double)acc[v] * (double)acc[v];
-    }
-  }
-  block_sum_store<1>(part, d.partials + (size_t)L.t * kNPart + 0);
-}
-
-// Pass B of iteration k: r_new = r - alpha q (tile + halo), s = H^T r_new,
-// u += alpha p_new; partials <r,r> (slot 1) and <s,s> (slot 2).
-template <typename T, int RMAX>
-__global__ __launch_bounds__(256) void k_cg_b(LaunchList ll, const JobDesc* __restrict__ descs) {
-  __shared__ T tile[(kTH + 2 * RMAX) * (kTW + 2 * RMAX)];
-  const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
-  const JobDesc& d = descs[L.d];
-  const SolverState* st = d.st;
-  if (__builtin_amdgcn_readfirstlane(st->done)) return;
-  const TileGeo g = tile_geo(d, L.t);
-  const int par = uni(st->par);
-  const double alpha = st->alpha;
-  const T* __restrict__ ro = (const T*)d.r[par];
-  T* __restrict__ rn = (T*)d.r[par ^ 1];
-  const T* __restrict__ q = (const T*)d.q[0];
-  const T* __restrict__ pn = (const T*)d.p[par ^ 1];
-  T* __restrict__ u = (T*)d.u;
-  T* __restrict__ s = (T*)d.s;
-  double part[2] = {0.0, 0.0};
-  load_tile<T, RMAX>(tile, g, [&](size_t o, bool interior) {
-    const T v = to_t<T>((double)ro[o] - alpha * (double)q[o]);
-    if (interior) {
-      rn[o] = v;
-      part[0] += (double)v * (double)v;
-    }
-    return v;
-  });
-  __syncthreads();
-  T acc[kV];
-  conv_tile<T, RMAX>(tile, g.R, (const T*)d.taps_t, g.wave, g.lane, acc);
-  const int gx = g.x0 + g.lane;
-#pragma unroll
-  for (int v = 0; v < kV; ++v) {
-    const int gy = g.y0 + g.wave * kV + v;
-    if (gy < g.h && gx < g.w) {
-      const size_t o = (size_t)gy * g.pitch + gx;
-      s[o] = acc[v];
-      part[1] += (double)acc[v] * (double)acc[v];
-      u[o] = to_t<T>((double)u[o] + alpha * (double)pn[o]);
-    }
-  }
-  block_sum_store<2>(part, d.partials + (size_t)L.t * kNPart + 1);
-}
-
-// ---------------------------------------------------------------------------
-// MR kernel (minimal-residual iteration, one operator product per step)
-// ---------------------------------------------------------------------------
-// If a step alpha is pending: r_new = r - alpha q and u += alpha r; then
-// q_new = H r_new.  Partials <r_new,q_new> (0), <r_new,r_new> (1), <q,q> (2).
-template <typename T, int RMAX>
-__global__ __launch_bounds__(256) void k_mr_pass(LaunchList ll, const JobDesc* __restrict__ descs) {
-  __shared__ T tile[(kTH + 2 * RMAX) * (kTW + 2 * RMAX)];
-  constexpr int LW = kTW + 2 * RMAX;
-  const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
-  const JobDesc& d = descs[L.d];
-  const SolverState* st = d.st;
-  if (__builtin_amdgcn_readfirstlane(st->done)) return;
-  const TileGeo g = tile_geo(d, L.t);
-  const int par = uni(st->par);
-  const bool pending = uni(st->pending) != 0;
-  const double alpha = st->alpha;
-  const T* __restrict__ ro = (const T*)d.r[par];
-  const T* __restrict__ qo = (const T*)d.q[par];
-  T* __restrict__ rn = (T*)d.r[par ^ 1];
-  T* __restrict__ qn = (T*)d.q[par ^ 1];
-  T* __restrict__ u = (T*)d.u;
-  double part[3] = {0.0, 0.0, 0.0};
-  load_tile<T, RMAX>(tile, g, [&](size_t o, bool interior) {
-    const T r0 = ro[o];
-    const T v = pending ? to_t<T>((double)r0 - alpha * (double)qo[o]) : r0;
-    if (interior) {
-      rn[o] = v;
-      part[1] += (double)v * (double)v;
-      if (pending) u[o] = to_t<T>((double)u[o] + alpha * (double)r0);
-    }
-    return v;
-  });
-  __syncthreads();
-  T acc[kV];
-  conv_tile<T, RMAX>(tile, g.R, (const T*)d.taps, g.wave, g.lane, acc);
-  const int gx = g.x0 + g.lane;
-#pragma unroll
-  for (int v = 0; v < kV; ++v) {
-    const int gy = g.y0 + g.wave * kV + v;
-    if (gy < g.h && gx < g.w) {
-      const size_t o = (size_t)gy * g.pitch + gx;
-      qn[o] = acc[v];
-      const T rc = tile[(g.wave * kV + v + g.R) * LW + g.lane + g.R];
-      part[0] += (double)rc * (double)acc[v];
-      part[2] += (double)acc[v] * (double)acc[v];
-    }
-  }
-  block_sum_store<3>(part, d.partials + (size_t)L.t * kNPart + 0);
-}
-
-// ---------------------------------------------------------------------------
-// Finalize kernels: one block per job, scalar recurrences in FP64.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ bool finite_d(double x) { return isfinite(x); }
 
 // Stopping tests of the smoother, in the order: non-finite, discrepancy
 // principle ||r|| <= c delta (RMS norm), iteration cap m_l, convergence guard.
@@ -633,9 +297,10 @@ __device__ __forceinline__ void linear_point(const XArgs& x, int I, int J) {
 // a0 + a1 s + a2 t on the 3x3 window with w = exp(-((u_c - u_n)/h)^2)
 // (exactly 0 beyond (./h)^2 > 30, out-of-image neighbours dropped), output
 // a0.  The fit is centred on the pixel value and on the weighted centroid,
-// and the 2x2 system for (a1, a2) is solved by a plane rotation that
-// diagonalises it, dropping eigenvalues below 1e-12 of the largest; the fitted
-// centre value stays accurate for near-collinear weight patterns.
+// and the 2x2 system for (a1, a2) is solved through its eigen-decomposition
+// (one Jacobi rotation, no trigonometric calls), dropping eigenvalues below
+// 1e-12 of the largest; the fitted centre value stays accurate for
+// near-collinear weight patterns.
 template <typename T>
 __device__ __forceinline__ void smooth_point(const XArgs& x, int i, int j) {
   const T* u = (const T*)x.s0;
@@ -671,15 +336,22 @@ __device__ __forceinline__ void smooth_point(const XArgs& x, int i, int j) {
   const double sb = m01 / m00, tb = m02 / m00, vb = b0 / m00;
   const double S11 = m11 - m01 * sb, S12 = m12 - m01 * tb, S22 = m22 - m02 * tb;
   const double c1 = b1 - m01 * vb, c2 = b2 - m02 * vb;
-  const double th = 0.5 * atan2(2.0 * S12, S11 - S22);
-  double sn, cs;
-  sincos(th, &sn, &cs);
-  const double l1 = S11 * cs * cs + 2.0 * S12 * cs * sn + S22 * sn * sn;
-  const double l2 = S11 * sn * sn - 2.0 * S12 * cs * sn + S22 * cs * cs;
+  // symmetric 2x2 Schur decomposition by one Jacobi rotation (t = tan of the
+  // rotation angle from tau = (S22 - S11) / (2 S12), the smaller root)
+  double cs = 1.0, sn = 0.0, l1 = S11, l2 = S22;
+  if (S12 != 0.0) {
+    const double tau = (S22 - S11) / (2.0 * S12);
+    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+    cs = 1.0 / sqrt(1.0 + t * t);
+    sn = t * cs;
+    l1 = S11 - t * S12;
+    l2 = S22 + t * S12;
+  }
+  // eigenvectors (cs, -sn) for l1 and (sn, cs) for l2
   const double lmax = fmax(fabs(l1), fabs(l2));
   double corr = 0.0;
-  if (l1 > 1e-12 * lmax && l1 > 0.0) corr += (sb * cs + tb * sn) * (c1 * cs + c2 * sn) / l1;
-  if (l2 > 1e-12 * lmax && l2 > 0.0) corr += (tb * cs - sb * sn) * (c2 * cs - c1 * sn) / l2;
+  if (l1 > 1e-12 * lmax && l1 > 0.0) corr += (sb * cs - tb * sn) * (c1 * cs - c2 * sn) / l1;
+  if (l2 > 1e-12 * lmax && l2 > 0.0) corr += (sb * sn + tb * cs) * (c1 * sn + c2 * cs) / l2;
   ((T*)x.dst)[(size_t)i * x.pd + j] = to_t<T>(uc + (vb - corr));
 }
 
@@ -828,35 +500,6 @@ __global__ __launch_bounds__(256) void k_out_copy(LaunchList ll, const JobDesc* 
   }
 }
 
-// ---------------------------------------------------------------------------
-// Operator-form convolution on one dense image (y = H x with given taps).
-// ---------------------------------------------------------------------------
-template <typename T, int RMAX>
-__global__ __launch_bounds__(256) void k_op_conv(const T* __restrict__ x, T* __restrict__ y, int H, int W,
-                                                 const T* __restrict__ taps, int R) {
-  __shared__ T tile[(kTH + 2 * RMAX) * (kTW + 2 * RMAX)];
-  const int tiles_x = (W + kTW - 1) / kTW;
-  TileGeo g;
-  g.R = R;
-  g.h = H;
-  g.w = W;
-  g.pitch = W;
-  g.y0 = (blockIdx.x / tiles_x) * kTH;
-  g.x0 = (blockIdx.x % tiles_x) * kTW;
-  g.wave = uni(threadIdx.x >> 6);
-  g.lane = threadIdx.x & 63;
-  load_tile<T, RMAX>(tile, g, [&](size_t o, bool) { return x[o]; });
-  __syncthreads();
-  T acc[kV];
-  conv_tile<T, RMAX>(tile, R, taps, g.wave, g.lane, acc);
-  const int gx = g.x0 + g.lane;
-#pragma unroll
-  for (int v = 0; v < kV; ++v) {
-    const int gy = g.y0 + g.wave * kV + v;
-    if (gy < H && gx < W) y[(size_t)gy * W + gx] = acc[v];
-  }
-}
-
 template <typename T>
 __global__ __launch_bounds__(256) void k_op_restrict(const T* __restrict__ gf, int Hf, int Wf, T* __restrict__ gc,
                                                      int Hc, int Wc) {
@@ -869,6 +512,17 @@ __global__ __launch_bounds__(256) void k_op_restrict(const T* __restrict__ gf, i
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
+hipError_t sm_f32_sep(Stage st, int R, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
+hipError_t sm_f32_sym(Stage st, bool disk, int R, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
+hipError_t sm_f64_sep(Stage st, int R, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
+hipError_t sm_f64_sym(Stage st, bool disk, int R, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
+hipError_t sm_gen(Stage st, bool f64, int rclass, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
+hipError_t opc_f32_sep(const void* x, void* y, int H, int W, const void* taps, int R, hipStream_t s);
+hipError_t opc_f32_sym(bool disk, const void* x, void* y, int H, int W, const void* taps, int R, hipStream_t s);
+hipError_t opc_f64_sep(const void* x, void* y, int H, int W, const void* taps, int R, hipStream_t s);
+hipError_t opc_f64_sym(bool disk, const void* x, void* y, int H, int W, const void* taps, int R, hipStream_t s);
+hipError_t opc_gen(bool f64, const void* x, void* y, int H, int W, const void* taps, int R, hipStream_t s);
+
 int rmax_class_for(int r) { return r <= 3 ? 3 : (r <= 6 ? 6 : 12); }
 
 static int tiles2(int h, int w, int th, int tw) { return ((h + th - 1) / th) * ((w + tw - 1) / tw); }
@@ -893,24 +547,22 @@ int blocks_for_stage(Stage st, const JobDesc& d) {
   }
 }
 
-template <typename T, int RMAX>
-static hipError_t launch_smoother(Stage st, const LaunchList& ll, const JobDesc* descs, hipStream_t s) {
-  const dim3 grid(ll.total), block(256);
-  switch (st) {
-    case kCgInit1:
-    case kMrInit: hipLaunchKernelGGL((k_init1<T, RMAX>), grid, block, 0, s, ll, descs); break;
-    case kCgInit2: hipLaunchKernelGGL((k_cg_init2<T, RMAX>), grid, block, 0, s, ll, descs); break;
-    case kCgA: hipLaunchKernelGGL((k_cg_a<T, RMAX>), grid, block, 0, s, ll, descs); break;
-    case kCgB: hipLaunchKernelGGL((k_cg_b<T, RMAX>), grid, block, 0, s, ll, descs); break;
-    case kMrPass: hipLaunchKernelGGL((k_mr_pass<T, RMAX>), grid, block, 0, s, ll, descs); break;
+static hipError_t launch_smoother(Stage st, bool f64, int variant, const LaunchList& ll, const JobDesc* descs,
+                                  hipStream_t s) {
+  const int kind = variant / 100, R = variant % 100;
+  switch (kind) {
+    case kConvGeneral: return sm_gen(st, f64, R, ll, descs, s);
+    case kConvSep: return f64 ? sm_f64_sep(st, R, ll, descs, s) : sm_f32_sep(st, R, ll, descs, s);
+    case kConvSymSquare:
+      return f64 ? sm_f64_sym(st, false, R, ll, descs, s) : sm_f32_sym(st, false, R, ll, descs, s);
+    case kConvSymDisk: return f64 ? sm_f64_sym(st, true, R, ll, descs, s) : sm_f32_sym(st, true, R, ll, descs, s);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t launch_typed(Stage st, int rmax_class, const LaunchList& ll, const JobDesc* descs, int src,
-                               int dst, hipStream_t s) {
+static hipError_t launch_typed(Stage st, int variant, const LaunchList& ll, const JobDesc* descs, int src, int dst,
+                               hipStream_t s) {
   const dim3 grid(ll.total), block(256);
   switch (st) {
     case kRestrict: hipLaunchKernelGGL(k_restrict<T>, grid, block, 0, s, ll, descs); return hipGetLastError();
@@ -932,12 +584,10 @@ static hipError_t launch_typed(Stage st, int rmax_class, const LaunchList& ll, c
       return hipGetLastError();
     default: break;
   }
-  if (rmax_class <= 3) return launch_smoother<T, 3>(st, ll, descs, s);
-  if (rmax_class <= 6) return launch_smoother<T, 6>(st, ll, descs, s);
-  return launch_smoother<T, 12>(st, ll, descs, s);
+  return launch_smoother(st, sizeof(T) == 8, variant, ll, descs, s);
 }
 
-hipError_t launch_stage(Stage st, bool f64, int rmax_class, const LaunchList& ll, const JobDesc* descs, int src,
+hipError_t launch_stage(Stage st, bool f64, int variant, const LaunchList& ll, const JobDesc* descs, int src,
                         int dst, hipStream_t s) {
   if (ll.n <= 0) return hipSuccess;
   const dim3 block(256);
@@ -949,26 +599,21 @@ hipError_t launch_stage(Stage st, bool f64, int rmax_class, const LaunchList& ll
     case kMrFin: hipLaunchKernelGGL(k_mr_fin, dim3(ll.n), block, 0, s, ll, descs); return hipGetLastError();
     default: break;
   }
-  return f64 ? launch_typed<double>(st, rmax_class, ll, descs, src, dst, s)
-             : launch_typed<float>(st, rmax_class, ll, descs, src, dst, s);
+  return f64 ? launch_typed<double>(st, variant, ll, descs, src, dst, s)
+             : launch_typed<float>(st, variant, ll, descs, src, dst, s);
 }
 
-template <typename T>
-static hipError_t op_conv_t(const void* x, void* y, int H, int W, const void* taps, int r, hipStream_t s) {
-  const int blocks = tiles2(H, W, kTH, kTW);
-  const int rc = rmax_class_for(r);
-  if (rc <= 3)
-    hipLaunchKernelGGL((k_op_conv<T, 3>), dim3(blocks), dim3(256), 0, s, (const T*)x, (T*)y, H, W, (const T*)taps, r);
-  else if (rc <= 6)
-    hipLaunchKernelGGL((k_op_conv<T, 6>), dim3(blocks), dim3(256), 0, s, (const T*)x, (T*)y, H, W, (const T*)taps, r);
-  else
-    hipLaunchKernelGGL((k_op_conv<T, 12>), dim3(blocks), dim3(256), 0, s, (const T*)x, (T*)y, H, W, (const T*)taps,
-                       r);
-  return hipGetLastError();
-}
-
-hipError_t op_conv(const void* x, void* y, int H, int W, const void* taps, int r, bool f64, hipStream_t s) {
-  return f64 ? op_conv_t<double>(x, y, H, W, taps, r, s) : op_conv_t<float>(x, y, H, W, taps, r, s);
+hipError_t op_conv(const void* x, void* y, int H, int W, const void* taps, int variant, bool f64, hipStream_t s) {
+  const int kind = variant / 100, R = variant % 100;
+  switch (kind) {
+    case kConvGeneral: return opc_gen(f64, x, y, H, W, taps, R, s);
+    case kConvSep: return f64 ? opc_f64_sep(x, y, H, W, taps, R, s) : opc_f32_sep(x, y, H, W, taps, R, s);
+    case kConvSymSquare:
+      return f64 ? opc_f64_sym(false, x, y, H, W, taps, R, s) : opc_f32_sym(false, x, y, H, W, taps, R, s);
+    case kConvSymDisk:
+      return f64 ? opc_f64_sym(true, x, y, H, W, taps, R, s) : opc_f32_sym(true, x, y, H, W, taps, R, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t op_restrict(const void* gf, int Hf, int Wf, void* gc, bool f64, hipStream_t s) {

@@ -48,8 +48,76 @@ constexpr size_t kTapsSlotBytes = 32 << 10;  // pinned staging of one job's PSF 
 // ---------------------------------------------------------------------------
 struct LevelPlan {
   int h = 0, w = 0, pitch = 0, rad = 0, cap = 0, ntiles = 0, tiles_x = 0;
-  std::vector<double> psf;  // (2 rad + 1)^2, FP64
+  int variant = 0;                    // blur-operator kernel family (ConvKind * 100 + R)
+  std::vector<double> psf;            // (2 rad + 1)^2, FP64
+  std::vector<double> taps, taps_t;   // the variant's tap layout for H and H^T
 };
+
+// Largest b with a^2 + b^2 <= R^2 (disk support), or R (square support); the
+// same layout rule as the symmetric device policy.
+static int sym_span_h(int R, bool disk, int a) {
+  if (!disk) return R;
+  int b = 0;
+  while ((b + 1) * (b + 1) + a * a <= R * R) ++b;
+  return b;
+}
+
+// Pick the blur-operator kernel family for one level's PSF and lay out its
+// taps (FP64; converted to the element type at upload):
+//   rank one (to 8 ulp)                 -> separable: row(-R..R), col(-R..R)
+//   symmetric in both axes, disk support -> row-filter kernel on the quadrant
+//   symmetric in both axes               -> same with square support (R <= 6)
+//   otherwise                            -> general (all taps)
+static void choose_variant(LevelPlan& lp) {
+  const int R = lp.rad, n = 2 * R + 1;
+  const std::vector<double>& P = lp.psf;
+  auto at = [&](int a, int b) { return P[(a + R) * n + (b + R)]; };
+  int a0 = 0, b0 = 0;
+  double mx = 0.0;
+  for (int a = -R; a <= R; ++a)
+    for (int b = -R; b <= R; ++b)
+      if (std::fabs(at(a, b)) > mx) {
+        mx = std::fabs(at(a, b));
+        a0 = a;
+        b0 = b;
+      }
+  if (mx > 0.0) {
+    std::vector<double> col(n), row(n);
+    for (int k = -R; k <= R; ++k) {
+      col[k + R] = at(k, b0);
+      row[k + R] = at(a0, k) / at(a0, b0);
+    }
+    double err = 0.0;
+    for (int a = -R; a <= R; ++a)
+      for (int b = -R; b <= R; ++b) err = std::max(err, std::fabs(at(a, b) - col[a + R] * row[b + R]));
+    if (err <= 8.0 * 2.220446049250313e-16 * mx) {
+      lp.variant = kConvSep * 100 + R;
+      lp.taps.assign(row.begin(), row.end());
+      lp.taps.insert(lp.taps.end(), col.begin(), col.end());
+      lp.taps_t.assign(row.rbegin(), row.rend());
+      lp.taps_t.insert(lp.taps_t.end(), col.rbegin(), col.rend());
+      return;
+    }
+  }
+  bool sym = true, disk = true;
+  for (int a = -R; a <= R; ++a)
+    for (int b = -R; b <= R; ++b) {
+      if (at(a, b) != at(-a, b) || at(a, b) != at(a, -b)) sym = false;
+      if (a * a + b * b > R * R && at(a, b) != 0.0) disk = false;
+    }
+  if (sym && ((disk && R <= 8) || R <= 6)) {
+    const bool use_disk = disk && R <= 8;
+    lp.variant = (use_disk ? kConvSymDisk : kConvSymSquare) * 100 + R;
+    lp.taps.clear();
+    for (int a = 0; a <= R; ++a)
+      for (int b = 0; b <= sym_span_h(R, use_disk, a); ++b) lp.taps.push_back(at(a, b));
+    lp.taps_t = lp.taps;  // H^T = H for a PSF symmetric in both axes
+    return;
+  }
+  lp.variant = kConvGeneral * 100 + rmax_class_for(R);
+  lp.taps = P;
+  lp.taps_t.assign(P.rbegin(), P.rend());
+}
 
 struct Plan {
   int H = 0, W = 0, L = 0;
@@ -200,9 +268,9 @@ static int build_plan(int H, int W, const double* psf, int r, int L, const int* 
     return o;
   };
   for (int l = 0; l < L; ++l) {
-    const size_t nt = (size_t)(2 * P.lv[l].rad + 1) * (2 * P.lv[l].rad + 1);
-    P.off_taps[l] = take(nt * P.esz);
-    P.off_tapst[l] = take(nt * P.esz);
+    choose_variant(P.lv[l]);
+    P.off_taps[l] = take(P.lv[l].taps.size() * P.esz);
+    P.off_tapst[l] = take(P.lv[l].taps_t.size() * P.esz);
   }
   P.taps_bytes = off;
   if (P.taps_bytes > kTapsSlotBytes) return fail(EECMG_EINVAL, "PSF pyramid too large");
@@ -468,18 +536,15 @@ class Engine {
     char* tb = h_taps_ + (size_t)slot * kTapsSlotBytes;
     for (int l = 0; l < P.L; ++l) {
       const LevelPlan& lp = P.lv[l];
-      const int n = 2 * lp.rad + 1;
-      for (int a = 0; a < n; ++a)
-        for (int b = 0; b < n; ++b) {
-          const double v = lp.psf[a * n + b], vt = lp.psf[(n - 1 - a) * n + (n - 1 - b)];
-          if (P.f64) {
-            ((double*)(tb + P.off_taps[l]))[a * n + b] = v;
-            ((double*)(tb + P.off_tapst[l]))[a * n + b] = vt;
-          } else {
-            ((float*)(tb + P.off_taps[l]))[a * n + b] = (float)v;
-            ((float*)(tb + P.off_tapst[l]))[a * n + b] = (float)vt;
-          }
+      for (size_t k = 0; k < lp.taps.size(); ++k) {
+        if (P.f64) {
+          ((double*)(tb + P.off_taps[l]))[k] = lp.taps[k];
+          ((double*)(tb + P.off_tapst[l]))[k] = lp.taps_t[k];
+        } else {
+          ((float*)(tb + P.off_taps[l]))[k] = (float)lp.taps[k];
+          ((float*)(tb + P.off_tapst[l]))[k] = (float)lp.taps_t[k];
         }
+      }
     }
     chk(hipMemcpyAsync(mem, tb, P.taps_bytes, hipMemcpyHostToDevice, stream_));
     if (P.own_gin) j->g_in_dev = mem + P.off_gin;
@@ -720,7 +785,7 @@ class Engine {
 
   // Launch `stage` for jobs at the given level (-1: each job's current level),
   // splitting by nothing: caller groups jobs of one precision / variant.
-  void launch_group(Stage st, const std::vector<Job*>& jobs, int level, bool f64, int rmax_class, int src, int dst) {
+  void launch_group(Stage st, const std::vector<Job*>& jobs, int level, bool f64, int variant, int src, int dst) {
     LaunchList ll;
     ll.n = 0;
     ll.total = 0;
@@ -747,17 +812,17 @@ class Engine {
       std::lock_guard<std::mutex> g(pr.mu);
       hipEvent_t a = pr.ev(), b = pr.ev();
       chk(hipEventRecord(a, stream_));
-      chk(launch_stage(st, f64, rmax_class, ll, d_desc_, src, dst, stream_));
+      chk(launch_stage(st, f64, variant, ll, d_desc_, src, dst, stream_));
       chk(hipEventRecord(b, stream_));
       pr.pending.push_back({(int)st, a, b, px});
       return;
     }
-    chk(launch_stage(st, f64, rmax_class, ll, d_desc_, src, dst, stream_));
+    chk(launch_stage(st, f64, variant, ll, d_desc_, src, dst, stream_));
   }
 
   static int variant_key(const Job* j) {
     const int l = j->cur_level();
-    return (j->plan.f64 ? 1000 : 0) + rmax_class_for(j->plan.lv[l].rad);
+    return (j->plan.f64 ? 100000 : 0) + j->plan.lv[l].variant;
   }
 
   void issue_transfers(const std::vector<std::pair<Job*, int>>& xs) {
@@ -789,8 +854,8 @@ class Engine {
     std::map<std::pair<int, int>, std::vector<Job*>> groups;  // (smoother, variant)
     for (Job* j : js) groups[{j->plan.prm.smoother, variant_key(j)}].push_back(j);
     for (auto& kv : groups) {
-      const bool f64 = kv.first.second >= 1000;
-      const int rc = kv.first.second % 1000;
+      const bool f64 = kv.first.second >= 100000;
+      const int rc = kv.first.second % 100000;
       if (kv.first.first == EECMG_SMOOTHER_CGLS) {
         launch_group(kCgInit1, kv.second, -1, f64, rc, -1, -1);
         launch_group(kCgInit2, kv.second, -1, f64, rc, -1, -1);
@@ -810,8 +875,8 @@ class Engine {
       for (auto& x : its)
         if (x.second > it) groups[{x.first->plan.prm.smoother, variant_key(x.first)}].push_back(x.first);
       for (auto& kv : groups) {
-        const bool f64 = kv.first.second >= 1000;
-        const int rc = kv.first.second % 1000;
+        const bool f64 = kv.first.second >= 100000;
+        const int rc = kv.first.second % 100000;
         if (kv.first.first == EECMG_SMOOTHER_CGLS) {
           launch_group(kCgA, kv.second, -1, f64, rc, -1, -1);
           launch_group(kCgFinA, kv.second, -1, f64, rc, -1, -1);
@@ -1179,12 +1244,15 @@ int eecmg_restore_batch_dev(int n_images, const void* const* g_delta_dev, const 
 }
 
 // ------------------------------------------------------------------ operators
-static int op_taps(const double* psf, int r, bool f64, bool flip, void** d_taps) {
+static int op_taps(const double* psf, int r, bool f64, bool flip, void** d_taps, int* variant) {
   const int n = 2 * r + 1;
-  std::vector<double> t((size_t)n * n);
-  for (int a = 0; a < n; ++a)
-    for (int b = 0; b < n; ++b) t[a * n + b] = flip ? psf[(n - 1 - a) * n + (n - 1 - b)] : psf[a * n + b];
-  const size_t bytes = (size_t)n * n * (f64 ? 8 : 4);
+  LevelPlan lp;
+  lp.rad = r;
+  lp.psf.assign(psf, psf + (size_t)n * n);
+  choose_variant(lp);
+  *variant = lp.variant;
+  const std::vector<double>& t = flip ? lp.taps_t : lp.taps;
+  const size_t bytes = t.size() * (f64 ? 8 : 4);
   EECMG_HIP(hipMalloc(d_taps, bytes));
   if (f64) {
     EECMG_HIP(hipMemcpy(*d_taps, t.data(), bytes, hipMemcpyHostToDevice));
@@ -1211,9 +1279,10 @@ int eecmg_op_conv_dev(const void* x_dev, void* y_dev, int H, int W, const double
   if ((rc = check_dev_ptr(x_dev, "x_dev")) || (rc = check_dev_ptr(y_dev, "y_dev"))) return rc;
   const bool f64 = precision == EECMG_FP64;
   void* taps = nullptr;
-  rc = op_taps(psf, psf_radius, f64, transpose != 0, &taps);
+  int variant = 0;
+  rc = op_taps(psf, psf_radius, f64, transpose != 0, &taps, &variant);
   if (rc) return rc;
-  hipError_t e = op_conv(x_dev, y_dev, H, W, taps, psf_radius, f64, (hipStream_t)hip_stream);
+  hipError_t e = op_conv(x_dev, y_dev, H, W, taps, variant, f64, (hipStream_t)hip_stream);
   if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)hip_stream);
   (void)hipFree(taps);
   if (e != hipSuccess) return fail(EECMG_EDEVICE, hipGetErrorString(e));

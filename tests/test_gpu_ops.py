@@ -35,13 +35,36 @@ def _close(got, ref, prec, what=""):
     assert err <= TOL[prec], f"{what}: max rel err {err:.3e}"
 
 
+def _psf(kind, r, rng):
+    """PSFs that select each blur-operator kernel family."""
+    if kind == "general":  # no symmetry
+        return rng.uniform(-0.2, 1.0, size=(2 * r + 1, 2 * r + 1))
+    if kind == "separable":  # rank one (Gaussian)
+        return synth.gaussian_psf(max(r, 1) / 2.5, r)
+    if kind == "disk":  # symmetric in both axes, disk support
+        return synth.disk_psf(r)
+    # symmetric in both axes, full square support
+    q = rng.uniform(0.0, 1.0, size=(r + 1, r + 1))
+    full = np.zeros((2 * r + 1, 2 * r + 1))
+    for a in range(-r, r + 1):
+        for b in range(-r, r + 1):
+            full[a + r, b + r] = q[abs(a), abs(b)]
+    return full / full.sum()
+
+
+CONV_CASES = [("general", 37, 70, 0), ("general", 64, 64, 1), ("general", 97, 130, 3), ("general", 33, 200, 6),
+              ("general", 130, 65, 7), ("general", 70, 70, 12), ("general", 5, 3, 2), ("general", 1, 1, 4),
+              ("separable", 37, 70, 0), ("separable", 97, 130, 4), ("separable", 130, 200, 7),
+              ("separable", 70, 33, 12), ("disk", 65, 129, 1), ("disk", 97, 130, 3), ("disk", 200, 130, 6),
+              ("disk", 33, 70, 8), ("symsq", 97, 130, 2), ("symsq", 64, 200, 6), ("symsq", 3, 5, 1)]
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("H,W,r", [(37, 70, 0), (64, 64, 1), (97, 130, 3), (33, 200, 6), (130, 65, 7), (70, 70, 12),
-                                   (5, 3, 2), (1, 1, 4)])
+@pytest.mark.parametrize("kind,H,W,r", CONV_CASES)
 @pytest.mark.parametrize("transpose", [False, True])
-def test_conv_parity(torch_cuda, prec, H, W, r, transpose):
+def test_conv_parity(torch_cuda, prec, kind, H, W, r, transpose):
     rng = np.random.Generator(np.random.PCG64(H * 1000 + W * 10 + r))
-    psf = rng.uniform(-0.2, 1.0, size=(2 * r + 1, 2 * r + 1))
+    psf = _psf(kind, r, rng)
     x = rng.uniform(0, 255, size=(H, W)).astype(_dt(prec)).astype(np.float64)
     psf_used = psf.astype(_dt(prec)).astype(np.float64)
     y = eecmg.conv_dev(_dev(torch_cuda, x, prec), psf, transpose=transpose, precision=prec)
@@ -49,9 +72,9 @@ def test_conv_parity(torch_cuda, prec, H, W, r, transpose):
     # elementwise bound of a recursive/FMA sum of n terms: n u sum |w x|
     unit = 2.0 ** -53 if prec == "f64" else 2.0 ** -24
     n = (2 * r + 1) ** 2
-    bound = (n + 1) * unit * oracle.conv(np.abs(x), np.abs(psf_used), transpose=transpose) + 1e-300
+    bound = (n + 2) * unit * oracle.conv(np.abs(x), np.abs(psf_used), transpose=transpose) + 1e-300
     err = np.abs(y.cpu().numpy().astype(np.float64) - ref)
-    assert np.all(err <= bound), f"conv {H}x{W} r={r} T={transpose}: worst ratio {np.max(err / bound):.3f}"
+    assert np.all(err <= bound), f"conv {kind} {H}x{W} r={r} T={transpose}: worst ratio {np.max(err / bound):.3f}"
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
