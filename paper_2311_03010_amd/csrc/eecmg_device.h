@@ -132,43 +132,64 @@ struct ConvGeneral {
   }
 };
 
+// Sliding-column scheme shared by the separable and symmetric policies.  The
+// lane walks down its column one LDS row t at a time; row t feeds the outputs
+// v = t - R + a (a = R .. -R), so output v receives its first contribution at
+// t = v and is complete after t = v + 2R.  Exactly NW = 2R + 1 outputs are
+// pending at any time, so they live in a circular register buffer indexed by
+// v mod NW.  The row loop runs in groups of NW rows with the group body
+// unrolled: every register index is then a compile-time constant (no dynamic
+// VGPR indexing) whatever the tile height.  Rows past the tile only feed
+// outputs v >= TH, which are never emitted; the LDS tile is padded to whole
+// groups so those reads stay inside it.
+template <int R>
+struct Slide {
+  static constexpr int NW = 2 * R + 1;
+  static constexpr int LH = kTH + 2 * R;
+  static constexpr int NG = (LH + NW - 1) / NW;
+  static constexpr int LH_PAD = NG * NW;
+  static constexpr int slot(int k, int a) { return ((k - R + a) % NW + NW) % NW; }
+};
+
 // Rank-one PSF psf(a,b) = col(a) row(b) (the Gaussian of Section 5 and its
-// coarse levels).  One wave per 64 x 32 tile; the lane slides down its column:
-// for each LDS row it forms the horizontal filter h = sum_b row(b) x(., j-b)
-// once and adds col(a) h to the (at most 2R+1) pending outputs it feeds.
+// coarse levels).  For each LDS row the lane forms the horizontal filter
+// h = sum_b row(b) x(., j-b) once and adds col(a) h to the pending outputs.
 // Taps: row(-R..R) followed by col(-R..R).
 template <typename T, int R>
 struct ConvSep {
-  static constexpr int NT = 64, TW = kTW, TH = kTH, LW = kTW + 2 * R, LH = kTH + 2 * R;
+  using S = Slide<R>;
+  static constexpr int NT = 64, TW = kTW, TH = kTH, LW = kTW + 2 * R, LH = S::LH_PAD;
   static constexpr bool kRuntimeR = false;
   template <typename Emit>
   __device__ static __forceinline__ void conv(const T* __restrict__ tile, const T* __restrict__ taps, int, int,
                                               int lane, Emit emit) {
-    T rw[2 * R + 1], cl[2 * R + 1];
+    constexpr int NW = S::NW;
+    T rw[NW], cl[NW];
 #pragma unroll
-    for (int k = 0; k < 2 * R + 1; ++k) {
+    for (int k = 0; k < NW; ++k) {
       rw[k] = taps[k];
-      cl[k] = taps[2 * R + 1 + k];
+      cl[k] = taps[NW + k];
     }
-    T acc[TH];
+    T acc[NW];
+#pragma unroll 1
+    for (int gi = 0; gi < S::NG; ++gi) {
 #pragma unroll
-    for (int t = 0; t < LH; ++t) {
-      const T* __restrict__ row = tile + t * LW + lane + R;
-      T h = rw[0] * row[R];
+      for (int k = 0; k < NW; ++k) {
+        const int t = gi * NW + k;
+        const T* __restrict__ row = tile + t * LW + lane + R;
+        T h = rw[0] * row[R];
 #pragma unroll
-      for (int b = -R + 1; b <= R; ++b) h = fma(rw[b + R], row[-b], h);
+        for (int b = -R + 1; b <= R; ++b) h = fma(rw[b + R], row[-b], h);
 #pragma unroll
-      for (int a = R; a >= -R; --a) {
-        const int v = t - R + a;
-        if (v >= 0 && v < TH) {
+        for (int a = R; a >= -R; --a) {
           if (a == R)
-            acc[v] = cl[a + R] * h;
+            acc[S::slot(k, a)] = cl[a + R] * h;
           else
-            acc[v] = fma(cl[a + R], h, acc[v]);
+            acc[S::slot(k, a)] = fma(cl[a + R], h, acc[S::slot(k, a)]);
         }
+        const int vd = t - 2 * R;
+        if (vd >= 0 && vd < TH) emit(vd, acc[S::slot(k, -R)]);
       }
-      const int vd = t - 2 * R;
-      if (vd >= 0 && vd < TH) emit(vd, acc[vd]);
     }
   }
 };
@@ -197,50 +218,49 @@ constexpr int sym_ntaps(int R, bool disk) { return sym_offset(R, disk, R + 1); }
 // (b = 0..span(a)).
 template <typename T, int R, bool DISK>
 struct ConvSym {
-  static constexpr int NT = 64, TW = kTW, TH = kTH, LW = kTW + 2 * R, LH = kTH + 2 * R;
+  using S = Slide<R>;
+  static constexpr int NT = 64, TW = kTW, TH = kTH, LW = kTW + 2 * R, LH = S::LH_PAD;
   static constexpr bool kRuntimeR = false;
   static constexpr int NTAPS = sym_ntaps(R, DISK);
   template <typename Emit>
   __device__ static __forceinline__ void conv(const T* __restrict__ tile, const T* __restrict__ taps, int, int,
                                               int lane, Emit emit) {
+    constexpr int NW = S::NW;
     T wt[NTAPS];
 #pragma unroll
     for (int k = 0; k < NTAPS; ++k) wt[k] = taps[k];
-    T acc[TH];
+    T acc[NW];
+#pragma unroll 1
+    for (int gi = 0; gi < S::NG; ++gi) {
 #pragma unroll
-    for (int t = 0; t < LH; ++t) {
-      const T* __restrict__ row = tile + t * LW + lane + R;
-      const T x0 = row[0];
-      T pr[R + 1];
+      for (int k = 0; k < NW; ++k) {
+        const int t = gi * NW + k;
+        const T* __restrict__ row = tile + t * LW + lane + R;
+        const T x0 = row[0];
+        T pr[R + 1];
 #pragma unroll
-      for (int b = 1; b <= R; ++b) pr[b] = row[b] + row[-b];
-      T h[R + 1];
+        for (int b = 1; b <= R; ++b) pr[b] = row[b] + row[-b];
+        T h[R + 1];
 #pragma unroll
-      for (int a = 0; a <= R; ++a) {
-        const bool need = (t - R + a >= 0 && t - R + a < TH) || (t - R - a >= 0 && t - R - a < TH);
-        if (need) {
+        for (int a = 0; a <= R; ++a) {
           const int o = sym_offset(R, DISK, a);
-          const int span = sym_span(R, DISK, a);
           T v = wt[o] * x0;
 #pragma unroll
           for (int b = 1; b <= R; ++b)
-            if (b <= span) v = fma(wt[o + b], pr[b], v);
+            if (b <= sym_span(R, DISK, a)) v = fma(wt[o + b], pr[b], v);
           h[a] = v;
         }
-      }
 #pragma unroll
-      for (int a = R; a >= -R; --a) {
-        const int v = t - R + a;
-        if (v >= 0 && v < TH) {
+        for (int a = R; a >= -R; --a) {
           const T hv = h[a >= 0 ? a : -a];
           if (a == R)
-            acc[v] = hv;
+            acc[S::slot(k, a)] = hv;
           else
-            acc[v] = acc[v] + hv;
+            acc[S::slot(k, a)] = acc[S::slot(k, a)] + hv;
         }
+        const int vd = t - 2 * R;
+        if (vd >= 0 && vd < TH) emit(vd, acc[S::slot(k, -R)]);
       }
-      const int vd = t - 2 * R;
-      if (vd >= 0 && vd < TH) emit(vd, acc[vd]);
     }
   }
 };
@@ -274,8 +294,8 @@ __device__ __forceinline__ TileGeo tile_geo(const JobDesc& d, int t) {
 template <typename T, typename P, typename F>
 __device__ __forceinline__ void load_tile(T* __restrict__ tile, const TileGeo& g, F f) {
   const int R = P::kRuntimeR ? g.R : (P::LW - P::TW) / 2;
-  constexpr int NW = P::NT / 64;
-  for (int ly = g.wave; ly < P::TH + 2 * R; ly += NW) {
+  constexpr int NWV = P::NT / 64;
+  for (int ly = g.wave; ly < P::TH + 2 * R; ly += NWV) {
     const int gy = g.y0 - R + ly;
     const bool row_in = gy >= 0 && gy < g.h;
     const bool row_int = ly >= R && ly < R + P::TH;

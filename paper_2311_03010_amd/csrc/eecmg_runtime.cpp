@@ -68,7 +68,7 @@ static int sym_span_h(int R, bool disk, int a) {
 //   symmetric in both axes, disk support -> row-filter kernel on the quadrant
 //   symmetric in both axes               -> same with square support (R <= 6)
 //   otherwise                            -> general (all taps)
-static void choose_variant(LevelPlan& lp) {
+static void choose_variant(LevelPlan& lp, bool f64) {
   const int R = lp.rad, n = 2 * R + 1;
   const std::vector<double>& P = lp.psf;
   auto at = [&](int a, int b) { return P[(a + R) * n + (b + R)]; };
@@ -105,8 +105,10 @@ static void choose_variant(LevelPlan& lp) {
       if (at(a, b) != at(-a, b) || at(a, b) != at(a, -b)) sym = false;
       if (a * a + b * b > R * R && at(a, b) != 0.0) disk = false;
     }
-  if (sym && ((disk && R <= 8) || R <= 6)) {
-    const bool use_disk = disk && R <= 8;
+  // FP64 disk kernels above R = 6 would spill registers: general kernel instead
+  const int disk_max = f64 ? 6 : 8;
+  if (sym && ((disk && R <= disk_max) || R <= 6)) {
+    const bool use_disk = disk && R <= disk_max;
     lp.variant = (use_disk ? kConvSymDisk : kConvSymSquare) * 100 + R;
     lp.taps.clear();
     for (int a = 0; a <= R; ++a)
@@ -268,7 +270,7 @@ static int build_plan(int H, int W, const double* psf, int r, int L, const int* 
     return o;
   };
   for (int l = 0; l < L; ++l) {
-    choose_variant(P.lv[l]);
+    choose_variant(P.lv[l], P.f64);
     P.off_taps[l] = take(P.lv[l].taps.size() * P.esz);
     P.off_tapst[l] = take(P.lv[l].taps_t.size() * P.esz);
   }
@@ -1249,7 +1251,7 @@ static int op_taps(const double* psf, int r, bool f64, bool flip, void** d_taps,
   LevelPlan lp;
   lp.rad = r;
   lp.psf.assign(psf, psf + (size_t)n * n);
-  choose_variant(lp);
+  choose_variant(lp, f64);
   *variant = lp.variant;
   const std::vector<double>& t = flip ? lp.taps_t : lp.taps;
   const size_t bytes = t.size() * (f64 ? 8 : 4);

@@ -1,5 +1,5 @@
-// FP64 smoother kernels: separable R = 0..12, doubly-symmetric square R = 1..6
-// and disk R = 1..8.
+// FP64 smoother kernels: separable R = 0..12, doubly-symmetric square and disk
+// support R = 1..6.
 #include "eecmg_device.h"
 
 namespace eecmg {
@@ -35,7 +35,7 @@ hipError_t sm_f64_sym(Stage st, bool disk, int R, const LaunchList& ll, const Jo
   if (disk) {
     switch (R) {
       EECMG_SYM_CASE(1, true) EECMG_SYM_CASE(2, true) EECMG_SYM_CASE(3, true) EECMG_SYM_CASE(4, true)
-      EECMG_SYM_CASE(5, true) EECMG_SYM_CASE(6, true) EECMG_SYM_CASE(7, true) EECMG_SYM_CASE(8, true)
+      EECMG_SYM_CASE(5, true) EECMG_SYM_CASE(6, true)
       default: return hipErrorInvalidValue;
     }
   }
@@ -50,7 +50,7 @@ hipError_t opc_f64_sym(bool disk, const void* x, void* y, int H, int W, const vo
   if (disk) {
     switch (R) {
       EECMG_SYM_OP(1, true) EECMG_SYM_OP(2, true) EECMG_SYM_OP(3, true) EECMG_SYM_OP(4, true)
-      EECMG_SYM_OP(5, true) EECMG_SYM_OP(6, true) EECMG_SYM_OP(7, true) EECMG_SYM_OP(8, true)
+      EECMG_SYM_OP(5, true) EECMG_SYM_OP(6, true)
       default: return hipErrorInvalidValue;
     }
   }
