@@ -54,15 +54,15 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Sum NV per-lane FP64 values over an NT-thread block in a fixed order and
-// store them (thread 0) to out[0..NV).
+// store them (thread 0) to out[i * stride], i < NV.
 template <int NT, int NV>
-__device__ __forceinline__ void block_sum_store(double (&v)[NV], double* __restrict__ out) {
+__device__ __forceinline__ void block_sum_store(double (&v)[NV], double* __restrict__ out, int stride) {
 #pragma unroll
   for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
   if constexpr (NT == 64) {
     if (threadIdx.x == 0) {
 #pragma unroll
-      for (int i = 0; i < NV; ++i) out[i] = v[i];
+      for (int i = 0; i < NV; ++i) out[i * stride] = v[i];
     }
   } else {
     constexpr int NW = NT / 64;
@@ -79,7 +79,7 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NV], double* __restr
         double s = red[0][i];
 #pragma unroll
         for (int w = 1; w < NW; ++w) s += red[w][i];
-        out[i] = s;
+        out[i * stride] = s;
       }
     }
   }
@@ -101,7 +101,7 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NV], double* __restr
 // register index is a compile-time constant) and applies every row offset.
 template <typename T, int RMAX>
 struct ConvGeneral {
-  static constexpr int NT = 256, TW = kTW, TH = kTH, LW = kTW + 2 * RMAX, LH = kTH + 2 * RMAX;
+  static constexpr int NT = 256, TW = kTW, TH = kTH, LW = kTW + 2 * RMAX, LH = kTH + 2 * RMAX, RC = RMAX;
   static constexpr bool kRuntimeR = true;
   template <typename Emit>
   __device__ static __forceinline__ void conv(const T* __restrict__ tile, const T* __restrict__ taps, int R, int wave,
@@ -158,7 +158,7 @@ struct Slide {
 template <typename T, int R>
 struct ConvSep {
   using S = Slide<R>;
-  static constexpr int NT = 64, TW = kTW, TH = kTH, LW = kTW + 2 * R, LH = S::LH_PAD;
+  static constexpr int NT = 64, TW = kTW, TH = kTH, LW = kTW + 2 * R, LH = S::LH_PAD, RC = R;
   static constexpr bool kRuntimeR = false;
   template <typename Emit>
   __device__ static __forceinline__ void conv(const T* __restrict__ tile, const T* __restrict__ taps, int, int,
@@ -219,7 +219,7 @@ constexpr int sym_ntaps(int R, bool disk) { return sym_offset(R, disk, R + 1); }
 template <typename T, int R, bool DISK>
 struct ConvSym {
   using S = Slide<R>;
-  static constexpr int NT = 64, TW = kTW, TH = kTH, LW = kTW + 2 * R, LH = S::LH_PAD;
+  static constexpr int NT = 64, TW = kTW, TH = kTH, LW = kTW + 2 * R, LH = S::LH_PAD, RC = R;
   static constexpr bool kRuntimeR = false;
   static constexpr int NTAPS = sym_ntaps(R, DISK);
   template <typename Emit>
@@ -288,26 +288,81 @@ __device__ __forceinline__ TileGeo tile_geo(const JobDesc& d, int t) {
   return g;
 }
 
-// Load tile + halo through a per-pixel functor f(offset, interior) -> T
-// (interior: the pixel belongs to this tile's output region).  Pixels
-// outside the image are zero (the operator's zero boundary condition).
-template <typename T, typename P, typename F>
-__device__ __forceinline__ void load_tile(T* __restrict__ tile, const TileGeo& g, F f) {
-  const int R = P::kRuntimeR ? g.R : (P::LW - P::TW) / 2;
-  constexpr int NWV = P::NT / 64;
-  for (int ly = g.wave; ly < P::TH + 2 * R; ly += NWV) {
-    const int gy = g.y0 - R + ly;
-    const bool row_in = gy >= 0 && gy < g.h;
-    const bool row_int = ly >= R && ly < R + P::TH;
-    for (int lx = g.lane; lx < P::TW + 2 * R; lx += 64) {
-      const int gx = g.x0 - R + lx;
-      T v = T(0);
-      if (row_in && gx >= 0 && gx < g.w) {
-        const bool interior = row_int && lx >= R && lx < R + P::TW;
-        v = f((size_t)gy * g.pitch + gx, interior);
+// Load tile + halo: for every tile element in the image, make(load(o), o,
+// interior) gives the LDS value (interior: the pixel belongs to this tile's
+// output region; make may store it or accumulate a partial); elements outside
+// the image are zero (the operator's zero boundary condition).
+// For compile-time radii the loop is fully unrolled and split in two phases:
+// every global load is issued first, from an address clamped into the image
+// (always valid), and only then are the values combined and written to LDS,
+// so a wave keeps dozens of loads in flight instead of waiting row by row.
+template <typename T, typename P, typename LoadF, typename MakeF>
+__device__ __forceinline__ void load_tile(T* __restrict__ tile, const TileGeo& g, LoadF load, MakeF make) {
+  if constexpr (P::kRuntimeR) {
+    const int R = g.R;
+    constexpr int NWV = P::NT / 64;
+    for (int ly = g.wave; ly < P::TH + 2 * R; ly += NWV) {
+      const int gy = g.y0 - R + ly;
+      const bool row_in = gy >= 0 && gy < g.h;
+      const bool row_int = ly >= R && ly < R + P::TH;
+      for (int lx = g.lane; lx < P::TW + 2 * R; lx += 64) {
+        const int gx = g.x0 - R + lx;
+        T v = T(0);
+        if (row_in && gx >= 0 && gx < g.w) {
+          const size_t o = (size_t)gy * g.pitch + gx;
+          v = make(load(o), o, row_int && lx >= R && lx < R + P::TW);
+        }
+        tile[ly * P::LW + lx] = v;
       }
-      tile[ly * P::LW + lx] = v;
     }
+  } else {
+    constexpr int R = P::RC, LWr = P::TW + 2 * R, N = LWr * (P::TH + 2 * R);
+    constexpr int IT = (N + P::NT - 1) / P::NT;
+    using V = decltype(load((size_t)0));
+    V vals[IT];
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+      const int idx = (int)threadIdx.x + k * P::NT;
+      const int ly = idx / LWr, lx = idx - ly * LWr;
+      const int gy = min(max(g.y0 - R + ly, 0), g.h - 1);
+      const int gx = min(max(g.x0 - R + lx, 0), g.w - 1);
+      vals[k] = load((size_t)gy * g.pitch + gx);
+    }
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+      const int idx = (int)threadIdx.x + k * P::NT;
+      if (k < IT - 1 || idx < N) {
+        const int ly = idx / LWr, lx = idx - ly * LWr;
+        const int gy = g.y0 - R + ly, gx = g.x0 - R + lx;
+        T v = T(0);
+        if (gy >= 0 && gy < g.h && gx >= 0 && gx < g.w) {
+          const bool interior = ly >= R && ly < R + P::TH && lx >= R && lx < R + P::TW;
+          v = make(vals[k], (size_t)gy * g.pitch + gx, interior);
+        }
+        tile[ly * P::LW + lx] = v;
+      }
+    }
+  }
+}
+
+// The tile's own output pixels (no halo), one column per lane: f(o, row) for
+// every in-image pixel, with all loads of the functor issued as one burst.
+template <typename P, typename LoadF, typename UseF>
+__device__ __forceinline__ void for_interior(const TileGeo& g, LoadF load, UseF use) {
+  constexpr int NWV = P::NT / 64, ROWS = P::TH / NWV;
+  const int gx = g.x0 + g.lane;
+  const int gxc = min(gx, g.w - 1);
+  using V = decltype(load((size_t)0));
+  V vals[ROWS];
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i) {
+    const int gy = min(g.y0 + g.wave * ROWS + i, g.h - 1);
+    vals[i] = load((size_t)gy * g.pitch + gxc);
+  }
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i) {
+    const int gy = g.y0 + g.wave * ROWS + i;
+    if (gy < g.h && gx < g.w) use(vals[i], (size_t)gy * g.pitch + gx, g.wave * ROWS + i);
   }
 }
 
@@ -320,30 +375,36 @@ __device__ __forceinline__ int pol_R(const TileGeo& g) {
 // Smoother pass kernels, templated on the element type and blur policy.
 // ---------------------------------------------------------------------------
 
+template <typename T>
+struct Two {
+  T a, b;
+};
+
 // r = g - H u0, stored in r[0]; partial <r,r> in slot 1.  (CGLS and MR)
 template <typename T, typename P>
 __global__ __launch_bounds__(P::NT) void k_init1(LaunchList ll, const JobDesc* __restrict__ descs) {
   __shared__ T tile[P::LH * P::LW];
+  __shared__ T gsh[P::TH * P::TW];
   const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
   const JobDesc& d = descs[L.d];
   const TileGeo g = tile_geo<P>(d, L.t);
   const T* __restrict__ u = (const T*)d.u;
   const T* __restrict__ gg = (const T*)d.g;
   T* __restrict__ r = (T*)d.r[0];
-  load_tile<T, P>(tile, g, [&](size_t o, bool) { return u[o]; });
+  load_tile<T, P>(tile, g, [&](size_t o) { return u[o]; }, [&](T v, size_t, bool) { return v; });
+  for_interior<P>(g, [&](size_t o) { return gg[o]; }, [&](T v, size_t, int row) { gsh[row * P::TW + g.lane] = v; });
   __syncthreads();
   double part[1] = {0.0};
   const int gx = g.x0 + g.lane;
   P::conv(tile, (const T*)d.taps, g.R, g.wave, g.lane, [&](int v, T acc) {
     const int gy = g.y0 + v;
     if (gy < g.h && gx < g.w) {
-      const size_t o = (size_t)gy * g.pitch + gx;
-      const T rv = to_t<T>((double)gg[o] - (double)acc);
-      r[o] = rv;
+      const T rv = to_t<T>((double)gsh[v * P::TW + g.lane] - (double)acc);
+      r[(size_t)gy * g.pitch + gx] = rv;
       part[0] += (double)rv * (double)rv;
     }
   });
-  block_sum_store<P::NT, 1>(part, d.partials + (size_t)L.t * kNPart + 1);
+  block_sum_store<P::NT, 1>(part, d.partials + (size_t)1 * d.pstride + L.t, d.pstride);
 }
 
 // s = H^T r, p[0] = s; partial <s,s> in slot 2.
@@ -356,7 +417,7 @@ __global__ __launch_bounds__(P::NT) void k_cg_init2(LaunchList ll, const JobDesc
   const T* __restrict__ r = (const T*)d.r[0];
   T* __restrict__ s = (T*)d.s;
   T* __restrict__ p = (T*)d.p[0];
-  load_tile<T, P>(tile, g, [&](size_t o, bool) { return r[o]; });
+  load_tile<T, P>(tile, g, [&](size_t o) { return r[o]; }, [&](T v, size_t, bool) { return v; });
   __syncthreads();
   double part[1] = {0.0};
   const int gx = g.x0 + g.lane;
@@ -369,7 +430,7 @@ __global__ __launch_bounds__(P::NT) void k_cg_init2(LaunchList ll, const JobDesc
       part[0] += (double)acc * (double)acc;
     }
   });
-  block_sum_store<P::NT, 1>(part, d.partials + (size_t)L.t * kNPart + 2);
+  block_sum_store<P::NT, 1>(part, d.partials + (size_t)2 * d.pstride + L.t, d.pstride);
 }
 
 // Pass A of iteration k: p_new = s + beta p_old (on tile + halo), q = H p_new;
@@ -388,11 +449,13 @@ __global__ __launch_bounds__(P::NT) void k_cg_a(LaunchList ll, const JobDesc* __
   const T* __restrict__ po = (const T*)d.p[par];
   T* __restrict__ pn = (T*)d.p[par ^ 1];
   T* __restrict__ q = (T*)d.q[0];
-  load_tile<T, P>(tile, g, [&](size_t o, bool interior) {
-    const T v = to_t<T>((double)s[o] + beta * (double)po[o]);
-    if (interior) pn[o] = v;
-    return v;
-  });
+  load_tile<T, P>(
+      tile, g, [&](size_t o) { return Two<T>{s[o], po[o]}; },
+      [&](Two<T> x, size_t o, bool interior) {
+        const T v = to_t<T>((double)x.a + beta * (double)x.b);
+        if (interior) pn[o] = v;
+        return v;
+      });
   __syncthreads();
   double part[1] = {0.0};
   const int gx = g.x0 + g.lane;
@@ -403,11 +466,11 @@ __global__ __launch_bounds__(P::NT) void k_cg_a(LaunchList ll, const JobDesc* __
       part[0] += (double)acc * (double)acc;
     }
   });
-  block_sum_store<P::NT, 1>(part, d.partials + (size_t)L.t * kNPart + 0);
+  block_sum_store<P::NT, 1>(part, d.partials + (size_t)0 * d.pstride + L.t, d.pstride);
 }
 
-// Pass B of iteration k: r_new = r - alpha q (tile + halo), s = H^T r_new,
-// u += alpha p_new; partials <r,r> (slot 1) and <s,s> (slot 2).
+// Pass B of iteration k: r_new = r - alpha q (tile + halo), u += alpha p_new,
+// s = H^T r_new; partials <r,r> (slot 1) and <s,s> (slot 2).
 template <typename T, typename P>
 __global__ __launch_bounds__(P::NT) void k_cg_b(LaunchList ll, const JobDesc* __restrict__ descs) {
   __shared__ T tile[P::LH * P::LW];
@@ -425,26 +488,29 @@ __global__ __launch_bounds__(P::NT) void k_cg_b(LaunchList ll, const JobDesc* __
   T* __restrict__ u = (T*)d.u;
   T* __restrict__ s = (T*)d.s;
   double part[2] = {0.0, 0.0};
-  load_tile<T, P>(tile, g, [&](size_t o, bool interior) {
-    const T v = to_t<T>((double)ro[o] - alpha * (double)q[o]);
-    if (interior) {
-      rn[o] = v;
-      part[0] += (double)v * (double)v;
-    }
-    return v;
-  });
+  load_tile<T, P>(
+      tile, g, [&](size_t o) { return Two<T>{ro[o], q[o]}; },
+      [&](Two<T> x, size_t o, bool interior) {
+        const T v = to_t<T>((double)x.a - alpha * (double)x.b);
+        if (interior) {
+          rn[o] = v;
+          part[0] += (double)v * (double)v;
+        }
+        return v;
+      });
+  for_interior<P>(
+      g, [&](size_t o) { return Two<T>{u[o], pn[o]}; },
+      [&](Two<T> x, size_t o, int) { u[o] = to_t<T>((double)x.a + alpha * (double)x.b); });
   __syncthreads();
   const int gx = g.x0 + g.lane;
   P::conv(tile, (const T*)d.taps_t, g.R, g.wave, g.lane, [&](int v, T acc) {
     const int gy = g.y0 + v;
     if (gy < g.h && gx < g.w) {
-      const size_t o = (size_t)gy * g.pitch + gx;
-      s[o] = acc;
+      s[(size_t)gy * g.pitch + gx] = acc;
       part[1] += (double)acc * (double)acc;
-      u[o] = to_t<T>((double)u[o] + alpha * (double)pn[o]);
     }
   });
-  block_sum_store<P::NT, 2>(part, d.partials + (size_t)L.t * kNPart + 1);
+  block_sum_store<P::NT, 2>(part, d.partials + (size_t)1 * d.pstride + L.t, d.pstride);
 }
 
 // MR pass: if a step alpha is pending, r_new = r - alpha q and u += alpha r;
@@ -467,16 +533,21 @@ __global__ __launch_bounds__(P::NT) void k_mr_pass(LaunchList ll, const JobDesc*
   T* __restrict__ qn = (T*)d.q[par ^ 1];
   T* __restrict__ u = (T*)d.u;
   double part[3] = {0.0, 0.0, 0.0};
-  load_tile<T, P>(tile, g, [&](size_t o, bool interior) {
-    const T r0 = ro[o];
-    const T v = pending ? to_t<T>((double)r0 - alpha * (double)qo[o]) : r0;
-    if (interior) {
-      rn[o] = v;
-      part[1] += (double)v * (double)v;
-      if (pending) u[o] = to_t<T>((double)u[o] + alpha * (double)r0);
-    }
-    return v;
-  });
+  // qo is read even before the first step (its value is then unused)
+  load_tile<T, P>(
+      tile, g, [&](size_t o) { return Two<T>{ro[o], qo[o]}; },
+      [&](Two<T> x, size_t o, bool interior) {
+        const T v = pending ? to_t<T>((double)x.a - alpha * (double)x.b) : x.a;
+        if (interior) {
+          rn[o] = v;
+          part[1] += (double)v * (double)v;
+        }
+        return v;
+      });
+  if (pending)
+    for_interior<P>(
+        g, [&](size_t o) { return Two<T>{u[o], ro[o]}; },
+        [&](Two<T> x, size_t o, int) { u[o] = to_t<T>((double)x.a + alpha * (double)x.b); });
   __syncthreads();
   const int gx = g.x0 + g.lane;
   P::conv(tile, (const T*)d.taps, g.R, g.wave, g.lane, [&](int v, T acc) {
@@ -488,7 +559,7 @@ __global__ __launch_bounds__(P::NT) void k_mr_pass(LaunchList ll, const JobDesc*
       part[2] += (double)acc * (double)acc;
     }
   });
-  block_sum_store<P::NT, 3>(part, d.partials + (size_t)L.t * kNPart + 0);
+  block_sum_store<P::NT, 3>(part, d.partials + (size_t)0 * d.pstride + L.t, d.pstride);
 }
 
 // Operator form: y = H x on one dense image with the given taps layout.
@@ -506,7 +577,7 @@ __global__ __launch_bounds__(P::NT) void k_op_conv(const T* __restrict__ x, T* _
   g.x0 = (blockIdx.x % tiles_x) * P::TW;
   g.wave = uni(threadIdx.x >> 6);
   g.lane = threadIdx.x & 63;
-  load_tile<T, P>(tile, g, [&](size_t o, bool) { return x[o]; });
+  load_tile<T, P>(tile, g, [&](size_t o) { return x[o]; }, [&](T v, size_t, bool) { return v; });
   __syncthreads();
   const int gx = g.x0 + g.lane;
   P::conv(tile, taps, R, g.wave, g.lane, [&](int v, T acc) {

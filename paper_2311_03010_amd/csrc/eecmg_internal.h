@@ -64,7 +64,10 @@ struct JobDesc {
   double cdelta, eps2;
   SolverState* st;
   LevelRecord* rec;  // kMaxLevels records of this job
-  double* partials;  // ntiles * kNPart
+  double* partials;  // kNPart components, component c of tile t at partials[c * pstride + t]
+  uint64_t* mirror;  // host-visible progress word of this job's slot (see mirror_word)
+  uint32_t tag;      // (job id << 8) | level, echoed in the progress word
+  int32_t pstride;
   // transfer into this level from level-2 (A) and level-1 (B)
   const void* uA;
   const void* uB;
@@ -81,6 +84,12 @@ struct JobDesc {
   void* u_lv[kMaxLevels];
   int32_t lh[kMaxLevels], lw[kMaxLevels], lp[kMaxLevels];
 };
+
+// Progress word published by the finalize kernels into pinned host memory:
+// [63:32] tag (job id << 8 | level), [31:8] iterations done, [7:0] stop reason.
+__host__ __device__ inline uint64_t mirror_word(uint32_t tag, int32_t k, int32_t done) {
+  return ((uint64_t)tag << 32) | ((uint64_t)(uint32_t)(k & 0xFFFFFF) << 8) | (uint64_t)(uint32_t)(done & 0xFF);
+}
 
 // Kernel-argument list of the jobs one launch covers.  Block b belongs to the
 // entry e with start[e] <= b < start[e+1]; job[e] indexes the JobDesc table.
@@ -128,7 +137,8 @@ int rmax_class_for(int r);
 int blocks_for_stage(Stage st, const JobDesc& d);
 
 // Operator kernels on dense buffers (one image, no job table).
-hipError_t op_conv(const void* x, void* y, int H, int W, const void* taps, int variant, bool f64, hipStream_t s);
+hipError_t op_conv(const void* x, void* y, int H, int W, const void* taps, int variant, int radius, bool f64,
+                   hipStream_t s);
 hipError_t op_restrict(const void* gf, int Hf, int Wf, void* gc, bool f64, hipStream_t s);
 hipError_t op_extrapolate(const void* uA, const void* uB, int HB, int WB, void* ut, bool f64, hipStream_t s);
 hipError_t op_prolong_quad(const void* ut, int HC, int WC, void* uC, bool f64, hipStream_t s);

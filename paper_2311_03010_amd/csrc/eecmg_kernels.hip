@@ -18,17 +18,28 @@ namespace eecmg {
 __device__ __forceinline__ bool finite_d(double x) { return isfinite(x); }
 
 // Fixed-order sum of selected components of the tile partials of one job,
-// returned to every thread of the 256-thread block.
+// returned to every thread of the 256-thread block.  Thread i sums the
+// contiguous chunk [i*ch, (i+1)*ch) of each component in index order, then the
+// 256 chunk sums are combined by a fixed tree: the result depends only on the
+// job's own partials.
 template <int NV>
-__device__ __forceinline__ void sum_partials(const double* __restrict__ part, int ntiles, const int (&comp)[NV],
-                                             double (&out)[NV]) {
+__device__ __forceinline__ void sum_partials(const double* __restrict__ part, int ntiles, int stride,
+                                             const int (&comp)[NV], double (&out)[NV]) {
   __shared__ double red[4][NV];
+  const int ch = (ntiles + 255) / 256;
+  const int t0 = min((int)threadIdx.x * ch, ntiles), t1 = min(t0 + ch, ntiles);
   double acc[NV];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-  for (int t = threadIdx.x; t < ntiles; t += 256) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] += part[(size_t)t * kNPart + comp[i]];
+  for (int i = 0; i < NV; ++i) {
+    const double* __restrict__ c = part + (size_t)comp[i] * stride;
+    double a = 0.0;
+    int t = t0;
+    for (; t + 4 <= t1; t += 4) {
+      const double v0 = c[t], v1 = c[t + 1], v2 = c[t + 2], v3 = c[t + 3];
+      a = (((a + v0) + v1) + v2) + v3;
+    }
+    for (; t < t1; ++t) a += c[t];
+    acc[i] = a;
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -40,6 +51,13 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ part, in
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < NV; ++i) out[i] = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
+}
+
+// Publish the job's progress (level tag, iterations, stop reason) to pinned
+// host memory as one 64-bit system-scope store; the host only uses it to
+// decide how many more iterations to enqueue.
+__device__ __forceinline__ void publish(const JobDesc& d, const SolverState* st) {
+  __hip_atomic_store(d.mirror, mirror_word(d.tag, st->k, st->done), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Stopping tests of the smoother, in the order: non-finite, discrepancy
@@ -69,7 +87,7 @@ __global__ __launch_bounds__(256) void k_cg_fin_init(LaunchList ll, const JobDes
   const JobDesc& d = descs[ll.job[blockIdx.x]];
   double v[2];
   const int comp[2] = {1, 2};
-  sum_partials<2>(d.partials, d.ntiles, comp, v);
+  sum_partials<2>(d.partials, d.ntiles, d.pstride, comp, v);
   if (threadIdx.x != 0) return;
   SolverState* st = d.st;
   st->k = 0;
@@ -86,6 +104,7 @@ __global__ __launch_bounds__(256) void k_cg_fin_init(LaunchList ll, const JobDes
   d.rec[d.level].reason = kStopNone;
   d.rec[d.level].rms = sqrt(v[0] / ((double)d.h * (double)d.w));
   check_stop(st, d, v[0], v[1], v[1], !finite_d(v[0]) || !finite_d(v[1]));
+  publish(d, st);
 }
 
 __global__ __launch_bounds__(256) void k_cg_fin_a(LaunchList ll, const JobDesc* __restrict__ descs) {
@@ -94,7 +113,7 @@ __global__ __launch_bounds__(256) void k_cg_fin_a(LaunchList ll, const JobDesc* 
   if (st->done) return;
   double v[1];
   const int comp[1] = {0};
-  sum_partials<1>(d.partials, d.ntiles, comp, v);
+  sum_partials<1>(d.partials, d.ntiles, d.pstride, comp, v);
   if (threadIdx.x != 0) return;
   const double eta = v[0];
   st->eta = eta;
@@ -104,6 +123,7 @@ __global__ __launch_bounds__(256) void k_cg_fin_a(LaunchList ll, const JobDesc* 
     d.rec[d.level].iters = st->k;
     d.rec[d.level].reason = reason;
     d.rec[d.level].rms = sqrt(st->rr / ((double)d.h * (double)d.w));
+    publish(d, st);
     return;
   }
   st->alpha = st->gamma / eta;
@@ -115,7 +135,7 @@ __global__ __launch_bounds__(256) void k_cg_fin_b(LaunchList ll, const JobDesc* 
   if (st->done) return;
   double v[2];
   const int comp[2] = {1, 2};
-  sum_partials<2>(d.partials, d.ntiles, comp, v);
+  sum_partials<2>(d.partials, d.ntiles, d.pstride, comp, v);
   if (threadIdx.x != 0) return;
   const double gnew = v[1];
   st->beta = gnew / st->gamma;
@@ -124,13 +144,14 @@ __global__ __launch_bounds__(256) void k_cg_fin_b(LaunchList ll, const JobDesc* 
   st->par ^= 1;
   st->seq += 1;
   check_stop(st, d, v[0], gnew, st->gamma0, !finite_d(v[0]) || !finite_d(gnew));
+  publish(d, st);
 }
 
 __global__ __launch_bounds__(256) void k_mr_fin_init(LaunchList ll, const JobDesc* __restrict__ descs) {
   const JobDesc& d = descs[ll.job[blockIdx.x]];
   double v[1];
   const int comp[1] = {1};
-  sum_partials<1>(d.partials, d.ntiles, comp, v);
+  sum_partials<1>(d.partials, d.ntiles, d.pstride, comp, v);
   if (threadIdx.x != 0) return;
   SolverState* st = d.st;
   st->k = 0;
@@ -145,6 +166,7 @@ __global__ __launch_bounds__(256) void k_mr_fin_init(LaunchList ll, const JobDes
   d.rec[d.level].reason = kStopNone;
   d.rec[d.level].rms = sqrt(v[0] / ((double)d.h * (double)d.w));
   check_stop(st, d, v[0], v[0], v[0], !finite_d(v[0]));
+  publish(d, st);
 }
 
 __global__ __launch_bounds__(256) void k_mr_fin(LaunchList ll, const JobDesc* __restrict__ descs) {
@@ -153,7 +175,7 @@ __global__ __launch_bounds__(256) void k_mr_fin(LaunchList ll, const JobDesc* __
   if (st->done) return;
   double v[3];
   const int comp[3] = {0, 1, 2};
-  sum_partials<3>(d.partials, d.ntiles, comp, v);
+  sum_partials<3>(d.partials, d.ntiles, d.pstride, comp, v);
   if (threadIdx.x != 0) return;
   if (st->pending) st->k += 1;
   st->pending = 0;
@@ -161,18 +183,20 @@ __global__ __launch_bounds__(256) void k_mr_fin(LaunchList ll, const JobDesc* __
   st->seq += 1;
   const double rq = v[0], rr = v[1], qq = v[2];
   check_stop(st, d, rr, rr, st->rr0, !finite_d(rr) || !finite_d(rq) || !finite_d(qq));
-  if (st->done) return;
-  st->eta = qq;
-  if (qq == 0.0) {
-    st->done = kStopGuard;
-    d.rec[d.level].iters = st->k;
-    d.rec[d.level].reason = kStopGuard;
-    d.rec[d.level].rms = sqrt(rr / ((double)d.h * (double)d.w));
-    return;
+  if (!st->done) {
+    st->eta = qq;
+    if (qq == 0.0) {
+      st->done = kStopGuard;
+      d.rec[d.level].iters = st->k;
+      d.rec[d.level].reason = kStopGuard;
+      d.rec[d.level].rms = sqrt(rr / ((double)d.h * (double)d.w));
+    } else {
+      st->rq = rq;
+      st->alpha = rq / qq;
+      st->pending = 1;
+    }
   }
-  st->rq = rq;
-  st->alpha = rq / qq;
-  st->pending = 1;
+  publish(d, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -603,10 +627,11 @@ hipError_t launch_stage(Stage st, bool f64, int variant, const LaunchList& ll, c
              : launch_typed<float>(st, variant, ll, descs, src, dst, s);
 }
 
-hipError_t op_conv(const void* x, void* y, int H, int W, const void* taps, int variant, bool f64, hipStream_t s) {
+hipError_t op_conv(const void* x, void* y, int H, int W, const void* taps, int variant, int radius, bool f64,
+                   hipStream_t s) {
   const int kind = variant / 100, R = variant % 100;
   switch (kind) {
-    case kConvGeneral: return opc_gen(f64, x, y, H, W, taps, R, s);
+    case kConvGeneral: return opc_gen(f64, x, y, H, W, taps, radius, s);  // template class from the radius
     case kConvSep: return f64 ? opc_f64_sep(x, y, H, W, taps, R, s) : opc_f32_sep(x, y, H, W, taps, R, s);
     case kConvSymSquare:
       return f64 ? opc_f64_sym(false, x, y, H, W, taps, R, s) : opc_f32_sym(false, x, y, H, W, taps, R, s);

@@ -441,7 +441,7 @@ struct Job {
   int next_chunk = 1;
   int confirmed = 0;
   bool level_done_seen = false;
-  uint64_t level_rb_seq = 0;  // first readback that can describe the current level
+  uint32_t uid = 0;           // engine-assigned id, part of the progress tag
   hipEvent_t done_ev = nullptr;
   int status = EECMG_OK;
   LevelRecord rec[kMaxLevels];
@@ -474,11 +474,10 @@ class Engine {
     EECMG_HIP(hipHostMalloc((void**)&h_desc_, sizeof(JobDesc) * kMaxSlots * kMaxLevels, hipHostMallocDefault));
     EECMG_HIP(hipHostMalloc((void**)&h_rec_, sizeof(LevelRecord) * kMaxSlots * kMaxLevels, hipHostMallocDefault));
     EECMG_HIP(hipHostMalloc((void**)&h_taps_, kTapsSlotBytes * kMaxSlots, hipHostMallocDefault));
-    for (auto& r : rb_) {
-      EECMG_HIP(hipHostMalloc((void**)&r.h, sizeof(SolverState) * kMaxSlots, hipHostMallocDefault));
-      EECMG_HIP(hipEventCreateWithFlags(&r.ev, hipEventDisableTiming));
-      r.pending = false;
-    }
+    EECMG_HIP(hipHostMalloc((void**)&h_mirror_, sizeof(uint64_t) * kMaxSlots, hipHostMallocCoherent));
+    std::memset((void*)h_mirror_, 0, sizeof(uint64_t) * kMaxSlots);
+    EECMG_HIP(hipHostGetDevicePointer((void**)&d_mirror_, (void*)h_mirror_, 0));
+    for (auto& e : step_ev_) EECMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     slots_.assign(kMaxSlots, nullptr);
     return EECMG_OK;
   }
@@ -492,11 +491,11 @@ class Engine {
     if (h_desc_) (void)hipHostFree(h_desc_);
     if (h_rec_) (void)hipHostFree(h_rec_);
     if (h_taps_) (void)hipHostFree(h_taps_);
-    for (auto& r : rb_) {
-      if (r.h) (void)hipHostFree(r.h);
-      if (r.ev) (void)hipEventDestroy(r.ev);
-      r.h = nullptr;
-      r.ev = nullptr;
+    if (h_mirror_) (void)hipHostFree((void*)h_mirror_);
+    h_mirror_ = nullptr;
+    for (auto& e : step_ev_) {
+      if (e) (void)hipEventDestroy(e);
+      e = nullptr;
     }
     d_desc_ = nullptr;
     d_state_ = nullptr;
@@ -528,6 +527,7 @@ class Engine {
     if (!mem) return EECMG_EAGAIN;
     j->slot = slot;
     j->mem = mem;
+    j->uid = (next_uid_++) & 0xFFFFFF;
     slots_[slot] = j;
     ++n_active_;
     j->phase = Job::kNew;
@@ -560,7 +560,7 @@ class Engine {
   // Issue one round of work for every active job.  Returns true if anything
   // was launched.
   bool step(std::vector<Job*>& finished) {
-    consume_readbacks(false);
+    poll_mirror();
     finished.clear();
     // action lists
     std::vector<Job*> restrict_l, out_l;
@@ -594,7 +594,6 @@ class Engine {
             j->confirmed = 0;
             j->next_chunk = 1;
             j->level_done_seen = false;
-            j->level_rb_seq = rb_seq_ + 1;  // the readback issued at the end of this step
             j->phase = Job::kIter;
             again = true;
             break;
@@ -614,13 +613,14 @@ class Engine {
               }
               break;
             }
+            // keep at most kMaxAhead unconfirmed iterations queued: enough to
+            // hide the host's reaction time, few enough that a data-dependent
+            // stop leaves almost no empty launches behind
             const int ahead = j->issued - j->confirmed;
-            int chunk = std::min(j->next_chunk, limit - j->issued);
-            chunk = std::min(chunk, kMaxAhead - ahead);
+            const int chunk = std::min(limit - j->issued, kMaxAhead - ahead);
             if (chunk > 0) {
               iter_l.push_back({j, chunk});
               j->issued += chunk;
-              j->next_chunk = std::min(2 * j->next_chunk, kMaxChunk);
             }
             break;
           }
@@ -664,23 +664,28 @@ class Engine {
       j->phase = Job::kWaitOut;
       launched = true;
     }
-    if (!iter_l.empty() || !init_l.empty()) issue_readback();
+    if (launched) {
+      step_cur_ = (step_cur_ + 1) % kStepEvents;
+      chk(hipEventRecord(step_ev_[step_cur_], stream_));
+      step_pending_ = true;
+    }
     return launched;
   }
 
-  // Block until some outstanding GPU work has completed (readback or output).
+  // Wait until the device reports progress for some job (through the pinned
+  // progress words) or all enqueued work has completed.
   void wait_some() {
-    for (auto& r : rb_)
-      if (r.pending && r.seq == oldest_pending_seq()) {
-        chk(hipEventSynchronize(r.ev));
-        consume_readbacks(false);
+    const std::vector<uint64_t> before = snapshot();
+    for (long spin = 0;; ++spin) {
+      if (snapshot() != before) return;
+      for (Job* j : slots_)
+        if (j && j->phase == Job::kWaitOut && hipEventQuery(j->done_ev) == hipSuccess) return;
+      if (!step_pending_ || hipEventQuery(step_ev_[step_cur_]) == hipSuccess) {
+        step_pending_ = false;
         return;
       }
-    for (Job* j : slots_)
-      if (j && j->phase == Job::kWaitOut) {
-        chk(hipEventSynchronize(j->done_ev));
-        return;
-      }
+      if (spin > 2000) std::this_thread::yield();
+    }
   }
 
   // Release a finished job's slot and memory.
@@ -699,21 +704,33 @@ class Engine {
   int device() const { return device_; }
 
  private:
-  static constexpr int kMaxChunk = 16;
-  static constexpr int kMaxAhead = 48;
+  static constexpr int kMaxAhead = 2;
 
-  struct Readback {
-    SolverState* h = nullptr;
-    hipEvent_t ev = nullptr;
-    bool pending = false;
-    uint64_t seq = 0;
-  };
+  static constexpr int kStepEvents = 4;
 
-  uint64_t oldest_pending_seq() const {
-    uint64_t m = UINT64_MAX;
-    for (auto& r : rb_)
-      if (r.pending) m = std::min(m, r.seq);
-    return m;
+  std::vector<uint64_t> snapshot() const {
+    std::vector<uint64_t> v(kMaxSlots);
+    for (int i = 0; i < kMaxSlots; ++i) v[i] = __atomic_load_n(&h_mirror_[i], __ATOMIC_ACQUIRE);
+    return v;
+  }
+
+  static uint32_t level_tag(const Job* j, int level) { return (j->uid << 8) | (uint32_t)level; }
+
+  // Read the progress words the finalize kernels publish; a word counts only
+  // if its tag names this job and its current level.
+  void poll_mirror() {
+    for (Job* j : slots_) {
+      if (!j || j->phase != Job::kIter) continue;
+      const uint64_t w = __atomic_load_n(&h_mirror_[j->slot], __ATOMIC_ACQUIRE);
+      if ((uint32_t)(w >> 32) != level_tag(j, j->cur_level())) continue;
+      const int k = (int)((w >> 8) & 0xFFFFFF), done = (int)(w & 0xFF);
+      const int passes = j->plan.prm.smoother == EECMG_SMOOTHER_MR ? k + 1 : k;
+      j->confirmed = std::max(j->confirmed, std::min(passes, j->issued));
+      if (done != 0) {
+        j->level_done_seen = true;
+        j->confirmed = j->issued;
+      }
+    }
   }
 
   bool needs_transfer(const Job* j, int l) const {
@@ -751,6 +768,9 @@ class Engine {
     d.st = d_state_ + j->slot;
     d.rec = d_rec_ + (size_t)j->slot * kMaxLevels;
     d.partials = (double*)(m + P.off_part);
+    d.pstride = P.max_tiles;
+    d.mirror = d_mirror_ + j->slot;
+    d.tag = level_tag(j, l);
     if (l >= 1) {
       d.uB = m + P.off_u[l - 1];
       d.hB = P.lv[l - 1].h;
@@ -892,59 +912,6 @@ class Engine {
     }
   }
 
-  void issue_readback() {
-    Readback* r = nullptr;
-    for (auto& x : rb_)
-      if (!x.pending) {
-        r = &x;
-        break;
-      }
-    if (!r) {
-      // all in flight: wait for the oldest
-      uint64_t m = oldest_pending_seq();
-      for (auto& x : rb_)
-        if (x.pending && x.seq == m) {
-          chk(hipEventSynchronize(x.ev));
-          consume_readbacks(false);
-          r = &x;
-          break;
-        }
-      if (!r || r->pending) return;
-    }
-    chk(hipMemcpyAsync(r->h, d_state_, sizeof(SolverState) * kMaxSlots, hipMemcpyDeviceToHost, stream_));
-    chk(hipEventRecord(r->ev, stream_));
-    r->pending = true;
-    r->seq = ++rb_seq_;
-  }
-
-  void consume_readbacks(bool block) {
-    // apply completed readbacks in issue order
-    for (;;) {
-      Readback* r = nullptr;
-      uint64_t m = oldest_pending_seq();
-      if (m == UINT64_MAX) return;
-      for (auto& x : rb_)
-        if (x.pending && x.seq == m) r = &x;
-      if (!r) return;
-      if (block)
-        chk(hipEventSynchronize(r->ev));
-      else if (hipEventQuery(r->ev) != hipSuccess)
-        return;
-      r->pending = false;
-      for (Job* j : slots_) {
-        if (!j || j->phase != Job::kIter) continue;
-        if (r->seq < j->level_rb_seq) continue;  // taken before this level began
-        const SolverState& s = r->h[j->slot];
-        if (s.level != j->cur_level()) continue;
-        j->confirmed = std::max(j->confirmed, std::min(s.k, j->issued));
-        if (s.done != 0) {
-          j->level_done_seen = true;
-          j->confirmed = j->issued;
-        }
-      }
-    }
-  }
-
   void finish(Job* j) {
     std::memcpy(j->rec, h_rec_ + (size_t)j->slot * kMaxLevels, sizeof(LevelRecord) * kMaxLevels);
     int st = EECMG_OK;
@@ -970,8 +937,12 @@ class Engine {
   LevelRecord* d_rec_ = nullptr;
   LevelRecord* h_rec_ = nullptr;
   char* h_taps_ = nullptr;
-  Readback rb_[3];
-  uint64_t rb_seq_ = 0;
+  volatile uint64_t* h_mirror_ = nullptr;
+  uint64_t* d_mirror_ = nullptr;
+  hipEvent_t step_ev_[kStepEvents] = {};
+  int step_cur_ = 0;
+  bool step_pending_ = false;
+  uint32_t next_uid_ = 1;
   std::vector<Job*> slots_;
   int n_active_ = 0;
 };
@@ -1284,7 +1255,7 @@ int eecmg_op_conv_dev(const void* x_dev, void* y_dev, int H, int W, const double
   int variant = 0;
   rc = op_taps(psf, psf_radius, f64, transpose != 0, &taps, &variant);
   if (rc) return rc;
-  hipError_t e = op_conv(x_dev, y_dev, H, W, taps, variant, f64, (hipStream_t)hip_stream);
+  hipError_t e = op_conv(x_dev, y_dev, H, W, taps, variant, psf_radius, f64, (hipStream_t)hip_stream);
   if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)hip_stream);
   (void)hipFree(taps);
   if (e != hipSuccess) return fail(EECMG_EDEVICE, hipGetErrorString(e));
