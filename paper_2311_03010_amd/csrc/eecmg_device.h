@@ -47,6 +47,19 @@ __device__ __forceinline__ T to_t(double x) {
   return (T)x;
 }
 
+// Pointers taken from a job descriptor are generic; casting them to the global
+// address space lets the compiler emit global (not flat) loads and stores
+// with a scalar base and a 32-bit offset.
+#define EECMG_G __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ EECMG_G T* gp(void* p) {
+  return (EECMG_G T*)p;
+}
+template <typename T>
+__device__ __forceinline__ const EECMG_G T* gpc(const void* p) {
+  return (const EECMG_G T*)p;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -288,37 +301,32 @@ __device__ __forceinline__ TileGeo tile_geo(const JobDesc& d, int t) {
   return g;
 }
 
-// Load tile + halo: for every tile element in the image, make(load(o), o,
-// interior) gives the LDS value (interior: the pixel belongs to this tile's
-// output region; make may store it or accumulate a partial); elements outside
-// the image are zero (the operator's zero boundary condition).
-// For compile-time radii the loop is fully unrolled and split in two phases:
-// every global load is issued first, from an address clamped into the image
-// (always valid), and only then are the values combined and written to LDS,
-// so a wave keeps dozens of loads in flight instead of waiting row by row.
-template <typename T, typename P, typename LoadF, typename MakeF>
-__device__ __forceinline__ void load_tile(T* __restrict__ tile, const TileGeo& g, LoadF load, MakeF make) {
+// Load tile + halo: every tile element in the image gets combine(load(o)),
+// elements outside the image are zero (the operator's zero boundary
+// condition); o is the element's 32-bit offset in the level's pitched array.
+// For compile-time radii the loop is fully unrolled in two phases: every
+// global load is issued first, from an address clamped into the image (always
+// valid), then the values are combined (branch-free) and written to LDS, so a
+// wave keeps dozens of loads in flight instead of waiting row by row.
+template <typename T, typename P, typename LoadF, typename CombF>
+__device__ __forceinline__ void load_tile(T* __restrict__ tile, const TileGeo& g, LoadF load, CombF combine) {
   if constexpr (P::kRuntimeR) {
     const int R = g.R;
     constexpr int NWV = P::NT / 64;
     for (int ly = g.wave; ly < P::TH + 2 * R; ly += NWV) {
       const int gy = g.y0 - R + ly;
       const bool row_in = gy >= 0 && gy < g.h;
-      const bool row_int = ly >= R && ly < R + P::TH;
       for (int lx = g.lane; lx < P::TW + 2 * R; lx += 64) {
         const int gx = g.x0 - R + lx;
         T v = T(0);
-        if (row_in && gx >= 0 && gx < g.w) {
-          const size_t o = (size_t)gy * g.pitch + gx;
-          v = make(load(o), o, row_int && lx >= R && lx < R + P::TW);
-        }
+        if (row_in && gx >= 0 && gx < g.w) v = combine(load((unsigned)(gy * g.pitch + gx)));
         tile[ly * P::LW + lx] = v;
       }
     }
   } else {
     constexpr int R = P::RC, LWr = P::TW + 2 * R, N = LWr * (P::TH + 2 * R);
     constexpr int IT = (N + P::NT - 1) / P::NT;
-    using V = decltype(load((size_t)0));
+    using V = decltype(load(0u));
     V vals[IT];
 #pragma unroll
     for (int k = 0; k < IT; ++k) {
@@ -326,7 +334,7 @@ __device__ __forceinline__ void load_tile(T* __restrict__ tile, const TileGeo& g
       const int ly = idx / LWr, lx = idx - ly * LWr;
       const int gy = min(max(g.y0 - R + ly, 0), g.h - 1);
       const int gx = min(max(g.x0 - R + lx, 0), g.w - 1);
-      vals[k] = load((size_t)gy * g.pitch + gx);
+      vals[k] = load((unsigned)(gy * g.pitch + gx));
     }
 #pragma unroll
     for (int k = 0; k < IT; ++k) {
@@ -334,35 +342,48 @@ __device__ __forceinline__ void load_tile(T* __restrict__ tile, const TileGeo& g
       if (k < IT - 1 || idx < N) {
         const int ly = idx / LWr, lx = idx - ly * LWr;
         const int gy = g.y0 - R + ly, gx = g.x0 - R + lx;
-        T v = T(0);
-        if (gy >= 0 && gy < g.h && gx >= 0 && gx < g.w) {
-          const bool interior = ly >= R && ly < R + P::TH && lx >= R && lx < R + P::TW;
-          v = make(vals[k], (size_t)gy * g.pitch + gx, interior);
-        }
-        tile[ly * P::LW + lx] = v;
+        const bool ok = gy >= 0 && gy < g.h && gx >= 0 && gx < g.w;
+        const T v = combine(vals[k]);
+        tile[ly * P::LW + lx] = ok ? v : T(0);
       }
     }
   }
 }
 
-// The tile's own output pixels (no halo), one column per lane: f(o, row) for
-// every in-image pixel, with all loads of the functor issued as one burst.
+// The tile's own output pixels (no halo), one column per lane, rows split
+// between the waves: f(load(o), o, row) for every in-image pixel, with all
+// loads issued as one burst (from clamped, always valid addresses).
 template <typename P, typename LoadF, typename UseF>
 __device__ __forceinline__ void for_interior(const TileGeo& g, LoadF load, UseF use) {
   constexpr int NWV = P::NT / 64, ROWS = P::TH / NWV;
   const int gx = g.x0 + g.lane;
   const int gxc = min(gx, g.w - 1);
-  using V = decltype(load((size_t)0));
+  using V = decltype(load(0u));
   V vals[ROWS];
 #pragma unroll
   for (int i = 0; i < ROWS; ++i) {
     const int gy = min(g.y0 + g.wave * ROWS + i, g.h - 1);
-    vals[i] = load((size_t)gy * g.pitch + gxc);
+    vals[i] = load((unsigned)(gy * g.pitch + gxc));
   }
 #pragma unroll
   for (int i = 0; i < ROWS; ++i) {
     const int gy = g.y0 + g.wave * ROWS + i;
-    if (gy < g.h && gx < g.w) use(vals[i], (size_t)gy * g.pitch + gx, g.wave * ROWS + i);
+    if (gy < g.h && gx < g.w) use(vals[i], (unsigned)(gy * g.pitch + gx), g.wave * ROWS + i);
+  }
+}
+
+// Interior pixels read back from the LDS tile (after the barrier that follows
+// load_tile): use(v, o, in_image) for the lane's rows; the caller predicates
+// its stores on in_image.
+template <typename T, typename P, typename UseF>
+__device__ __forceinline__ void tile_interior(const T* __restrict__ tile, const TileGeo& g, int R, UseF use) {
+  constexpr int NWV = P::NT / 64, ROWS = P::TH / NWV;
+  const int gx = g.x0 + g.lane;
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i) {
+    const int row = g.wave * ROWS + i;
+    const int gy = g.y0 + row;
+    use(tile[(row + R) * P::LW + g.lane + R], (unsigned)(gy * g.pitch + gx), gy < g.h && gx < g.w);
   }
 }
 
@@ -388,19 +409,19 @@ __global__ __launch_bounds__(P::NT) void k_init1(LaunchList ll, const JobDesc* _
   const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
   const JobDesc& d = descs[L.d];
   const TileGeo g = tile_geo<P>(d, L.t);
-  const T* __restrict__ u = (const T*)d.u;
-  const T* __restrict__ gg = (const T*)d.g;
-  T* __restrict__ r = (T*)d.r[0];
-  load_tile<T, P>(tile, g, [&](size_t o) { return u[o]; }, [&](T v, size_t, bool) { return v; });
-  for_interior<P>(g, [&](size_t o) { return gg[o]; }, [&](T v, size_t, int row) { gsh[row * P::TW + g.lane] = v; });
+  const auto* __restrict__ u = gpc<T>(d.u);
+  const auto* __restrict__ gg = gpc<T>(d.g);
+  auto* __restrict__ r = gp<T>(d.r[0]);
+  load_tile<T, P>(tile, g, [&](unsigned o) { return u[o]; }, [](T v) { return v; });
+  for_interior<P>(g, [&](unsigned o) { return gg[o]; }, [&](T v, unsigned, int row) { gsh[row * P::TW + g.lane] = v; });
   __syncthreads();
   double part[1] = {0.0};
   const int gx = g.x0 + g.lane;
   P::conv(tile, (const T*)d.taps, g.R, g.wave, g.lane, [&](int v, T acc) {
     const int gy = g.y0 + v;
+    const T rv = gsh[v * P::TW + g.lane] - acc;
     if (gy < g.h && gx < g.w) {
-      const T rv = to_t<T>((double)gsh[v * P::TW + g.lane] - (double)acc);
-      r[(size_t)gy * g.pitch + gx] = rv;
+      r[(unsigned)(gy * g.pitch + gx)] = rv;
       part[0] += (double)rv * (double)rv;
     }
   });
@@ -414,17 +435,17 @@ __global__ __launch_bounds__(P::NT) void k_cg_init2(LaunchList ll, const JobDesc
   const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
   const JobDesc& d = descs[L.d];
   const TileGeo g = tile_geo<P>(d, L.t);
-  const T* __restrict__ r = (const T*)d.r[0];
-  T* __restrict__ s = (T*)d.s;
-  T* __restrict__ p = (T*)d.p[0];
-  load_tile<T, P>(tile, g, [&](size_t o) { return r[o]; }, [&](T v, size_t, bool) { return v; });
+  const auto* __restrict__ r = gpc<T>(d.r[0]);
+  auto* __restrict__ s = gp<T>(d.s);
+  auto* __restrict__ p = gp<T>(d.p[0]);
+  load_tile<T, P>(tile, g, [&](unsigned o) { return r[o]; }, [](T v) { return v; });
   __syncthreads();
   double part[1] = {0.0};
   const int gx = g.x0 + g.lane;
   P::conv(tile, (const T*)d.taps_t, g.R, g.wave, g.lane, [&](int v, T acc) {
     const int gy = g.y0 + v;
     if (gy < g.h && gx < g.w) {
-      const size_t o = (size_t)gy * g.pitch + gx;
+      const unsigned o = (unsigned)(gy * g.pitch + gx);
       s[o] = acc;
       p[o] = acc;
       part[0] += (double)acc * (double)acc;
@@ -444,25 +465,23 @@ __global__ __launch_bounds__(P::NT) void k_cg_a(LaunchList ll, const JobDesc* __
   if (__builtin_amdgcn_readfirstlane(st->done)) return;
   const TileGeo g = tile_geo<P>(d, L.t);
   const int par = uni(st->par);
-  const double beta = st->beta;
-  const T* __restrict__ s = (const T*)d.s;
-  const T* __restrict__ po = (const T*)d.p[par];
-  T* __restrict__ pn = (T*)d.p[par ^ 1];
-  T* __restrict__ q = (T*)d.q[0];
+  const T beta = (T)st->beta;
+  const auto* __restrict__ s = gpc<T>(d.s);
+  const auto* __restrict__ po = gpc<T>(d.p[par]);
+  auto* __restrict__ pn = gp<T>(d.p[par ^ 1]);
+  auto* __restrict__ q = gp<T>(d.q[0]);
   load_tile<T, P>(
-      tile, g, [&](size_t o) { return Two<T>{s[o], po[o]}; },
-      [&](Two<T> x, size_t o, bool interior) {
-        const T v = to_t<T>((double)x.a + beta * (double)x.b);
-        if (interior) pn[o] = v;
-        return v;
-      });
+      tile, g, [&](unsigned o) { return Two<T>{s[o], po[o]}; }, [&](Two<T> x) { return fma(beta, x.b, x.a); });
   __syncthreads();
+  tile_interior<T, P>(tile, g, pol_R<P>(g), [&](T v, unsigned o, bool in) {
+    if (in) pn[o] = v;
+  });
   double part[1] = {0.0};
   const int gx = g.x0 + g.lane;
   P::conv(tile, (const T*)d.taps, g.R, g.wave, g.lane, [&](int v, T acc) {
     const int gy = g.y0 + v;
     if (gy < g.h && gx < g.w) {
-      q[(size_t)gy * g.pitch + gx] = acc;
+      q[(unsigned)(gy * g.pitch + gx)] = acc;
       part[0] += (double)acc * (double)acc;
     }
   });
@@ -480,33 +499,29 @@ __global__ __launch_bounds__(P::NT) void k_cg_b(LaunchList ll, const JobDesc* __
   if (__builtin_amdgcn_readfirstlane(st->done)) return;
   const TileGeo g = tile_geo<P>(d, L.t);
   const int par = uni(st->par);
-  const double alpha = st->alpha;
-  const T* __restrict__ ro = (const T*)d.r[par];
-  T* __restrict__ rn = (T*)d.r[par ^ 1];
-  const T* __restrict__ q = (const T*)d.q[0];
-  const T* __restrict__ pn = (const T*)d.p[par ^ 1];
-  T* __restrict__ u = (T*)d.u;
-  T* __restrict__ s = (T*)d.s;
+  const T alpha = (T)st->alpha;
+  const auto* __restrict__ ro = gpc<T>(d.r[par]);
+  auto* __restrict__ rn = gp<T>(d.r[par ^ 1]);
+  const auto* __restrict__ q = gpc<T>(d.q[0]);
+  const auto* __restrict__ pn = gpc<T>(d.p[par ^ 1]);
+  auto* __restrict__ u = gp<T>(d.u);
+  auto* __restrict__ s = gp<T>(d.s);
   double part[2] = {0.0, 0.0};
   load_tile<T, P>(
-      tile, g, [&](size_t o) { return Two<T>{ro[o], q[o]}; },
-      [&](Two<T> x, size_t o, bool interior) {
-        const T v = to_t<T>((double)x.a - alpha * (double)x.b);
-        if (interior) {
-          rn[o] = v;
-          part[0] += (double)v * (double)v;
-        }
-        return v;
-      });
+      tile, g, [&](unsigned o) { return Two<T>{ro[o], q[o]}; }, [&](Two<T> x) { return fma(-alpha, x.b, x.a); });
   for_interior<P>(
-      g, [&](size_t o) { return Two<T>{u[o], pn[o]}; },
-      [&](Two<T> x, size_t o, int) { u[o] = to_t<T>((double)x.a + alpha * (double)x.b); });
+      g, [&](unsigned o) { return Two<T>{u[o], pn[o]}; },
+      [&](Two<T> x, unsigned o, int) { u[o] = fma(alpha, x.b, x.a); });
   __syncthreads();
+  tile_interior<T, P>(tile, g, pol_R<P>(g), [&](T v, unsigned o, bool in) {
+    if (in) rn[o] = v;
+    part[0] += in ? (double)v * (double)v : 0.0;
+  });
   const int gx = g.x0 + g.lane;
   P::conv(tile, (const T*)d.taps_t, g.R, g.wave, g.lane, [&](int v, T acc) {
     const int gy = g.y0 + v;
     if (gy < g.h && gx < g.w) {
-      s[(size_t)gy * g.pitch + gx] = acc;
+      s[(unsigned)(gy * g.pitch + gx)] = acc;
       part[1] += (double)acc * (double)acc;
     }
   });
@@ -526,34 +541,32 @@ __global__ __launch_bounds__(P::NT) void k_mr_pass(LaunchList ll, const JobDesc*
   const int R = pol_R<P>(g);
   const int par = uni(st->par);
   const bool pending = uni(st->pending) != 0;
-  const double alpha = st->alpha;
-  const T* __restrict__ ro = (const T*)d.r[par];
-  const T* __restrict__ qo = (const T*)d.q[par];
-  T* __restrict__ rn = (T*)d.r[par ^ 1];
-  T* __restrict__ qn = (T*)d.q[par ^ 1];
-  T* __restrict__ u = (T*)d.u;
+  const T alpha = pending ? (T)st->alpha : T(0);
+  const auto* __restrict__ ro = gpc<T>(d.r[par]);
+  const auto* __restrict__ qo = gpc<T>(d.q[par]);
+  auto* __restrict__ rn = gp<T>(d.r[par ^ 1]);
+  auto* __restrict__ qn = gp<T>(d.q[par ^ 1]);
+  auto* __restrict__ u = gp<T>(d.u);
   double part[3] = {0.0, 0.0, 0.0};
-  // qo is read even before the first step (its value is then unused)
-  load_tile<T, P>(
-      tile, g, [&](size_t o) { return Two<T>{ro[o], qo[o]}; },
-      [&](Two<T> x, size_t o, bool interior) {
-        const T v = pending ? to_t<T>((double)x.a - alpha * (double)x.b) : x.a;
-        if (interior) {
-          rn[o] = v;
-          part[1] += (double)v * (double)v;
-        }
-        return v;
-      });
-  if (pending)
+  if (pending) {
+    load_tile<T, P>(
+        tile, g, [&](unsigned o) { return Two<T>{ro[o], qo[o]}; }, [&](Two<T> x) { return fma(-alpha, x.b, x.a); });
     for_interior<P>(
-        g, [&](size_t o) { return Two<T>{u[o], ro[o]}; },
-        [&](Two<T> x, size_t o, int) { u[o] = to_t<T>((double)x.a + alpha * (double)x.b); });
+        g, [&](unsigned o) { return Two<T>{u[o], ro[o]}; },
+        [&](Two<T> x, unsigned o, int) { u[o] = fma(alpha, x.b, x.a); });
+  } else {
+    load_tile<T, P>(tile, g, [&](unsigned o) { return ro[o]; }, [](T v) { return v; });
+  }
   __syncthreads();
+  tile_interior<T, P>(tile, g, R, [&](T v, unsigned o, bool in) {
+    if (in) rn[o] = v;
+    part[1] += in ? (double)v * (double)v : 0.0;
+  });
   const int gx = g.x0 + g.lane;
   P::conv(tile, (const T*)d.taps, g.R, g.wave, g.lane, [&](int v, T acc) {
     const int gy = g.y0 + v;
     if (gy < g.h && gx < g.w) {
-      qn[(size_t)gy * g.pitch + gx] = acc;
+      qn[(unsigned)(gy * g.pitch + gx)] = acc;
       const T rc = tile[(v + R) * P::LW + g.lane + R];
       part[0] += (double)rc * (double)acc;
       part[2] += (double)acc * (double)acc;
@@ -577,12 +590,12 @@ __global__ __launch_bounds__(P::NT) void k_op_conv(const T* __restrict__ x, T* _
   g.x0 = (blockIdx.x % tiles_x) * P::TW;
   g.wave = uni(threadIdx.x >> 6);
   g.lane = threadIdx.x & 63;
-  load_tile<T, P>(tile, g, [&](size_t o) { return x[o]; }, [&](T v, size_t, bool) { return v; });
+  load_tile<T, P>(tile, g, [&](unsigned o) { return x[o]; }, [](T v) { return v; });
   __syncthreads();
   const int gx = g.x0 + g.lane;
   P::conv(tile, taps, R, g.wave, g.lane, [&](int v, T acc) {
     const int gy = g.y0 + v;
-    if (gy < H && gx < W) y[(size_t)gy * W + gx] = acc;
+    if (gy < H && gx < W) y[(unsigned)(gy * W + gx)] = acc;
   });
 }
 
