@@ -10,11 +10,10 @@ input into a device-resident output.
 Prints one JSON line.  Besides the throughput it reports
   roofline:      the finest-level CGLS pass B kernel (dominant), algorithmic
                  HBM bytes per launch / its mean duration from HIP events on
-                 the library's launch stream during the timed region;
-  cpu_baseline:  the FP64 CPU oracle on a bounded sample of the same
-                 workload (every level's initialisation, one iteration and
-                 transfer timed at full size, scaled by the iteration counts
-                 of the run).
+                 the library's launch stream during the timed region (launches
+                 that found their level already stopped are excluded);
+  cpu_baseline:  the FP64 CPU oracle timed on one complete restore of the
+                 same input on the host's cores.
 """
 from __future__ import annotations
 
@@ -30,7 +29,46 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
-FP32_VALU_PEAK_TFLOPS = 78.6   # non-packed FP32 FMA: 256 CU x 64 lanes x 2 flop x 2.4 GHz
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cg_pass_b_disk6_4096.json")
+KERNEL_SOURCES = ["paper_2311_03010_amd/csrc/eecmg_device.h", "paper_2311_03010_amd/csrc/eecmg_sm_f32_sym.hip",
+                  "paper_2311_03010_amd/csrc/eecmg_internal.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE passes (scaled by the copy-kernel calibration), or
+    None when the kernel sources changed since they were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def copy_probe():
+    """A plain device copy of known size, for calibrating the HBM counters."""
+    import torch
+
+    n = 256 << 20  # floats: 1 GiB per buffer
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 5}))
 
 
 def _log(msg):
@@ -38,45 +76,19 @@ def _log(msg):
 
 
 def cpu_baseline(p, stats):
-    """Oracle (FP64, all host cores via OpenMP) timed on a bounded sample."""
+    """The FP64 CPU oracle (OpenMP over the pixel loops of its stencils) timed
+    on one complete restore of the same input, same parameters."""
     import oracle
 
-    L = p.n_levels
-    sizes = oracle.level_sizes(p.shape[0], p.shape[1], L)
-    psfs = [None] * L
-    psfs[L - 1] = p.psf
-    for l in range(L - 2, -1, -1):
-        psfs[l] = oracle.coarse_psf(psfs[l + 1], 0)
-    gs = [None] * L
-    gs[L - 1] = p.g_delta
-    for l in range(L - 2, -1, -1):
-        gs[l] = oracle.restrict(gs[l + 1], *sizes[l])
-    total = 0.0
-    rng = np.random.Generator(np.random.PCG64(1))
-    for l in range(L):
-        t0 = time.perf_counter()
-        oracle.cgls(gs[l], psfs[l], cap=0)
-        t_init = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        oracle.cgls(gs[l], psfs[l], cap=1, eps=0.0)
-        t_one = time.perf_counter() - t0
-        t_iter = max(t_one - t_init, 0.0)
-        t_x = 0.0
-        if l >= 2:
-            (ha, wa), (hb, wb), (hc, wc) = sizes[l - 2], sizes[l - 1], sizes[l]
-            uA = rng.uniform(0, 255, (ha, wa))
-            uB = rng.uniform(0, 255, (hb, wb))
-            t0 = time.perf_counter()
-            ut = oracle.extrapolate(uA, uB)
-            uc = oracle.prolong_quad(ut, hc, wc)
-            us = oracle.local_smooth(uc)
-            oracle.pm_step(us)
-            t_x = time.perf_counter() - t0
-        total += t_init + stats["iters"][l] * t_iter + t_x
-    mpx = p.shape[0] * p.shape[1] / total / 1e6
-    return {"value": mpx, "unit": "Mpixel/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "every level's CGLS init + one iteration + transfer at full 4096^2 size, scaled by the run's "
-                      f"per-level iteration counts {stats['iters']}; estimated full restore {total:.1f} s"}
+    g = p.g_delta.astype(np.float32).astype(np.float64) if p.precision != "f64" else p.g_delta
+    t0 = time.perf_counter()
+    _, st = oracle.restore(g, p.psf, p.n_levels, delta=p.delta, k=p.k,
+                           guard_eps=1e-6 if p.precision != "f64" else 1e-14)
+    dt = time.perf_counter() - t0
+    return {"value": round(p.shape[0] * p.shape[1] / dt / 1e6, 4), "unit": "Mpixel/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"one complete restore of the same {p.shape[0]}x{p.shape[1]} input ({dt:.1f} s); "
+                      f"oracle iterations per level {st['iters']} (GPU {stats['iters']})"}
 
 
 def main():
@@ -86,7 +98,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", type=int, default=3, choices=[1, 2, 3])
+    ap.add_argument("--batch", type=int, default=4, help="images in the batched leg (0 = skip)")
+    ap.add_argument("--copy-probe", action="store_true", help="only run the HBM counter calibration copy")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU design is described but not built", file=sys.stderr)
@@ -139,9 +156,30 @@ def main():
     if rb:
         ach = rb["gbs"]
         roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_cg_b<float,6> (finest level)",
-                    "avg_launch_us": round(rb["avg_us"], 2)}
+                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                    "kernel": "k_cg_b<float, ConvSym<float, 6, true>> (finest level, 4096^2)",
+                    "avg_launch_us": round(rb["avg_us"], 2), "alg_bytes_per_launch": int(20 * H * W)}
     extra = {"kernels": kern, "iters_per_level": stats["iters"], "stop_reason": stats["reason"]}
+
+    batched = None
+    if args.batch > 0:
+        # copies of the same input (identical work per image), all images in
+        # one batched cascade: every stage is one launch for all of them
+        _log(f"bench: batched leg, {args.batch} images")
+        gs = [g.clone() for _ in range(args.batch)]
+        outs = [torch.empty_like(x) for x in gs]
+        bkw = dict(precision=prec, params=[{"delta": p.delta}] * len(gs))
+        for _ in range(max(1, args.warmup)):
+            eecmg.restore_batch_dev(gs, [p.psf] * len(gs), [p.n_levels] * len(gs), outs=outs, **bkw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            eecmg.restore_batch_dev(gs, [p.psf] * len(gs), [p.n_levels] * len(gs), outs=outs, **bkw)
+        torch.cuda.synchronize()
+        bdt = time.perf_counter() - t0
+        batched = {"images": len(gs), "value": round(len(gs) * H * W * args.steps / bdt / 1e6, 3),
+                   "unit": "Mpixel/s", "ms_per_step": round(bdt / args.steps * 1e3, 3),
+                   "speedup_vs_plain": round(len(gs) * H * W * args.steps / bdt / 1e6 / value, 3)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -155,7 +193,7 @@ def main():
             "config": {"workload": p.name, "H": H, "W": W, "psf": "disk r=6" if args.workload == 3 else "gaussian",
                        "n_levels": p.n_levels, "precision": prec, "stop_rule": "discrepancy c=1.1",
                        "caps": "economic m_l rule", "form": "plain"},
-            "roofline": roofline, "cpu_baseline": cpu, "detail": extra}
+            "roofline": roofline, "cpu_baseline": cpu, "batched": batched, "detail": extra}
     print(json.dumps(line), flush=True)
 
 

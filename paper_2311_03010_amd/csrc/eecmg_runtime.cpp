@@ -376,12 +376,19 @@ struct Profiler {
   std::mutex mu;
   std::atomic<bool> on{false};
   int min_blocks = 0;
+  struct Tag {
+    uint32_t uid;
+    int level, kidx;
+    bool mr;
+  };
   struct Rec {
     int stage;
     hipEvent_t a, b;
     double pixels;
+    std::vector<Tag> tags;  // smoother passes: which iteration each job runs
   };
   std::vector<Rec> pending;
+  std::map<uint64_t, int> final_iters;  // (uid, level) -> iterations run
   std::vector<hipEvent_t> pool;
   int launches[kNumStages] = {};
   double ms[kNumStages] = {};
@@ -397,10 +404,22 @@ struct Profiler {
     (void)hipEventCreate(&e);
     return e;
   }
+  // A smoother pass launched after its level had already stopped returns at
+  // once; such launches are not counted.  CGLS iteration k runs both passes
+  // iff k < iterations run; MR pass k runs iff k <= iterations run.
+  bool real(const Rec& r) const {
+    if (r.tags.empty()) return true;
+    for (const Tag& t : r.tags) {
+      auto it = final_iters.find(((uint64_t)t.uid << 8) | (uint64_t)t.level);
+      if (it == final_iters.end()) return true;
+      if (t.mr ? t.kidx <= it->second : t.kidx < it->second) return true;
+    }
+    return false;
+  }
   void harvest() {
     for (auto& r : pending) {
       float t = 0.f;
-      if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+      if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess && real(r)) {
         launches[r.stage] += 1;
         ms[r.stage] += t;
         pixels[r.stage] += r.pixels;
@@ -807,7 +826,8 @@ class Engine {
 
   // Launch `stage` for jobs at the given level (-1: each job's current level),
   // splitting by nothing: caller groups jobs of one precision / variant.
-  void launch_group(Stage st, const std::vector<Job*>& jobs, int level, bool f64, int variant, int src, int dst) {
+  void launch_group(Stage st, const std::vector<Job*>& jobs, int level, bool f64, int variant, int src, int dst,
+                    const std::vector<int>* kidx = nullptr) {
     LaunchList ll;
     ll.n = 0;
     ll.total = 0;
@@ -836,7 +856,11 @@ class Engine {
       chk(hipEventRecord(a, stream_));
       chk(launch_stage(st, f64, variant, ll, d_desc_, src, dst, stream_));
       chk(hipEventRecord(b, stream_));
-      pr.pending.push_back({(int)st, a, b, px});
+      Profiler::Rec rec{(int)st, a, b, px, {}};
+      if (kidx)
+        for (size_t i = 0; i < jobs.size(); ++i)
+          rec.tags.push_back({jobs[i]->uid, jobs[i]->cur_level(), (*kidx)[i], st == kMrPass});
+      pr.pending.push_back(std::move(rec));
       return;
     }
     chk(launch_stage(st, f64, variant, ll, d_desc_, src, dst, stream_));
@@ -894,18 +918,24 @@ class Engine {
     for (auto& x : its) maxc = std::max(maxc, x.second);
     for (int it = 0; it < maxc; ++it) {
       std::map<std::pair<int, int>, std::vector<Job*>> groups;
+      std::map<std::pair<int, int>, std::vector<int>> kidx;  // iteration index per job
       for (auto& x : its)
-        if (x.second > it) groups[{x.first->plan.prm.smoother, variant_key(x.first)}].push_back(x.first);
+        if (x.second > it) {
+          const std::pair<int, int> key{x.first->plan.prm.smoother, variant_key(x.first)};
+          groups[key].push_back(x.first);
+          kidx[key].push_back(x.first->issued - x.second + it);
+        }
       for (auto& kv : groups) {
         const bool f64 = kv.first.second >= 100000;
         const int rc = kv.first.second % 100000;
+        const std::vector<int>* ki = &kidx[kv.first];
         if (kv.first.first == EECMG_SMOOTHER_CGLS) {
-          launch_group(kCgA, kv.second, -1, f64, rc, -1, -1);
+          launch_group(kCgA, kv.second, -1, f64, rc, -1, -1, ki);
           launch_group(kCgFinA, kv.second, -1, f64, rc, -1, -1);
-          launch_group(kCgB, kv.second, -1, f64, rc, -1, -1);
+          launch_group(kCgB, kv.second, -1, f64, rc, -1, -1, ki);
           launch_group(kCgFinB, kv.second, -1, f64, rc, -1, -1);
         } else {
-          launch_group(kMrPass, kv.second, -1, f64, rc, -1, -1);
+          launch_group(kMrPass, kv.second, -1, f64, rc, -1, -1, ki);
           launch_group(kMrFin, kv.second, -1, f64, rc, -1, -1);
         }
       }
@@ -914,6 +944,11 @@ class Engine {
 
   void finish(Job* j) {
     std::memcpy(j->rec, h_rec_ + (size_t)j->slot * kMaxLevels, sizeof(LevelRecord) * kMaxLevels);
+    {
+      Profiler& pr = profiler();
+      std::lock_guard<std::mutex> g(pr.mu);
+      for (int l = 0; l < j->plan.L; ++l) pr.final_iters[((uint64_t)j->uid << 8) | (uint64_t)l] = j->rec[l].iters;
+    }
     int st = EECMG_OK;
     for (int l = 0; l < j->plan.L; ++l)
       if (j->rec[l].reason == kStopNonFinite) st = EECMG_ENUMERIC;
@@ -1086,6 +1121,7 @@ int eecmg_profile_reset(void) {
     p.ms[i] = 0.0;
     p.pixels[i] = 0.0;
   }
+  p.final_iters.clear();
   return EECMG_OK;
 }
 
