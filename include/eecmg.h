@@ -33,10 +33,13 @@
  *   - Host-pointer calls copy inputs before doing any work and write outputs
  *     only on EECMG_OK.  Device-pointer calls (_dev) take pointers to device
  *     memory on the current HIP device and a hipStream_t (NULL = default
- *     stream); they return once the whole cascade is enqueued on that stream
- *     and the caller synchronises the stream before reading the output.  The
- *     caller owns every buffer it passes and keeps device buffers alive until
- *     then.
+ *     stream).  The restore calls run the cascade on that stream and return
+ *     when it has completed (the level schedule follows the device's progress
+ *     words, so it cannot run ahead of the device); output and stats are then
+ *     final.  The single-operator calls (eecmg_op_*_dev) return once their
+ *     kernels are enqueued and the caller synchronises the stream before
+ *     reading the output.  The caller owns every buffer it passes and keeps
+ *     device buffers alive until the work is complete.
  *   - Thread safety: every function may be called from any thread; calls that
  *     share a context or the process-wide plain-restore engine are serialised
  *     internally.
@@ -224,6 +227,16 @@ int eecmg_op_prolong_quad_dev(const void* ut_dev, int HC, int WC, void* uC_dev, 
 /* Linear prolongation L of eq. (15): uB (ceil(HC/2) x ceil(WC/2)) -> uC. */
 int eecmg_op_prolong_linear_dev(const void* uB_dev, int HC, int WC, void* uC_dev, int precision,
                                 void* hip_stream);
+/* Level transfer with its stages fused into one kernel (Sections 3.2-4):
+ * the prolongation of uB (ceil(HC/2) x ceil(WC/2)) -- the quadratic
+ * interpolation P of Section 3.2 when prolongation == 0, the linear
+ * prolongation of eq. (15) when 1 -- then the smoothing S with parameter
+ * smooth_h > 0, then pm_steps (0 or 1) Perona-Malik steps D with threshold
+ * k > 0 and step 0 < tau <= 1/4, written to uC (HC x WC, must not alias uB).
+ * Gives the values of the separate operator calls run in sequence; EINVAL for
+ * pm_steps outside {0, 1}. */
+int eecmg_op_transfer_dev(const void* uB_dev, int HC, int WC, void* uC_dev, int prolongation, double smooth_h,
+                          int pm_steps, double k, double tau, int precision, void* hip_stream);
 /* Local smoothing S (Section 3.3, eq. 18-19), out of place, H x W. */
 int eecmg_op_local_smooth_dev(const void* u_dev, void* out_dev, int H, int W, double smooth_h, int precision,
                               void* hip_stream);
@@ -240,7 +253,8 @@ int eecmg_op_pm_step_dev(const void* u_dev, void* out_dev, int H, int W, double 
  * H x W).  Stage ids: 1 CGLS init r, 2 CGLS init s, 4 CGLS pass A (q = H p),
  * 6 CGLS pass B (s = H^T r), 8 MR init, 10 MR pass, 12 extrapolation,
  * 13 quadratic interpolation, 14 linear prolongation, 15 smoothing S,
- * 16 denoising D.  Process-wide; not meant for concurrent contexts.
+ * 16 denoising D, 18 fused prolongation + S (+ first D step).  Process-wide;
+ * not meant for concurrent contexts.
  * ------------------------------------------------------------------------- */
 int eecmg_profile_enable(int enable, int min_blocks);
 int eecmg_profile_reset(void);

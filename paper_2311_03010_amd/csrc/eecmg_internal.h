@@ -120,6 +120,8 @@ enum Stage : int32_t {
   kXfSmooth,        // S: src -> dst
   kXfPm,            // D: src -> dst
   kOutCopy,         // u (finest, pitched) -> dense u_out
+  kXfFused,         // prolongation -> S (-> one D step), fused; variant bit 0 quadratic, bit 1 with D
+  kXfFusedSmall,    // the same with short tiles, for small levels
   kNumStages
 };
 
@@ -145,5 +147,7 @@ hipError_t op_prolong_quad(const void* ut, int HC, int WC, void* uC, bool f64, h
 hipError_t op_prolong_linear(const void* uB, int HC, int WC, void* uC, bool f64, hipStream_t s);
 hipError_t op_local_smooth(const void* u, void* out, int H, int W, double h, bool f64, hipStream_t s);
 hipError_t op_pm_step(const void* u, void* out, int H, int W, double k, double tau, bool f64, hipStream_t s);
+hipError_t op_fused_transfer(const void* uB, int HC, int WC, void* uC, bool quad, double smooth_h, bool denoise,
+                             double k, double tau, bool f64, hipStream_t s);
 
 }  // namespace eecmg

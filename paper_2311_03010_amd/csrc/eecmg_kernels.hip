@@ -279,131 +279,202 @@ struct QExt {
 // One axis of the quadratic interpolation: fine index I, coarse panel
 // (2a, 2a+1, 2a+2) with Lagrange weights (3/8, 3/4, -1/8) and (-1/8, 3/4, 3/8)
 // at the quarter points.
+// Branch-free: the three nodes base..base+2 (base = p, or p - 1 for odd p;
+// inside the extended grid for every fine I) are always read and the result
+// selected; an even I takes node p itself.
 template <typename F>
 __device__ __forceinline__ double quad1(int I, F f) {
   const int p = I >> 1;
-  if (!(I & 1)) return f(p);
-  if (!(p & 1)) return 0.375 * f(p) + 0.75 * f(p + 1) - 0.125 * f(p + 2);
-  return -0.125 * f(p - 1) + 0.75 * f(p) + 0.375 * f(p + 1);
+  const bool podd = (p & 1) != 0;
+  const int base = podd ? p - 1 : p;
+  const double f0 = f(base), f1 = f(base + 1), f2 = f(base + 2);
+  const double w0 = podd ? -0.125 : 0.375, w2 = podd ? 0.375 : -0.125;
+  const double odd = fma(w2, f2, fma(0.75, f1, w0 * f0));
+  return (I & 1) ? odd : (podd ? f1 : f0);
+}
+
+// Quadratic interpolation value at fine (I, J) from the extended coarse
+// values E(p, q): along i first (for the needed columns q), then along j.
+template <typename F>
+__device__ __forceinline__ double quad_value(int I, int J, F E) {
+  return quad1(J, [&](int q) { return quad1(I, [&](int p) { return E(p, q); }); });
 }
 
 template <typename T>
 __device__ __forceinline__ void quad_point(const XArgs& x, int I, int J) {
   const QExt<T> E{(const T*)x.s0, x.h0, x.w0, x.p0};
-  // along i first (T(I, q) for the needed columns q), then along j
-  const double v = quad1(J, [&](int q) { return quad1(I, [&](int p) { return E(p, q); }); });
-  ((T*)x.dst)[(size_t)I * x.pd + J] = to_t<T>(v);
+  ((T*)x.dst)[(size_t)I * x.pd + J] = to_t<T>(quad_value(I, J, E));
 }
 
-// Linear prolongation of eq. (15) with one linearly extrapolated virtual
-// node per axis (along j first, then along i).
+// Source of the linear prolongation extended by one linearly extrapolated
+// virtual node per axis (along j for the real rows first, then along i).
+template <typename T>
+struct LExt {
+  const T* u;
+  int h, w, p;
+  __device__ __forceinline__ double at(int i, int j) const { return (double)u[(size_t)i * p + j]; }
+  __device__ __forceinline__ double rowext(int i, int j) const {
+    return j < w ? at(i, j) : 2.0 * at(i, w - 1) - at(i, w - 2);
+  }
+  __device__ __forceinline__ double operator()(int i, int j) const {
+    return i < h ? rowext(i, j) : 2.0 * rowext(h - 1, j) - rowext(h - 2, j);
+  }
+};
+
+// Linear prolongation of eq. (15): nodes copy, edge midpoints average their
+// ends, cell centres average along the (a,b)-(a+1,b+1) diagonal.
+template <typename F>
+__device__ __forceinline__ double linear_value(int I, int J, F E) {
+  const int a = I >> 1, b = J >> 1;
+  if (!(I & 1) && !(J & 1)) return E(a, b);
+  if (!(I & 1)) return 0.5 * (E(a, b) + E(a, b + 1));
+  if (!(J & 1)) return 0.5 * (E(a, b) + E(a + 1, b));
+  return 0.5 * (E(a, b) + E(a + 1, b + 1));
+}
+
 template <typename T>
 __device__ __forceinline__ void linear_point(const XArgs& x, int I, int J) {
-  const T* u = (const T*)x.s0;
-  const int h = x.h0, w = x.w0, p = x.p0;
-  auto at = [&](int i, int j) { return (double)u[(size_t)i * p + j]; };
-  auto rowext = [&](int i, int j) { return j < w ? at(i, j) : 2.0 * at(i, w - 1) - at(i, w - 2); };
-  auto E = [&](int i, int j) { return i < h ? rowext(i, j) : 2.0 * rowext(h - 1, j) - rowext(h - 2, j); };
-  const int a = I >> 1, b = J >> 1;
-  double v;
-  if (!(I & 1) && !(J & 1))
-    v = E(a, b);
-  else if (!(I & 1))
-    v = 0.5 * (E(a, b) + E(a, b + 1));
-  else if (!(J & 1))
-    v = 0.5 * (E(a, b) + E(a + 1, b));
-  else
-    v = 0.5 * (E(a, b) + E(a + 1, b + 1));
-  ((T*)x.dst)[(size_t)I * x.pd + J] = to_t<T>(v);
+  const LExt<T> E{(const T*)x.s0, x.h0, x.w0, x.p0};
+  ((T*)x.dst)[(size_t)I * x.pd + J] = to_t<T>(linear_value(I, J, E));
 }
 
 // Local smoothing S (Section 3.3, eq. 18-19): weighted LS fit of
 // a0 + a1 s + a2 t on the 3x3 window with w = exp(-((u_c - u_n)/h)^2)
 // (exactly 0 beyond (./h)^2 > 30, out-of-image neighbours dropped), output
-// a0.  The fit is centred on the pixel value and on the weighted centroid,
-// and the 2x2 system for (a1, a2) is solved through its eigen-decomposition
-// (one Jacobi rotation, no trigonometric calls), dropping eigenvalues below
-// 1e-12 of the largest; the fitted centre value stays accurate for
-// near-collinear weight patterns.
+// a0.  nb[3 (s+1) + (t+1)] holds the window (any finite value where the
+// neighbour is outside the image); up/down/left/right tell whether rows
+// s = -1 / +1 and columns t = -1 / +1 are inside.  The fit is centred on the
+// pixel value and on the weighted centroid, which leaves a 2x2 system
+// S a = c for the slopes and a0 = u_c + vb - (sb, tb) . a.  A well
+// conditioned S (det > 1e-3 tr^2, so both eigenvalues exceed 1e-3 of the
+// larger) is solved by its adjugate; otherwise through its eigen-decomposition
+// (one Jacobi rotation, no trigonometric calls) with eigenvalues below 1e-12
+// of the largest dropped, so near-collinear weight patterns stay accurate.
+// The window moments are formed from row and column sums (the offsets are
+// -1, 0, 1).  The FP32 path evaluates the weights with the hardware
+// exponential.
+template <bool F32>
+__device__ __forceinline__ double smooth_core(const double (&nb)[9], bool up, bool down, bool left, bool right,
+                                              double inv_h) {
+  const double uc = nb[4];
+  double w[9], wv[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    if (k == 4) {
+      w[k] = wv[k] = 0.0;
+      continue;
+    }
+    const int si = k / 3 - 1, ti = k % 3 - 1;
+    const bool in = (si < 0 ? up : (si > 0 ? down : true)) && (ti < 0 ? left : (ti > 0 ? right : true));
+    const double v = nb[k] - uc;
+    const double z = v * inv_h;
+    const double e = z * z;
+    const bool keep = in && !(e > 30.0);
+    double wt;
+    if (F32) {
+      const float x = __expf(-(float)e);
+      wt = (double)(keep ? x : 0.0f);
+    } else {
+      const double x = exp(-e);
+      wt = keep ? x : 0.0;
+    }
+    w[k] = wt;
+    wv[k] = wt * v;
+  }
+  const double rA = (w[0] + w[1]) + w[2], rB = (w[6] + w[7]) + w[8];
+  const double cL = (w[0] + w[3]) + w[6], cR = (w[2] + w[5]) + w[8];
+  const double m00 = ((1.0 + rA) + rB) + (w[3] + w[5]);
+  const double m01 = rB - rA, m11 = rA + rB, m02 = cR - cL, m22 = cL + cR;
+  const double m12 = (w[8] + w[0]) - (w[6] + w[2]);
+  const double RA = (wv[0] + wv[1]) + wv[2], RB = (wv[6] + wv[7]) + wv[8];
+  const double CL = (wv[0] + wv[3]) + wv[6], CR = (wv[2] + wv[5]) + wv[8];
+  const double b0 = (RA + RB) + (wv[3] + wv[5]), b1 = RB - RA, b2 = CR - CL;
+
+  const double inv0 = 1.0 / m00;
+  const double sb = m01 * inv0, tb = m02 * inv0, vb = b0 * inv0;
+  const double S11 = fma(-m01, sb, m11), S12 = fma(-m01, tb, m12), S22 = fma(-m02, tb, m22);
+  const double c1 = fma(-m01, vb, b1), c2 = fma(-m02, vb, b2);
+  const double det = fma(S11, S22, -S12 * S12), tr = S11 + S22;
+  double corr;
+  if (det > 1e-3 * tr * tr) {
+    corr = (sb * fma(S22, c1, -S12 * c2) + tb * fma(S11, c2, -S12 * c1)) / det;
+  } else {
+    // symmetric 2x2 Schur decomposition by one Jacobi rotation (t = tan of
+    // the rotation angle from tau = (S22 - S11) / (2 S12), the smaller root)
+    double cs = 1.0, sn = 0.0, l1 = S11, l2 = S22;
+    if (S12 != 0.0) {
+      const double tau = (S22 - S11) / (2.0 * S12);
+      const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+      cs = 1.0 / sqrt(1.0 + t * t);
+      sn = t * cs;
+      l1 = S11 - t * S12;
+      l2 = S22 + t * S12;
+    }
+    // eigenvectors (cs, -sn) for l1 and (sn, cs) for l2
+    const double lmax = fmax(fabs(l1), fabs(l2));
+    corr = 0.0;
+    if (l1 > 1e-12 * lmax && l1 > 0.0) corr += (sb * cs - tb * sn) * (c1 * cs - c2 * sn) / l1;
+    if (l2 > 1e-12 * lmax && l2 > 0.0) corr += (sb * sn + tb * cs) * (c1 * sn + c2 * cs) / l2;
+  }
+  return uc + (vb - corr);
+}
+
+// S at (i, j) of an H x W image read through U(ii, jj) (in-image positions
+// only: outside neighbours are read at the clamped position and dropped).
+template <bool F32, typename F>
+__device__ __forceinline__ double smooth_value(int i, int j, int H, int W, double inv_h, F U) {
+  const int im = max(i - 1, 0), ip = min(i + 1, H - 1), jm = max(j - 1, 0), jp = min(j + 1, W - 1);
+  const double nb[9] = {U(im, jm), U(im, j), U(im, jp), U(i, jm), U(i, j), U(i, jp), U(ip, jm), U(ip, j), U(ip, jp)};
+  return smooth_core<F32>(nb, i > 0, i + 1 < H, j > 0, j + 1 < W, inv_h);
+}
+
 template <typename T>
 __device__ __forceinline__ void smooth_point(const XArgs& x, int i, int j) {
   const T* u = (const T*)x.s0;
-  const int H = x.h0, W = x.w0, P = x.p0;
-  const double inv_h = 1.0 / x.a0;
-  const double uc = (double)u[(size_t)i * P + j];
-  double m00 = 0, m01 = 0, m02 = 0, m11 = 0, m12 = 0, m22 = 0, b0 = 0, b1 = 0, b2 = 0;
-#pragma unroll
-  for (int s = -1; s <= 1; ++s) {
-#pragma unroll
-    for (int t = -1; t <= 1; ++t) {
-      const int ii = i + s, jj = j + t;
-      if (ii < 0 || ii >= H || jj < 0 || jj >= W) continue;
-      const double v = (double)u[(size_t)ii * P + jj] - uc;
-      const double z = v * inv_h;
-      const double e = z * z;
-      double wt;
-      if (sizeof(T) == 4)
-        wt = e > 30.0 ? 0.0 : (double)expf(-(float)e);
-      else
-        wt = e > 30.0 ? 0.0 : exp(-e);
-      m00 += wt;
-      m01 += wt * s;
-      m02 += wt * t;
-      m11 += wt * (s * s);
-      m12 += wt * (s * t);
-      m22 += wt * (t * t);
-      b0 += wt * v;
-      b1 += wt * s * v;
-      b2 += wt * t * v;
-    }
-  }
-  const double sb = m01 / m00, tb = m02 / m00, vb = b0 / m00;
-  const double S11 = m11 - m01 * sb, S12 = m12 - m01 * tb, S22 = m22 - m02 * tb;
-  const double c1 = b1 - m01 * vb, c2 = b2 - m02 * vb;
-  // symmetric 2x2 Schur decomposition by one Jacobi rotation (t = tan of the
-  // rotation angle from tau = (S22 - S11) / (2 S12), the smaller root)
-  double cs = 1.0, sn = 0.0, l1 = S11, l2 = S22;
-  if (S12 != 0.0) {
-    const double tau = (S22 - S11) / (2.0 * S12);
-    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-    cs = 1.0 / sqrt(1.0 + t * t);
-    sn = t * cs;
-    l1 = S11 - t * S12;
-    l2 = S22 + t * S12;
-  }
-  // eigenvectors (cs, -sn) for l1 and (sn, cs) for l2
-  const double lmax = fmax(fabs(l1), fabs(l2));
-  double corr = 0.0;
-  if (l1 > 1e-12 * lmax && l1 > 0.0) corr += (sb * cs - tb * sn) * (c1 * cs - c2 * sn) / l1;
-  if (l2 > 1e-12 * lmax && l2 > 0.0) corr += (sb * sn + tb * cs) * (c1 * sn + c2 * cs) / l2;
-  ((T*)x.dst)[(size_t)i * x.pd + j] = to_t<T>(uc + (vb - corr));
+  const int P = x.p0;
+  const double v = smooth_value<sizeof(T) == 4>(i, j, x.h0, x.w0, 1.0 / x.a0,
+                                                [&](int ii, int jj) { return (double)u[(size_t)ii * P + jj]; });
+  ((T*)x.dst)[(size_t)i * x.pd + j] = to_t<T>(v);
 }
 
 // One explicit Perona-Malik step (Section 4, eq. 21, 23-25):
 // out = u + tau sum_{in-image nb} (c_nb + c)/2 (u_nb - u), c = 1/(1+|grad u|^2/k^2)
 // with |grad u| from central differences on a replicated border.
-template <typename T>
-__device__ __forceinline__ double pm_c(const T* u, int H, int W, int P, int i, int j, double ik2) {
+template <typename F>
+__device__ __forceinline__ double pm_c(int i, int j, int H, int W, double ik2, F U) {
   const int ip = i + 1 < H ? i + 1 : H - 1, im = i > 0 ? i - 1 : 0;
   const int jp = j + 1 < W ? j + 1 : W - 1, jm = j > 0 ? j - 1 : 0;
-  const double ux = 0.5 * ((double)u[(size_t)ip * P + j] - (double)u[(size_t)im * P + j]);
-  const double uy = 0.5 * ((double)u[(size_t)i * P + jp] - (double)u[(size_t)i * P + jm]);
-  return 1.0 / (1.0 + (ux * ux + uy * uy) * ik2);
+  const double ux = 0.5 * (U(ip, j) - U(im, j));
+  const double uy = 0.5 * (U(i, jp) - U(i, jm));
+  return 1.0 / fma(fma(ux, ux, uy * uy), ik2, 1.0);
+}
+
+// C(i, j) supplies the diffusivity (pm_c) at in-image pixels.
+// Out-of-image neighbours contribute nothing: they are read at the clamped
+// (in-image) position and dropped through a select.
+template <typename F, typename G>
+__device__ __forceinline__ double pm_value(int i, int j, int H, int W, double tau, F U, G C) {
+  const double uc = U(i, j);
+  const double cc = C(i, j);
+  const int ip = min(i + 1, H - 1), im = max(i - 1, 0), jp = min(j + 1, W - 1), jm = max(j - 1, 0);
+  const double cn = C(ip, j), cs = C(im, j), ce = C(i, jp), cw = C(i, jm);
+  const double un = U(ip, j), us = U(im, j), ue = U(i, jp), uw = U(i, jm);
+  double acc = 0.0;
+  acc = (i + 1 < H) ? fma(0.5 * (cn + cc), un - uc, acc) : acc;
+  acc = (i > 0) ? fma(0.5 * (cs + cc), us - uc, acc) : acc;
+  acc = (j + 1 < W) ? fma(0.5 * (ce + cc), ue - uc, acc) : acc;
+  acc = (j > 0) ? fma(0.5 * (cw + cc), uw - uc, acc) : acc;
+  return fma(tau, acc, uc);
 }
 
 template <typename T>
 __device__ __forceinline__ void pm_point(const XArgs& x, int i, int j) {
   const T* u = (const T*)x.s0;
-  const int H = x.h0, W = x.w0, P = x.p0;
-  const double ik2 = 1.0 / (x.a0 * x.a0), tau = x.a1;
-  const double uc = (double)u[(size_t)i * P + j];
-  const double cc = pm_c(u, H, W, P, i, j, ik2);
-  double acc = 0.0;
-  if (i + 1 < H) acc += 0.5 * (pm_c(u, H, W, P, i + 1, j, ik2) + cc) * ((double)u[(size_t)(i + 1) * P + j] - uc);
-  if (i > 0) acc += 0.5 * (pm_c(u, H, W, P, i - 1, j, ik2) + cc) * ((double)u[(size_t)(i - 1) * P + j] - uc);
-  if (j + 1 < W) acc += 0.5 * (pm_c(u, H, W, P, i, j + 1, ik2) + cc) * ((double)u[(size_t)i * P + j + 1] - uc);
-  if (j > 0) acc += 0.5 * (pm_c(u, H, W, P, i, j - 1, ik2) + cc) * ((double)u[(size_t)i * P + j - 1] - uc);
-  ((T*)x.dst)[(size_t)i * x.pd + j] = to_t<T>(uc + tau * acc);
+  const int P = x.p0, H = x.h0, W = x.w0;
+  const double ik2 = 1.0 / (x.a0 * x.a0);
+  auto U = [&](int ii, int jj) { return (double)u[(size_t)ii * P + jj]; };
+  const double v = pm_value(i, j, H, W, x.a1, U, [&](int ii, int jj) { return pm_c(ii, jj, H, W, ik2, U); });
+  ((T*)x.dst)[(size_t)i * x.pd + j] = to_t<T>(v);
 }
 
 // Pixel loop of one 64 x 16 tile of the destination grid.
@@ -473,6 +544,162 @@ __global__ __launch_bounds__(256) void k_xfer(LaunchList ll, const JobDesc* __re
 template <typename T, int OP>
 __global__ __launch_bounds__(256) void k_xfer_op(XArgs x) {
   xfer_tile<T, OP>(x, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Fused prolongation -> S -> D of one level transfer (Sections 3.2-4)
+// ---------------------------------------------------------------------------
+// One TY x kFX tile of the destination level per 256-thread block (TY = 32,
+// or 8 on small levels, where fewer and shorter per-thread chains matter more
+// than the halo overhead).  The
+// prolongation (quadratic P, or the linear one of IECMG-L) is evaluated on the
+// tile plus the halo that S and D need, S on the tile plus D's halo and D's
+// diffusivities on the tile plus one pixel; every intermediate stays in LDS.
+// Each value comes from the same point functions as the separate stage
+// kernels and is rounded to T between stages exactly where they store it, so
+// the fused pipeline reproduces the stages run one after another.  The
+// quadratic P is evaluated separably (along i into an FP64 LDS panel, then
+// along j), which is the evaluation order quad_value defines.
+constexpr int kFX = 64, kFY = 32, kFYSmall = 8;
+
+struct FArgs {
+  const void* src;  // level l-1 input of the prolongation (grid B)
+  int hB, wB, pB;
+  void* dst;        // level l output
+  int h, w, pitch;
+  double smooth_h, pm_k, tau;
+};
+
+template <bool QUAD, bool DO_D, int TY>
+struct FusedGeo {
+  static constexpr int HS = DO_D ? 2 : 0;  // S halo
+  static constexpr int HP = HS + 1;        // P halo
+  static constexpr int PH = TY + 2 * HP, PW = kFX + 2 * HP;
+  static constexpr int SH = TY + 2 * HS, SW = kFX + 2 * HS;
+  static constexpr int CH = TY + 2, CW = kFX + 2;
+  static constexpr int BH = PH / 2 + 5, BW = PW / 2 + 5;  // coarse panel bound
+  static constexpr int NQ = QUAD ? BH * BW + PH * BW : 0;
+  static constexpr int NC = DO_D ? CH * CW : 0;
+  static constexpr int XN = (NQ > NC ? NQ : NC) > 0 ? (NQ > NC ? NQ : NC) : 1;
+};
+
+template <typename T, bool QUAD, bool DO_D, int TY>
+__device__ __forceinline__ void fused_tile(const FArgs& a, int t) {
+  using G = FusedGeo<QUAD, DO_D, TY>;
+  __shared__ double xs[G::XN];  // coarse panels (P), then diffusivities (D)
+  __shared__ T pt[G::PH * G::PW];
+  __shared__ T stl[DO_D ? G::SH * G::SW : 1];
+  const int h = a.h, w = a.w;
+  const int tiles_x = (w + kFX - 1) / kFX;
+  const int ty = t / tiles_x, tx = t - ty * tiles_x;
+  const int I0 = ty * TY, J0 = tx * kFX;
+  const int pi0 = I0 - G::HP, pj0 = J0 - G::HP;  // origin of the P tile
+  const int Ia = max(pi0, 0), Ib = min(pi0 + G::PH, h) - 1;
+  const int Ja = max(pj0, 0), Jb = min(pj0 + G::PW, w) - 1;
+  const T* src = (const T*)a.src;
+
+  if constexpr (QUAD) {
+    const QExt<T> E{src, a.hB, a.wB, a.pB};
+    const int pa = max((Ia >> 1) - 1, 0), pb = min((Ib >> 1) + 2, a.hB + 1);
+    const int qa = max((Ja >> 1) - 1, 0), qb = min((Jb >> 1) + 2, a.wB + 1);
+    double* bt = xs;                  // E(p, q)
+    double* rt = xs + G::BH * G::BW;  // R(I, q) = quad1 along i
+    for (int k = threadIdx.x; k < G::BH * G::BW; k += 256) {
+      const int r = k / G::BW, c = k - r * G::BW;
+      if (pa + r <= pb && qa + c <= qb) bt[k] = E(pa + r, qa + c);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < G::PH * G::BW; k += 256) {
+      const int r = k / G::BW, c = k - r * G::BW;
+      const int I = pi0 + r;
+      if (I >= Ia && I <= Ib && qa + c <= qb)
+        rt[k] = quad1(I, [&](int p) { return bt[(p - pa) * G::BW + c]; });
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < G::PH * G::PW; k += 256) {
+      const int r = k / G::PW, c = k - r * G::PW;
+      const int I = pi0 + r, J = pj0 + c;
+      T v = T(0);  // outside the image: a finite filler S never weighs
+      if (I >= Ia && I <= Ib && J >= Ja && J <= Jb)
+        v = to_t<T>(quad1(J, [&](int q) { return rt[r * G::BW + (q - qa)]; }));
+      pt[k] = v;
+    }
+  } else {
+    const LExt<T> E{src, a.hB, a.wB, a.pB};
+    for (int k = threadIdx.x; k < G::PH * G::PW; k += 256) {
+      const int r = k / G::PW, c = k - r * G::PW;
+      const int I = pi0 + r, J = pj0 + c;
+      pt[k] = (I >= Ia && I <= Ib && J >= Ja && J <= Jb) ? to_t<T>(linear_value(I, J, E)) : T(0);
+    }
+  }
+  __syncthreads();
+
+  const double inv_h = 1.0 / a.smooth_h;
+  // S at (I, J) from the P tile: the whole window lies inside the tile
+  // (out-of-image entries hold the filler), so no clamping is needed.
+  auto S_at = [&](int I, int J) {
+    const T* c = pt + (I - pi0) * G::PW + (J - pj0);
+    const double nb[9] = {(double)c[-G::PW - 1], (double)c[-G::PW], (double)c[-G::PW + 1],
+                          (double)c[-1],         (double)c[0],      (double)c[1],
+                          (double)c[G::PW - 1],  (double)c[G::PW],  (double)c[G::PW + 1]};
+    return smooth_core<sizeof(T) == 4>(nb, I > 0, I + 1 < h, J > 0, J + 1 < w, inv_h);
+  };
+  T* out = (T*)a.dst;
+  if constexpr (!DO_D) {
+    for (int k = threadIdx.x; k < TY * kFX; k += 256) {
+      const int I = I0 + k / kFX, J = J0 + k % kFX;
+      if (I < h && J < w) out[(size_t)I * a.pitch + J] = to_t<T>(S_at(I, J));
+    }
+  } else {
+    const int si0 = I0 - G::HS, sj0 = J0 - G::HS;
+    for (int k = threadIdx.x; k < G::SH * G::SW; k += 256) {
+      const int r = k / G::SW, c = k - r * G::SW;
+      const int I = si0 + r, J = sj0 + c;
+      if (I >= 0 && I < h && J >= 0 && J < w) stl[k] = to_t<T>(S_at(I, J));
+    }
+    __syncthreads();
+    const double ik2 = 1.0 / (a.pm_k * a.pm_k);
+    auto Us = [&](int ii, int jj) { return (double)stl[(ii - si0) * G::SW + (jj - sj0)]; };
+    double* ct = xs;
+    for (int k = threadIdx.x; k < G::CH * G::CW; k += 256) {
+      const int r = k / G::CW, c = k - r * G::CW;
+      const int I = I0 - 1 + r, J = J0 - 1 + c;
+      if (I >= 0 && I < h && J >= 0 && J < w) ct[k] = pm_c(I, J, h, w, ik2, Us);
+    }
+    __syncthreads();
+    auto Cc = [&](int ii, int jj) { return ct[(ii - (I0 - 1)) * G::CW + (jj - (J0 - 1))]; };
+    for (int k = threadIdx.x; k < TY * kFX; k += 256) {
+      const int I = I0 + k / kFX, J = J0 + k % kFX;
+      if (I < h && J < w) out[(size_t)I * a.pitch + J] = to_t<T>(pm_value(I, J, h, w, a.tau, Us, Cc));
+    }
+  }
+}
+
+// Engine form: grids and buffers from the job's descriptor.
+template <typename T, bool QUAD, bool DO_D, int TY>
+__global__ __launch_bounds__(256) void k_xfer_fused(LaunchList ll, const JobDesc* __restrict__ descs, int src,
+                                                    int dst) {
+  const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
+  const JobDesc& d = descs[L.d];
+  FArgs a;
+  a.src = xbuf(d, src);
+  a.hB = d.hB;
+  a.wB = d.wB;
+  a.pB = d.pB;
+  a.dst = xbuf(d, dst);
+  a.h = d.h;
+  a.w = d.w;
+  a.pitch = d.pitch;
+  a.smooth_h = d.smooth_h;
+  a.pm_k = d.pm_k;
+  a.tau = d.tau;
+  fused_tile<T, QUAD, DO_D, TY>(a, L.t);
+}
+
+// Operator form on one dense image.
+template <typename T, bool QUAD, bool DO_D>
+__global__ __launch_bounds__(256) void k_xfer_fused_op(FArgs a) {
+  fused_tile<T, QUAD, DO_D, kFY>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -567,6 +794,8 @@ int blocks_for_stage(Stage st, const JobDesc& d) {
     case kMrFinInit:
     case kMrFin: return 1;
     case kXfExtrap: return tiles2(d.hB, d.wB, kXH, kXW);
+    case kXfFused: return tiles2(d.h, d.w, kFY, kFX);
+    case kXfFusedSmall: return tiles2(d.h, d.w, kFYSmall, kFX);
     default: return tiles2(d.h, d.w, kXH, kXW);
   }
 }
@@ -582,6 +811,19 @@ static hipError_t launch_smoother(Stage st, bool f64, int variant, const LaunchL
     case kConvSymDisk: return f64 ? sm_f64_sym(st, true, R, ll, descs, s) : sm_f32_sym(st, true, R, ll, descs, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <typename T, int TY>
+static hipError_t launch_fused(int variant, dim3 grid, const LaunchList& ll, const JobDesc* descs, int src, int dst,
+                               hipStream_t s) {
+  const dim3 block(256);
+  switch (variant & 3) {
+    case 0: hipLaunchKernelGGL((k_xfer_fused<T, false, false, TY>), grid, block, 0, s, ll, descs, src, dst); break;
+    case 1: hipLaunchKernelGGL((k_xfer_fused<T, true, false, TY>), grid, block, 0, s, ll, descs, src, dst); break;
+    case 2: hipLaunchKernelGGL((k_xfer_fused<T, false, true, TY>), grid, block, 0, s, ll, descs, src, dst); break;
+    default: hipLaunchKernelGGL((k_xfer_fused<T, true, true, TY>), grid, block, 0, s, ll, descs, src, dst); break;
+  }
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -606,6 +848,8 @@ static hipError_t launch_typed(Stage st, int variant, const LaunchList& ll, cons
     case kXfPm:
       hipLaunchKernelGGL((k_xfer<T, kXfPm>), grid, block, 0, s, ll, descs, src, dst);
       return hipGetLastError();
+    case kXfFused: return launch_fused<T, kFY>(variant, grid, ll, descs, src, dst, s);
+    case kXfFusedSmall: return launch_fused<T, kFYSmall>(variant, grid, ll, descs, src, dst, s);
     default: break;
   }
   return launch_smoother(st, sizeof(T) == 8, variant, ll, descs, s);
@@ -733,6 +977,40 @@ hipError_t op_pm_step(const void* u, void* out, int H, int W, double k, double t
   x.a0 = k;
   x.a1 = tau;
   return op_xfer<kXfPm>(x, f64, s);
+}
+
+template <typename T>
+static void launch_fused_op(const FArgs& a, bool quad, bool denoise, hipStream_t s) {
+  const dim3 grid(tiles2(a.h, a.w, kFY, kFX)), block(256);
+  if (quad && denoise)
+    hipLaunchKernelGGL((k_xfer_fused_op<T, true, true>), grid, block, 0, s, a);
+  else if (quad)
+    hipLaunchKernelGGL((k_xfer_fused_op<T, true, false>), grid, block, 0, s, a);
+  else if (denoise)
+    hipLaunchKernelGGL((k_xfer_fused_op<T, false, true>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((k_xfer_fused_op<T, false, false>), grid, block, 0, s, a);
+}
+
+hipError_t op_fused_transfer(const void* uB, int HC, int WC, void* uC, bool quad, double smooth_h, bool denoise,
+                             double k, double tau, bool f64, hipStream_t s) {
+  FArgs a{};
+  a.src = uB;
+  a.hB = (HC + 1) / 2;
+  a.wB = (WC + 1) / 2;
+  a.pB = a.wB;
+  a.dst = uC;
+  a.h = HC;
+  a.w = WC;
+  a.pitch = WC;
+  a.smooth_h = smooth_h;
+  a.pm_k = k;
+  a.tau = tau;
+  if (f64)
+    launch_fused_op<double>(a, quad, denoise, s);
+  else
+    launch_fused_op<float>(a, quad, denoise, s);
+  return hipGetLastError();
 }
 
 }  // namespace eecmg

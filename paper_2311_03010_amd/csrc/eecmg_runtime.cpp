@@ -438,7 +438,8 @@ static Profiler& profiler() {
 
 static bool profiled_stage(Stage st) {
   return st == kCgInit1 || st == kCgInit2 || st == kCgA || st == kCgB || st == kMrInit || st == kMrPass ||
-         st == kXfExtrap || st == kXfQuad || st == kXfLinear || st == kXfSmooth || st == kXfPm;
+         st == kXfExtrap || st == kXfQuad || st == kXfLinear || st == kXfSmooth || st == kXfPm || st == kXfFused ||
+         st == kXfFusedSmall;
 }
 
 // ---------------------------------------------------------------------------
@@ -872,26 +873,31 @@ class Engine {
   }
 
   void issue_transfers(const std::vector<std::pair<Job*, int>>& xs) {
-    // group by (precision, cascade, pm_steps)
-    std::map<std::tuple<int, int, int>, std::vector<Job*>> groups;
-    for (auto& x : xs) groups[{x.first->plan.f64, x.first->plan.prm.cascade, x.first->plan.prm.pm_steps}].push_back(x.first);
+    // group by (precision, cascade, pm_steps, small level)
+    std::map<std::tuple<int, int, int, int>, std::vector<Job*>> groups;
+    for (auto& x : xs) {
+      const Job* j = x.first;
+      const LevelPlan& lv = j->plan.lv[j->cur_level()];
+      const bool small = ((lv.h + 31) / 32) * ((lv.w + 63) / 64) < 256;
+      groups[{j->plan.f64, j->plan.prm.cascade, j->plan.prm.pm_steps, small}].push_back(x.first);
+    }
     for (auto& kv : groups) {
       const bool f64 = std::get<0>(kv.first);
       const int cascade = std::get<1>(kv.first), n = std::get<2>(kv.first);
+      const Stage fused = std::get<3>(kv.first) ? kXfFusedSmall : kXfFused;
       auto& js = kv.second;
-      if (cascade == EECMG_CASCADE_EECMG) {
-        launch_group(kXfExtrap, js, -1, f64, 0, -1, kBufT2);
-        launch_group(kXfQuad, js, -1, f64, 0, kBufT2, kBufT1);
-      } else if (cascade == EECMG_CASCADE_IECMG_P) {
-        launch_group(kXfQuad, js, -1, f64, 0, kBufUB, kBufT1);
-      } else {
-        launch_group(kXfLinear, js, -1, f64, 0, kBufUB, kBufT1);
-      }
-      launch_group(kXfSmooth, js, -1, f64, 0, kBufT1, n == 0 ? kBufU : kBufT2);
-      for (int s = 0; s < n; ++s) {
-        const int src = (s % 2 == 0) ? kBufT2 : kBufT1;
-        const int dst = (s == n - 1) ? kBufU : ((s % 2 == 0) ? kBufT1 : kBufT2);
-        launch_group(kXfPm, js, -1, f64, 0, src, dst);
+      // EECMG: Pi into t2, then P, S and the first D step fused (t2 -> u);
+      // IECMG-P / IECMG-L prolong the level below directly.  Further D
+      // steps ping-pong between the two work buffers and end in u.
+      if (cascade == EECMG_CASCADE_EECMG) launch_group(kXfExtrap, js, -1, f64, 0, -1, kBufT2);
+      const int fsrc = cascade == EECMG_CASCADE_EECMG ? kBufT2 : kBufUB;
+      const int fvar = (cascade != EECMG_CASCADE_IECMG_L ? 1 : 0) | (n >= 1 ? 2 : 0);
+      int cur = n <= 1 ? kBufU : (fsrc == kBufT2 ? kBufT1 : kBufT2);
+      launch_group(fused, js, -1, f64, fvar, fsrc, cur);
+      for (int s = 1; s < n; ++s) {
+        const int nxt = (s == n - 1) ? kBufU : (cur == kBufT1 ? kBufT2 : kBufT1);
+        launch_group(kXfPm, js, -1, f64, 0, cur, nxt);
+        cur = nxt;
       }
     }
   }
@@ -1385,6 +1391,23 @@ int eecmg_op_prolong_linear_dev(const void* uB_dev, int HC, int WC, void* uC_dev
   if (HC < 3 || WC < 3) return fail(EECMG_EINVAL, "the coarser grid needs at least 2 nodes per axis");
   if ((rc = check_dev_ptr(uB_dev, "uB_dev")) || (rc = check_dev_ptr(uC_dev, "uC_dev"))) return rc;
   EECMG_OP_TAIL(op_prolong_linear(uB_dev, HC, WC, uC_dev, precision == EECMG_FP64, (hipStream_t)hip_stream));
+}
+
+int eecmg_op_transfer_dev(const void* uB_dev, int HC, int WC, void* uC_dev, int prolongation, double smooth_h,
+                          int pm_steps, double k, double tau, int precision, void* hip_stream) {
+  g_err.clear();
+  int rc = check_prec(precision);
+  if (rc) return rc;
+  if (prolongation != 0 && prolongation != 1) return fail(EECMG_EINVAL, "prolongation must be 0 (P) or 1 (linear)");
+  if (HC < (prolongation == 0 ? 5 : 3) || WC < (prolongation == 0 ? 5 : 3))
+    return fail(EECMG_EINVAL, "the coarser grid is too small for the prolongation");
+  if (!(smooth_h > 0.0)) return fail(EECMG_EINVAL, "smooth_h must be > 0");
+  if (pm_steps != 0 && pm_steps != 1) return fail(EECMG_EINVAL, "pm_steps must be 0 or 1");
+  if (pm_steps == 1 && (!(k > 0.0) || !(tau > 0.0 && tau <= 0.25))) return fail(EECMG_EINVAL, "bad k or tau");
+  if ((rc = check_dev_ptr(uB_dev, "uB_dev")) || (rc = check_dev_ptr(uC_dev, "uC_dev"))) return rc;
+  if (uB_dev == uC_dev) return fail(EECMG_EINVAL, "the transfer is out of place: uB and uC must not alias");
+  EECMG_OP_TAIL(op_fused_transfer(uB_dev, HC, WC, uC_dev, prolongation == 0, smooth_h, pm_steps == 1, k, tau,
+                                  precision == EECMG_FP64, (hipStream_t)hip_stream));
 }
 
 int eecmg_op_local_smooth_dev(const void* u_dev, void* out_dev, int H, int W, double smooth_h, int precision,

@@ -94,6 +94,7 @@ def lib():
         "eecmg_op_prolong_linear_dev": [vp, i, i, vp, i, vp],
         "eecmg_op_local_smooth_dev": [vp, vp, i, i, d, i, vp],
         "eecmg_op_pm_step_dev": [vp, vp, i, i, d, d, i, vp],
+        "eecmg_op_transfer_dev": [vp, i, i, vp, i, d, i, d, d, i, vp],
         "eecmg_profile_enable": [i, i],
         "eecmg_profile_reset": [],
         "eecmg_profile_read": [i, ip, dp, dp],
@@ -361,9 +362,22 @@ def pm_step_dev(u, k=10.0, tau=0.2, precision="f32", stream=None):
     return out
 
 
+def transfer_dev(ub, HC, WC, prolongation="quad", smooth_h=1.0, pm_steps=1, k=10.0, tau=0.2, precision="f32",
+                 stream=None):
+    """Fused prolongation (quadratic or linear) -> S -> pm_steps (0/1) D steps."""
+    import torch
+
+    out = torch.empty((HC, WC), dtype=ub.dtype, device=ub.device)
+    _check(lib().eecmg_op_transfer_dev(ctypes.c_void_p(ub.data_ptr()), HC, WC, ctypes.c_void_p(out.data_ptr()),
+                                       0 if prolongation == "quad" else 1, float(smooth_h), int(pm_steps), float(k),
+                                       float(tau), _prec_code(precision), _stream_handle(stream)))
+    return out
+
+
 # ------------------------------------------------------------ kernel timing
 STAGES = {"cg_init_r": 1, "cg_init_s": 2, "cg_pass_a": 4, "cg_pass_b": 6, "mr_init": 8, "mr_pass": 10,
-          "extrapolate": 12, "prolong_quad": 13, "prolong_linear": 14, "local_smooth": 15, "pm_step": 16}
+          "extrapolate": 12, "prolong_quad": 13, "prolong_linear": 14, "local_smooth": 15, "pm_step": 16,
+          "transfer_fused": 18}
 
 
 def profile_enable(enable=True, min_blocks=0):

@@ -120,6 +120,42 @@ def test_smooth_and_denoise_parity(torch_cuda, prec, H, W):
         _close(d.cpu().numpy(), oracle.pm_step(u, k, tau), prec, f"pm_step k={k}")
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prolong", ["quad", "linear"])
+@pytest.mark.parametrize("HC,WC", [(5, 5), (33, 33), (34, 30), (129, 70), (97, 200), (515, 1030)])
+def test_fused_transfer_parity(torch_cuda, prec, prolong, HC, WC):
+    """The fused prolongation -> S (-> D) kernel against (a) the separate
+    operator kernels run in sequence (bit-identical) and (b) the oracle's
+    operators composed with the same rounding to the storage precision
+    between stages.  Sizes span several 64 x 32 tiles, ragged edges and the
+    smallest grid the quadratic interpolation allows."""
+    rng = np.random.Generator(np.random.PCG64(HC * 31 + WC + (prolong == "quad")))
+    HB, WB = (HC + 1) // 2, (WC + 1) // 2
+    ub = 100 + 3.0 * rng.standard_normal((HB, WB))
+    ub[HB // 4: HB // 2, WB // 3: WB // 2] += 50.0  # an edge: S weights cut off, D slows down
+    ub = ub.astype(_dt(prec)).astype(np.float64)
+    t = torch_cuda
+    dt = _dt(prec)
+    for hs, steps, k, tau in ((1.0, 1, 10.0, 0.2), (2.5, 0, 10.0, 0.2), (0.7, 1, 3.0, 0.25)):
+        got = eecmg.transfer_dev(_dev(t, ub, prec), HC, WC, prolongation=prolong, smooth_h=hs, pm_steps=steps, k=k,
+                                 tau=tau, precision=prec).cpu().numpy()
+        # (a) separate kernels
+        if prolong == "quad":
+            x = eecmg.prolong_quad_dev(_dev(t, ub, prec), HC, WC, precision=prec)
+        else:
+            x = eecmg.prolong_linear_dev(_dev(t, ub, prec), HC, WC, precision=prec)
+        x = eecmg.local_smooth_dev(x, smooth_h=hs, precision=prec)
+        if steps:
+            x = eecmg.pm_step_dev(x, k=k, tau=tau, precision=prec)
+        np.testing.assert_array_equal(got, x.cpu().numpy(), err_msg=f"fused != separate (h={hs}, D steps {steps})")
+        # (b) oracle, rounded to the storage precision between stages
+        y = oracle.prolong_quad(ub, HC, WC) if prolong == "quad" else oracle.prolong_linear(ub, HC, WC)
+        y = oracle.local_smooth(y.astype(dt).astype(np.float64), hs)
+        if steps:
+            y = oracle.pm_step(y.astype(dt).astype(np.float64), k, tau)
+        _close(got, y, prec, f"fused transfer h={hs} steps={steps}")
+
+
 def test_operator_errors(torch_cuda):
     t = torch_cuda
     x = t.zeros((8, 8), dtype=t.float32, device="cuda:0")
@@ -130,3 +166,7 @@ def test_operator_errors(torch_cuda):
         eecmg.pm_step_dev(x, k=10.0, tau=0.3)
     with pytest.raises(eecmg.EecmgError):
         eecmg.local_smooth_dev(x, smooth_h=0.0)
+    with pytest.raises(eecmg.EecmgError):
+        eecmg.transfer_dev(x, 16, 16, pm_steps=2)
+    with pytest.raises(eecmg.EecmgError):
+        eecmg.transfer_dev(x, 4, 4)  # the quadratic interpolation needs 3 coarse nodes per axis
