@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cg_pass_b_disk6_4096.json")
-KERNEL_SOURCES = ["paper_2311_03010_amd/csrc/eecmg_device.h", "paper_2311_03010_amd/csrc/eecmg_sm_f32_sym.hip",
+KERNEL_SOURCES = ["paper_2311_03010_amd/csrc/eecmg_device.h", "paper_2311_03010_amd/csrc/eecmg_sm_box.hip",
                   "paper_2311_03010_amd/csrc/eecmg_internal.h"]
 
 
@@ -126,7 +126,9 @@ def main():
         eecmg.restore_dev(g, p.psf, p.n_levels, out=out, **kw)
     torch.cuda.synchronize()
 
-    fine_tiles = ((W + 63) // 64) * ((H + 31) // 32)
+    # finest-level launches only: every tile is at most 64 rows tall, and the
+    # next level has a quarter of the pixels
+    fine_tiles = ((W + 63) // 64) * ((H + 63) // 64)
     eecmg.profile_reset()
     eecmg.profile_enable(True, min_blocks=fine_tiles)
     _log(f"bench: timing {args.steps} steps")
@@ -141,23 +143,31 @@ def main():
     ms_step = dt / args.steps * 1e3
     value = H * W * args.steps / dt / 1e6
 
-    # dominant kernel: finest-level CGLS pass B (r -= alpha q, s = H^T r, u += alpha p)
-    # algorithmic HBM bytes per pixel: read r, u, write r, u, s = 5 x 4 B
+    # dominant kernel: finest-level CGLS pass B (r -= alpha q, s = H^T r, u += alpha p).
+    # Algorithmic HBM bytes per pixel and iteration are 32 (u, r, p, s each
+    # read and written once): 12 in pass A (read s, p; write p) and 20 in
+    # pass B (read r, u; write r, u, s).  The two passes actually move 16 and
+    # 28 (q is stored by A and read by B, p is read again by B).
     kern = {}
-    for name, bpp in (("cg_pass_a", 12), ("cg_pass_b", 20)):
+    for name, bpp, moved in (("cg_pass_a", 12, 16), ("cg_pass_b", 20, 28)):
         n, ms, px = eecmg.profile_read(name)
         if n:
             avg_ms = ms / n
             px_launch = px / n
             kern[name] = {"launches": n, "avg_us": avg_ms * 1e3, "alg_bytes_per_px": bpp,
-                          "gbs": bpp * px_launch / (avg_ms * 1e-3) / 1e9}
+                          "gbs": bpp * px_launch / (avg_ms * 1e-3) / 1e9, "moved_bytes_per_px": moved,
+                          "moved_gbs": moved * px_launch / (avg_ms * 1e-3) / 1e9}
+    for name in ("cg_init_r", "cg_init_s", "transfer_fused"):
+        n, ms, px = eecmg.profile_read(name)
+        if n:
+            kern[name] = {"launches": n, "avg_us": ms / n * 1e3}
     rb = kern.get("cg_pass_b")
     roofline = None
     if rb:
         ach = rb["gbs"]
         roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                    "kernel": "k_cg_b<float, ConvSym<float, 6, true>> (finest level, 4096^2)",
+                    "kernel": "k_cg_b<float, ConvBox<float, 6>> (finest level, 4096^2)",
                     "avg_launch_us": round(rb["avg_us"], 2), "alg_bytes_per_launch": int(20 * H * W)}
     extra = {"kernels": kern, "iters_per_level": stats["iters"], "stop_reason": stats["reason"]}
 

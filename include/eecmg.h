@@ -18,7 +18,8 @@
  *   - Return value: an eecmg_status (0 = OK).  Outputs go through out-pointers
  *     only; nothing throws across the ABI.  On a non-OK status,
  *     eecmg_last_error() returns a thread-local message.
- *   - Images are dense row-major H x W arrays (H rows, W columns, no padding);
+ *   - Images are dense row-major H x W arrays (H rows, W columns, no padding),
+ *     each below 4 GiB (EINVAL otherwise: kernels index with 32-bit offsets);
  *     element type double when params->precision == EECMG_FP64, float otherwise.
  *     H and W are image sizes, not the blur operator.
  *   - PSF: (2r+1) x (2r+1) doubles, row-major, psf[(a+r)*(2r+1)+(b+r)] is the

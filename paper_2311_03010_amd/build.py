@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libeecmg.so")
-SOURCES = ["eecmg_kernels.hip", "eecmg_sm_f32_sep.hip", "eecmg_sm_f32_sym.hip", "eecmg_sm_f64.hip",
+SOURCES = ["eecmg_kernels.hip", "eecmg_sm_f32_sep.hip", "eecmg_sm_f32_sym.hip", "eecmg_sm_f64.hip", "eecmg_sm_box.hip",
            "eecmg_sm_gen.hip", "eecmg_runtime.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

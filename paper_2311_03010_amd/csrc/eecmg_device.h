@@ -47,17 +47,63 @@ __device__ __forceinline__ T to_t(double x) {
   return (T)x;
 }
 
-// Pointers taken from a job descriptor are generic; casting them to the global
-// address space lets the compiler emit global (not flat) loads and stores
-// with a scalar base and a 32-bit offset.
+// Pointers taken from a job descriptor are generic; GPtr casts them to the
+// global address space and indexes with a 32-bit byte offset, so the compiler
+// emits global (not flat) loads and stores with a scalar base and one VGPR
+// offset.  Every level array is below 4 GiB (checked when a job is planned).
 #define EECMG_G __attribute__((address_space(1)))
 template <typename T>
-__device__ __forceinline__ EECMG_G T* gp(void* p) {
-  return (EECMG_G T*)p;
+struct GPtr {
+  EECMG_G T* p;
+  __device__ __forceinline__ EECMG_G T& operator[](unsigned o) const {
+    return *(EECMG_G T*)((EECMG_G char*)p + o * (unsigned)sizeof(T));
+  }
+};
+template <typename T>
+struct GPtrC {
+  const EECMG_G T* p;
+  __device__ __forceinline__ const EECMG_G T& operator[](unsigned o) const {
+    return *(const EECMG_G T*)((const EECMG_G char*)p + o * (unsigned)sizeof(T));
+  }
+};
+// Buffer view of one array for the streaming kernels: raw buffer loads and
+// stores whose range the hardware checks against the array size, so an
+// access at element offset >= n reads 0 and a store there is dropped.  The
+// kernels pass offset `n` (the view's `none`) for pixels outside the image
+// and need neither clamping nor branches around memory operations.
+template <typename T>
+struct BufView {
+  __amdgpu_buffer_rsrc_t rs;
+  __device__ __forceinline__ T ld(unsigned o) const {
+    if constexpr (sizeof(T) == 4) {
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, o * 4u, 0, 0));
+    } else {
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, o * 8u, 0, 0));
+    }
+  }
+  __device__ __forceinline__ void st(unsigned o, T v) const {
+    if constexpr (sizeof(T) == 4) {
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rs, o * 4u, 0, 0);
+    } else {
+      using V2 = unsigned __attribute__((ext_vector_type(2)));
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), rs, o * 8u, 0, 0);
+    }
+  }
+};
+// n: elements in the array (the level's h x pitch); below 2^32 bytes.
+template <typename T>
+__device__ __forceinline__ BufView<T> bview(const void* p, unsigned n) {
+  return BufView<T>{__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)(n * (unsigned)sizeof(T)),
+                                                      0x00020000)};
+}
+
+template <typename T>
+__device__ __forceinline__ GPtr<T> gp(void* p) {
+  return GPtr<T>{(EECMG_G T*)p};
 }
 template <typename T>
-__device__ __forceinline__ const EECMG_G T* gpc(const void* p) {
-  return (const EECMG_G T*)p;
+__device__ __forceinline__ GPtrC<T> gpc(const void* p) {
+  return GPtrC<T>{(const EECMG_G T*)p};
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -115,7 +161,7 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NV], double* __restr
 template <typename T, int RMAX>
 struct ConvGeneral {
   static constexpr int NT = 256, TW = kTW, TH = kTH, LW = kTW + 2 * RMAX, LH = kTH + 2 * RMAX, RC = RMAX;
-  static constexpr bool kRuntimeR = true;
+  static constexpr bool kRuntimeR = true, kStream = false;
   template <typename Emit>
   __device__ static __forceinline__ void conv(const T* __restrict__ tile, const T* __restrict__ taps, int R, int wave,
                                               int lane, Emit emit) {
@@ -145,65 +191,65 @@ struct ConvGeneral {
   }
 };
 
-// Sliding-column scheme shared by the separable and symmetric policies.  The
-// lane walks down its column one LDS row t at a time; row t feeds the outputs
-// v = t - R + a (a = R .. -R), so output v receives its first contribution at
-// t = v and is complete after t = v + 2R.  Exactly NW = 2R + 1 outputs are
-// pending at any time, so they live in a circular register buffer indexed by
-// v mod NW.  The row loop runs in groups of NW rows with the group body
-// unrolled: every register index is then a compile-time constant (no dynamic
-// VGPR indexing) whatever the tile height.  Rows past the tile only feed
-// outputs v >= TH, which are never emitted; the LDS tile is padded to whole
-// groups so those reads stay inside it.
+// Sliding-column scheme shared by the separable, symmetric and uniform-disk
+// policies.  The lane walks down its column one input row t at a time; row t
+// feeds the outputs v = t - R + a (a = R .. -R), so output v receives its
+// first contribution at t = v and is complete after t = v + 2R.  Exactly
+// NW = 2R + 1 outputs are pending at any time, so they live in a circular
+// register buffer indexed by v mod NW.  The row loop runs in groups of NW rows
+// with the group body unrolled: every register index is then a compile-time
+// constant (no dynamic VGPR indexing) whatever the strip height.
+//
+// A policy provides St (its taps and the pending outputs), init(St&, taps)
+// and step(St&, row, k): consume the input row whose centre element for the
+// lane is row[0] (row[b] is column offset b), with k = t mod NW, and return
+// output t - 2R (meaningful once t >= 2R).
 template <int R>
 struct Slide {
   static constexpr int NW = 2 * R + 1;
-  static constexpr int LH = kTH + 2 * R;
-  static constexpr int NG = (LH + NW - 1) / NW;
-  static constexpr int LH_PAD = NG * NW;
   static constexpr int slot(int k, int a) { return ((k - R + a) % NW + NW) % NW; }
+  // Materialise the pending outputs at the end of each row: keeps the
+  // compiler from deferring the additions (and every row filter feeding
+  // them) to the end of the unrolled group, which multiplies register use.
+  template <typename T>
+  __device__ static __forceinline__ void pin(T (&acc)[NW]) {
+#pragma unroll
+    for (int i = 0; i < NW; ++i) asm volatile("" : "+v"(acc[i]));
+  }
 };
 
 // Rank-one PSF psf(a,b) = col(a) row(b) (the Gaussian of Section 5 and its
-// coarse levels).  For each LDS row the lane forms the horizontal filter
+// coarse levels).  For each input row the lane forms the horizontal filter
 // h = sum_b row(b) x(., j-b) once and adds col(a) h to the pending outputs.
 // Taps: row(-R..R) followed by col(-R..R).
 template <typename T, int R>
 struct ConvSep {
   using S = Slide<R>;
-  static constexpr int NT = 64, TW = kTW, TH = kTH, LW = kTW + 2 * R, LH = S::LH_PAD, RC = R;
-  static constexpr bool kRuntimeR = false;
-  template <typename Emit>
-  __device__ static __forceinline__ void conv(const T* __restrict__ tile, const T* __restrict__ taps, int, int,
-                                              int lane, Emit emit) {
-    constexpr int NW = S::NW;
-    T rw[NW], cl[NW];
+  static constexpr int NT = 64, TW = kTW, TH = strip_th(R), LW = kTW + 2 * R, RC = R;
+  static constexpr bool kRuntimeR = false, kStream = true;
+  struct St {
+    T rw[S::NW], cl[S::NW], acc[S::NW];
+  };
+  __device__ static __forceinline__ void init(St& s, const T* __restrict__ taps) {
 #pragma unroll
-    for (int k = 0; k < NW; ++k) {
-      rw[k] = taps[k];
-      cl[k] = taps[NW + k];
+    for (int k = 0; k < S::NW; ++k) {
+      s.rw[k] = taps[k];
+      s.cl[k] = taps[S::NW + k];
     }
-    T acc[NW];
-#pragma unroll 1
-    for (int gi = 0; gi < S::NG; ++gi) {
+  }
+  __device__ static __forceinline__ T step(St& s, const T* __restrict__ row, int k) {
+    T h = s.rw[0] * row[R];
 #pragma unroll
-      for (int k = 0; k < NW; ++k) {
-        const int t = gi * NW + k;
-        const T* __restrict__ row = tile + t * LW + lane + R;
-        T h = rw[0] * row[R];
+    for (int b = -R + 1; b <= R; ++b) h = fma(s.rw[b + R], row[-b], h);
 #pragma unroll
-        for (int b = -R + 1; b <= R; ++b) h = fma(rw[b + R], row[-b], h);
-#pragma unroll
-        for (int a = R; a >= -R; --a) {
-          if (a == R)
-            acc[S::slot(k, a)] = cl[a + R] * h;
-          else
-            acc[S::slot(k, a)] = fma(cl[a + R], h, acc[S::slot(k, a)]);
-        }
-        const int vd = t - 2 * R;
-        if (vd >= 0 && vd < TH) emit(vd, acc[S::slot(k, -R)]);
-      }
+    for (int a = R; a >= -R; --a) {
+      if (a == R)
+        s.acc[S::slot(k, a)] = s.cl[a + R] * h;
+      else
+        s.acc[S::slot(k, a)] = fma(s.cl[a + R], h, s.acc[S::slot(k, a)]);
     }
+    S::pin(s.acc);
+    return s.acc[S::slot(k, -R)];
   }
 };
 
@@ -222,59 +268,83 @@ constexpr int sym_offset(int R, bool disk, int a) {
 constexpr int sym_ntaps(int R, bool disk) { return sym_offset(R, disk, R + 1); }
 
 // PSF symmetric under both axis reflections, psf(a,b) = psf(-a,b) = psf(a,-b),
-// with square or disk support (the out-of-focus disk of the 4096^2
-// workload).  Rows a and -a share one horizontal "row filter"
+// with square or disk support.  Rows a and -a share one horizontal "row
+// filter"
 //   h_a = psf(a,0) x(j) + sum_{b>=1} psf(a,b) (x(j-b) + x(j+b)),
-// computed once per LDS row from the pair sums and added to the outputs a
+// computed once per input row from the pair sums and added to the outputs a
 // rows below and above: about (R+1)(R+2)/2 + 2R ops per row and pixel
 // instead of (2R+1)^2 FMAs.  Taps: the quadrant a, b >= 0, row by row
 // (b = 0..span(a)).
 template <typename T, int R, bool DISK>
 struct ConvSym {
   using S = Slide<R>;
-  static constexpr int NT = 64, TW = kTW, TH = kTH, LW = kTW + 2 * R, LH = S::LH_PAD, RC = R;
-  static constexpr bool kRuntimeR = false;
+  static constexpr int NT = 64, TW = kTW, TH = strip_th(R), LW = kTW + 2 * R, RC = R;
+  static constexpr bool kRuntimeR = false, kStream = true;
   static constexpr int NTAPS = sym_ntaps(R, DISK);
-  template <typename Emit>
-  __device__ static __forceinline__ void conv(const T* __restrict__ tile, const T* __restrict__ taps, int, int,
-                                              int lane, Emit emit) {
-    constexpr int NW = S::NW;
-    T wt[NTAPS];
+  struct St {
+    T wt[NTAPS], acc[S::NW];
+  };
+  __device__ static __forceinline__ void init(St& s, const T* __restrict__ taps) {
 #pragma unroll
-    for (int k = 0; k < NTAPS; ++k) wt[k] = taps[k];
-    T acc[NW];
-#pragma unroll 1
-    for (int gi = 0; gi < S::NG; ++gi) {
+    for (int k = 0; k < NTAPS; ++k) s.wt[k] = taps[k];
+  }
+  __device__ static __forceinline__ T step(St& s, const T* __restrict__ row, int k) {
+    const T x0 = row[0];
+    T pr[R + 1];
 #pragma unroll
-      for (int k = 0; k < NW; ++k) {
-        const int t = gi * NW + k;
-        const T* __restrict__ row = tile + t * LW + lane + R;
-        const T x0 = row[0];
-        T pr[R + 1];
+    for (int b = 1; b <= R; ++b) pr[b] = row[b] + row[-b];
+    T h[R + 1];
 #pragma unroll
-        for (int b = 1; b <= R; ++b) pr[b] = row[b] + row[-b];
-        T h[R + 1];
+    for (int a = 0; a <= R; ++a) {
+      const int o = sym_offset(R, DISK, a);
+      T v = s.wt[o] * x0;
 #pragma unroll
-        for (int a = 0; a <= R; ++a) {
-          const int o = sym_offset(R, DISK, a);
-          T v = wt[o] * x0;
-#pragma unroll
-          for (int b = 1; b <= R; ++b)
-            if (b <= sym_span(R, DISK, a)) v = fma(wt[o + b], pr[b], v);
-          h[a] = v;
-        }
-#pragma unroll
-        for (int a = R; a >= -R; --a) {
-          const T hv = h[a >= 0 ? a : -a];
-          if (a == R)
-            acc[S::slot(k, a)] = hv;
-          else
-            acc[S::slot(k, a)] = acc[S::slot(k, a)] + hv;
-        }
-        const int vd = t - 2 * R;
-        if (vd >= 0 && vd < TH) emit(vd, acc[S::slot(k, -R)]);
-      }
+      for (int b = 1; b <= R; ++b)
+        if (b <= sym_span(R, DISK, a)) v = fma(s.wt[o + b], pr[b], v);
+      h[a] = v;
     }
+#pragma unroll
+    for (int a = R; a >= -R; --a) {
+      const T hv = h[a >= 0 ? a : -a];
+      if (a == R)
+        s.acc[S::slot(k, a)] = hv;
+      else
+        s.acc[S::slot(k, a)] = s.acc[S::slot(k, a)] + hv;
+    }
+    S::pin(s.acc);
+    return s.acc[S::slot(k, -R)];
+  }
+};
+
+// Uniform disk, psf(a,b) = w for a^2 + b^2 <= R^2 (the out-of-focus blur of
+// the experiments): the row filter of offset a is a plain sum over the span
+// |b| <= span(a).  The spans are nested, so one running sum of the pair sums
+// gives every row filter: 2R adds per input row instead of one FMA per tap,
+// and the weight is applied once per output.  Taps: {w}.
+template <typename T, int R>
+struct ConvBox {
+  using S = Slide<R>;
+  static constexpr int NT = 64, TW = kTW, TH = strip_th(R), LW = kTW + 2 * R, RC = R;
+  static constexpr bool kRuntimeR = false, kStream = true;
+  struct St {
+    T w, acc[S::NW];
+  };
+  __device__ static __forceinline__ void init(St& s, const T* __restrict__ taps) { s.w = taps[0]; }
+  __device__ static __forceinline__ T step(St& s, const T* __restrict__ row, int k) {
+    T cum[R + 1];
+    cum[0] = row[0];
+#pragma unroll
+    for (int b = 1; b <= R; ++b) cum[b] = cum[b - 1] + (row[b] + row[-b]);
+#pragma unroll
+    for (int a = R; a >= -R; --a) {
+      const T hv = cum[sym_span(R, true, a >= 0 ? a : -a)];
+      if (a == R)
+        s.acc[S::slot(k, a)] = hv;
+      else
+        s.acc[S::slot(k, a)] = s.acc[S::slot(k, a)] + hv;
+    }
+    S::pin(s.acc);
+    return s.w * s.acc[S::slot(k, -R)];
   }
 };
 
@@ -301,51 +371,22 @@ __device__ __forceinline__ TileGeo tile_geo(const JobDesc& d, int t) {
   return g;
 }
 
-// Load tile + halo: every tile element in the image gets combine(load(o)),
-// elements outside the image are zero (the operator's zero boundary
-// condition); o is the element's 32-bit offset in the level's pitched array.
-// For compile-time radii the loop is fully unrolled in two phases: every
-// global load is issued first, from an address clamped into the image (always
-// valid), then the values are combined (branch-free) and written to LDS, so a
-// wave keeps dozens of loads in flight instead of waiting row by row.
+// Load tile + halo (general policy): every tile element in the image gets
+// combine(load(o)), elements outside the image are zero (the operator's zero
+// boundary condition); o is the element's 32-bit offset in the level's
+// pitched array.
 template <typename T, typename P, typename LoadF, typename CombF>
 __device__ __forceinline__ void load_tile(T* __restrict__ tile, const TileGeo& g, LoadF load, CombF combine) {
-  if constexpr (P::kRuntimeR) {
-    const int R = g.R;
-    constexpr int NWV = P::NT / 64;
-    for (int ly = g.wave; ly < P::TH + 2 * R; ly += NWV) {
-      const int gy = g.y0 - R + ly;
-      const bool row_in = gy >= 0 && gy < g.h;
-      for (int lx = g.lane; lx < P::TW + 2 * R; lx += 64) {
-        const int gx = g.x0 - R + lx;
-        T v = T(0);
-        if (row_in && gx >= 0 && gx < g.w) v = combine(load((unsigned)(gy * g.pitch + gx)));
-        tile[ly * P::LW + lx] = v;
-      }
-    }
-  } else {
-    constexpr int R = P::RC, LWr = P::TW + 2 * R, N = LWr * (P::TH + 2 * R);
-    constexpr int IT = (N + P::NT - 1) / P::NT;
-    using V = decltype(load(0u));
-    V vals[IT];
-#pragma unroll
-    for (int k = 0; k < IT; ++k) {
-      const int idx = (int)threadIdx.x + k * P::NT;
-      const int ly = idx / LWr, lx = idx - ly * LWr;
-      const int gy = min(max(g.y0 - R + ly, 0), g.h - 1);
-      const int gx = min(max(g.x0 - R + lx, 0), g.w - 1);
-      vals[k] = load((unsigned)(gy * g.pitch + gx));
-    }
-#pragma unroll
-    for (int k = 0; k < IT; ++k) {
-      const int idx = (int)threadIdx.x + k * P::NT;
-      if (k < IT - 1 || idx < N) {
-        const int ly = idx / LWr, lx = idx - ly * LWr;
-        const int gy = g.y0 - R + ly, gx = g.x0 - R + lx;
-        const bool ok = gy >= 0 && gy < g.h && gx >= 0 && gx < g.w;
-        const T v = combine(vals[k]);
-        tile[ly * P::LW + lx] = ok ? v : T(0);
-      }
+  const int R = g.R;
+  constexpr int NWV = P::NT / 64;
+  for (int ly = g.wave; ly < P::TH + 2 * R; ly += NWV) {
+    const int gy = g.y0 - R + ly;
+    const bool row_in = gy >= 0 && gy < g.h;
+    for (int lx = g.lane; lx < P::TW + 2 * R; lx += 64) {
+      const int gx = g.x0 - R + lx;
+      T v = T(0);
+      if (row_in && gx >= 0 && gx < g.w) v = combine(load((unsigned)(gy * g.pitch + gx)));
+      tile[ly * P::LW + lx] = v;
     }
   }
 }
@@ -393,6 +434,118 @@ __device__ __forceinline__ int pol_R(const TileGeo& g) {
 }
 
 // ---------------------------------------------------------------------------
+// Streaming strips (sliding-column policies).  A wave owns the 64-column x
+// TH-row output strip of its tile and walks once down the input rows
+// y0 - R .. y0 + TH + R - 1.  Lane l holds input column x0 - R + l and, for
+// l < 2R, also x0 + 64 - R + l.  Each row's global loads are issued kPrefetch
+// rows ahead into a register ring; the combined row is written to a two-row
+// LDS buffer (64 + 2R columns) from which every lane reads its 2R + 1 window
+// columns, so LDS holds one row per wave and occupancy is set by registers.
+// Callbacks:
+//   load_in(o) -> VI      raw input at offset o (clamped, always valid)
+//   combine(VI) -> T      conv input value (zero outside the image is applied
+//                         by the driver)
+//   load_int(o) -> VN     extra data at the interior pixel of the lane
+//   interior(o, v, in, n) input row inside the strip: v is the combined value
+//                         at the lane's interior column (the column whose value
+//                         the lane holds: x0 - R + l for l >= R, else
+//                         x0 + 64 - R + l), o its offset, in = inside image
+//   load_em(o) -> VE      extra data at the lane's output pixel
+//   emit(o, acc, in, c, e) output row done at column x0 + l: acc = (H x), c =
+//                         the combined input at that same pixel
+// ---------------------------------------------------------------------------
+struct NoLoad {};
+struct NoLoadF {
+  __device__ NoLoad operator()(unsigned) const { return NoLoad{}; }
+};
+struct NoInterior {
+  template <typename T>
+  __device__ void operator()(unsigned, T, bool, NoLoad) const {}
+};
+
+constexpr int kPrefetch = 2;
+
+// none: the out-of-range element offset of the level's arrays (h x pitch).
+// Loads at none return 0 (combine(0) must be 0, the zero boundary), and
+// interior/emit receive none as the offset of pixels outside the image, so
+// their stores are dropped; `in` tells the callbacks which pixels count.
+template <typename T, typename P, typename InF, typename CombF, typename IntLoadF, typename IntF, typename EmLoadF,
+          typename EmF>
+__device__ __forceinline__ void stream_strip(const TileGeo& g, unsigned none, typename P::St& st, InF load_in,
+                                             CombF combine, IntLoadF load_int, IntF interior, EmLoadF load_em,
+                                             EmF emit) {
+  constexpr int R = P::RC, NW = 2 * R + 1, GS = strip_group(R), TH = P::TH, LH = TH + 2 * R, NG = LH / GS;
+  constexpr int LW = kTW + 2 * R;
+  static_assert(NG * GS == LH && GS % NW == 0, "strip height must fill whole row groups");
+  constexpr int D = GS < kPrefetch ? GS : kPrefetch;
+  constexpr int RW = 2 * kTW;  // row buffer width: every lane writes both of its values
+  static_assert(LW <= RW, "row buffer too narrow");
+  __shared__ T rowbuf[2 * RW];
+  using VI = decltype(load_in(0u));
+  using VN = decltype(load_int(0u));
+  using VE = decltype(load_em(0u));
+  const int lane = g.lane;
+  const bool has2 = lane < 2 * R;
+  const int c1 = g.x0 - R + lane, c2 = g.x0 + kTW - R + lane;
+  const bool in1 = c1 >= 0 && c1 < g.w, in2 = has2 && c2 < g.w;
+  const int ic = lane >= R ? c1 : c2;  // >= x0
+  const bool inic = ic < g.w;
+  const int ec = g.x0 + lane;
+  const bool inec = ec < g.w;
+  VI pa[GS], pb[GS];
+  VN pn[GS];
+  VE pe[GS];
+  T cen[NW];
+  // Row offsets are uniform; a row outside the image (or past the strip)
+  // maps every lane to none.
+  auto issue = [&](int t, VI& a, VI& b, VN& n, VE& e) {
+    const int y = g.y0 - R + t;
+    const bool row_ok = t < LH && y >= 0 && y < g.h;
+    const unsigned base = (unsigned)(y * g.pitch);
+    a = load_in((row_ok && in1) ? base + (unsigned)c1 : none);
+    b = load_in((row_ok && in2) ? base + (unsigned)c2 : none);
+    n = load_int((row_ok && t >= R && t < R + TH && inic) ? base + (unsigned)ic : none);
+    const int yo = y - R;
+    const bool emit_ok = t >= 2 * R && t < LH && yo < g.h;
+    e = load_em((emit_ok && inec) ? (unsigned)(yo * g.pitch + ec) : none);
+  };
+#pragma unroll
+  for (int t = 0; t < D; ++t) issue(t, pa[t], pb[t], pn[t], pe[t]);
+#pragma unroll 1
+  for (int gi = 0; gi < NG; ++gi) {
+#pragma unroll
+    for (int kg = 0; kg < GS; ++kg) {
+      const int t = gi * GS + kg, k = kg % NW;  // k = t mod NW
+      const VI a = pa[kg], b = pb[kg];
+      const VN n = pn[kg];
+      const VE e = pe[kg];
+      issue(t + D, pa[(kg + D) % GS], pb[(kg + D) % GS], pn[(kg + D) % GS], pe[(kg + D) % GS]);
+      const int y = g.y0 - R + t;
+      const T v1 = combine(a);
+      const T v2 = combine(b);
+      T* rb = rowbuf + (t & 1) * RW;
+      rb[lane] = v1;
+      rb[kTW + lane] = v2;
+      // interior and emit run on every step (outside their rows with in =
+      // false and offset none), so no memory operation sits in a branch
+      {
+        const bool in = t >= R && t < R + TH && y < g.h && inic;
+        interior(in ? (unsigned)(y * g.pitch + ic) : none, lane >= R ? v1 : v2, in, n);
+      }
+      __syncthreads();
+      const T* row = rb + lane + R;
+      cen[k] = row[0];
+      const T out = P::step(st, row, k);
+      {
+        const int yo = g.y0 + t - 2 * R;
+        const bool in = t >= 2 * R && yo < g.h && inec;
+        emit(in ? (unsigned)(yo * g.pitch + ec) : none, out, in, cen[((k - R) % NW + NW) % NW], e);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Smoother pass kernels, templated on the element type and blur policy.
 // ---------------------------------------------------------------------------
 
@@ -404,53 +557,83 @@ struct Two {
 // r = g - H u0, stored in r[0]; partial <r,r> in slot 1.  (CGLS and MR)
 template <typename T, typename P>
 __global__ __launch_bounds__(P::NT) void k_init1(LaunchList ll, const JobDesc* __restrict__ descs) {
-  __shared__ T tile[P::LH * P::LW];
-  __shared__ T gsh[P::TH * P::TW];
   const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
   const JobDesc& d = descs[L.d];
   const TileGeo g = tile_geo<P>(d, L.t);
-  const auto* __restrict__ u = gpc<T>(d.u);
-  const auto* __restrict__ gg = gpc<T>(d.g);
-  auto* __restrict__ r = gp<T>(d.r[0]);
-  load_tile<T, P>(tile, g, [&](unsigned o) { return u[o]; }, [](T v) { return v; });
-  for_interior<P>(g, [&](unsigned o) { return gg[o]; }, [&](T v, unsigned, int row) { gsh[row * P::TW + g.lane] = v; });
-  __syncthreads();
+  const auto u = gpc<T>(d.u);
+  const auto gg = gpc<T>(d.g);
+  auto r = gp<T>(d.r[0]);
   double part[1] = {0.0};
-  const int gx = g.x0 + g.lane;
-  P::conv(tile, (const T*)d.taps, g.R, g.wave, g.lane, [&](int v, T acc) {
-    const int gy = g.y0 + v;
-    const T rv = gsh[v * P::TW + g.lane] - acc;
-    if (gy < g.h && gx < g.w) {
-      r[(unsigned)(gy * g.pitch + gx)] = rv;
-      part[0] += (double)rv * (double)rv;
-    }
-  });
+  if constexpr (P::kStream) {
+    typename P::St st;
+    P::init(st, (const T*)d.taps);
+    const unsigned n = (unsigned)(g.h * g.pitch);
+    const auto U = bview<T>(d.u, n), G = bview<T>(d.g, n), Rn = bview<T>(d.r[0], n);
+    stream_strip<T, P>(
+        g, n, st, [&](unsigned o) { return U.ld(o); }, [](T v) { return v; }, NoLoadF{}, NoInterior{},
+        [&](unsigned o) { return G.ld(o); },
+        [&](unsigned o, T acc, bool in, T, T gv) {
+          const T rv = gv - acc;
+          Rn.st(o, rv);
+          part[0] += in ? (double)rv * (double)rv : 0.0;
+        });
+  } else {
+    __shared__ T tile[P::LH * P::LW];
+    __shared__ T gsh[P::TH * P::TW];
+    load_tile<T, P>(tile, g, [&](unsigned o) { return u[o]; }, [](T v) { return v; });
+    for_interior<P>(g, [&](unsigned o) { return gg[o]; },
+                    [&](T v, unsigned, int row) { gsh[row * P::TW + g.lane] = v; });
+    __syncthreads();
+    const int gx = g.x0 + g.lane;
+    P::conv(tile, (const T*)d.taps, g.R, g.wave, g.lane, [&](int v, T acc) {
+      const int gy = g.y0 + v;
+      const T rv = gsh[v * P::TW + g.lane] - acc;
+      if (gy < g.h && gx < g.w) {
+        r[(unsigned)(gy * g.pitch + gx)] = rv;
+        part[0] += (double)rv * (double)rv;
+      }
+    });
+  }
   block_sum_store<P::NT, 1>(part, d.partials + (size_t)1 * d.pstride + L.t, d.pstride);
 }
 
 // s = H^T r, p[0] = s; partial <s,s> in slot 2.
 template <typename T, typename P>
 __global__ __launch_bounds__(P::NT) void k_cg_init2(LaunchList ll, const JobDesc* __restrict__ descs) {
-  __shared__ T tile[P::LH * P::LW];
   const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
   const JobDesc& d = descs[L.d];
   const TileGeo g = tile_geo<P>(d, L.t);
-  const auto* __restrict__ r = gpc<T>(d.r[0]);
-  auto* __restrict__ s = gp<T>(d.s);
-  auto* __restrict__ p = gp<T>(d.p[0]);
-  load_tile<T, P>(tile, g, [&](unsigned o) { return r[o]; }, [](T v) { return v; });
-  __syncthreads();
+  const auto r = gpc<T>(d.r[0]);
+  auto s = gp<T>(d.s);
+  auto p = gp<T>(d.p[0]);
   double part[1] = {0.0};
-  const int gx = g.x0 + g.lane;
-  P::conv(tile, (const T*)d.taps_t, g.R, g.wave, g.lane, [&](int v, T acc) {
-    const int gy = g.y0 + v;
-    if (gy < g.h && gx < g.w) {
-      const unsigned o = (unsigned)(gy * g.pitch + gx);
-      s[o] = acc;
-      p[o] = acc;
-      part[0] += (double)acc * (double)acc;
-    }
-  });
+  auto put = [&](unsigned o, T acc) {
+    s[o] = acc;
+    p[o] = acc;
+    part[0] += (double)acc * (double)acc;
+  };
+  if constexpr (P::kStream) {
+    typename P::St st;
+    P::init(st, (const T*)d.taps_t);
+    const unsigned n = (unsigned)(g.h * g.pitch);
+    const auto Rr = bview<T>(d.r[0], n), S = bview<T>(d.s, n), Pp = bview<T>(d.p[0], n);
+    stream_strip<T, P>(
+        g, n, st, [&](unsigned o) { return Rr.ld(o); }, [](T v) { return v; }, NoLoadF{}, NoInterior{}, NoLoadF{},
+        [&](unsigned o, T acc, bool in, T, NoLoad) {
+          S.st(o, acc);
+          Pp.st(o, acc);
+          part[0] += in ? (double)acc * (double)acc : 0.0;
+        });
+  } else {
+    __shared__ T tile[P::LH * P::LW];
+    load_tile<T, P>(tile, g, [&](unsigned o) { return r[o]; }, [](T v) { return v; });
+    __syncthreads();
+    const int gx = g.x0 + g.lane;
+    P::conv(tile, (const T*)d.taps_t, g.R, g.wave, g.lane, [&](int v, T acc) {
+      const int gy = g.y0 + v;
+      if (gy < g.h && gx < g.w) put((unsigned)(gy * g.pitch + gx), acc);
+    });
+  }
   block_sum_store<P::NT, 1>(part, d.partials + (size_t)2 * d.pstride + L.t, d.pstride);
 }
 
@@ -458,7 +641,6 @@ __global__ __launch_bounds__(P::NT) void k_cg_init2(LaunchList ll, const JobDesc
 // partial <q,q> in slot 0.
 template <typename T, typename P>
 __global__ __launch_bounds__(P::NT) void k_cg_a(LaunchList ll, const JobDesc* __restrict__ descs) {
-  __shared__ T tile[P::LH * P::LW];
   const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
   const JobDesc& d = descs[L.d];
   const SolverState* st = d.st;
@@ -466,25 +648,42 @@ __global__ __launch_bounds__(P::NT) void k_cg_a(LaunchList ll, const JobDesc* __
   const TileGeo g = tile_geo<P>(d, L.t);
   const int par = uni(st->par);
   const T beta = (T)st->beta;
-  const auto* __restrict__ s = gpc<T>(d.s);
-  const auto* __restrict__ po = gpc<T>(d.p[par]);
-  auto* __restrict__ pn = gp<T>(d.p[par ^ 1]);
-  auto* __restrict__ q = gp<T>(d.q[0]);
-  load_tile<T, P>(
-      tile, g, [&](unsigned o) { return Two<T>{s[o], po[o]}; }, [&](Two<T> x) { return fma(beta, x.b, x.a); });
-  __syncthreads();
-  tile_interior<T, P>(tile, g, pol_R<P>(g), [&](T v, unsigned o, bool in) {
-    if (in) pn[o] = v;
-  });
+  const auto s = gpc<T>(d.s);
+  const auto po = gpc<T>(d.p[par]);
+  auto pn = gp<T>(d.p[par ^ 1]);
+  auto q = gp<T>(d.q[0]);
   double part[1] = {0.0};
-  const int gx = g.x0 + g.lane;
-  P::conv(tile, (const T*)d.taps, g.R, g.wave, g.lane, [&](int v, T acc) {
-    const int gy = g.y0 + v;
-    if (gy < g.h && gx < g.w) {
-      q[(unsigned)(gy * g.pitch + gx)] = acc;
-      part[0] += (double)acc * (double)acc;
-    }
-  });
+  auto load = [&](unsigned o) { return Two<T>{s[o], po[o]}; };
+  auto comb = [&](Two<T> x) { return fma(beta, x.b, x.a); };
+  if constexpr (P::kStream) {
+    typename P::St ps;
+    P::init(ps, (const T*)d.taps);
+    const unsigned n = (unsigned)(g.h * g.pitch);
+    const auto S = bview<T>(d.s, n), Po = bview<T>(d.p[par], n), Pn = bview<T>(d.p[par ^ 1], n);
+    const auto Q = bview<T>(d.q[0], n);
+    stream_strip<T, P>(
+        g, n, ps, [&](unsigned o) { return Two<T>{S.ld(o), Po.ld(o)}; }, comb, NoLoadF{},
+        [&](unsigned o, T v, bool, NoLoad) { Pn.st(o, v); }, NoLoadF{},
+        [&](unsigned o, T acc, bool in, T, NoLoad) {
+          Q.st(o, acc);
+          part[0] += in ? (double)acc * (double)acc : 0.0;
+        });
+  } else {
+    __shared__ T tile[P::LH * P::LW];
+    load_tile<T, P>(tile, g, load, comb);
+    __syncthreads();
+    tile_interior<T, P>(tile, g, pol_R<P>(g), [&](T v, unsigned o, bool in) {
+      if (in) pn[o] = v;
+    });
+    const int gx = g.x0 + g.lane;
+    P::conv(tile, (const T*)d.taps, g.R, g.wave, g.lane, [&](int v, T acc) {
+      const int gy = g.y0 + v;
+      if (gy < g.h && gx < g.w) {
+        q[(unsigned)(gy * g.pitch + gx)] = acc;
+        part[0] += (double)acc * (double)acc;
+      }
+    });
+  }
   block_sum_store<P::NT, 1>(part, d.partials + (size_t)0 * d.pstride + L.t, d.pstride);
 }
 
@@ -492,7 +691,6 @@ __global__ __launch_bounds__(P::NT) void k_cg_a(LaunchList ll, const JobDesc* __
 // s = H^T r_new; partials <r,r> (slot 1) and <s,s> (slot 2).
 template <typename T, typename P>
 __global__ __launch_bounds__(P::NT) void k_cg_b(LaunchList ll, const JobDesc* __restrict__ descs) {
-  __shared__ T tile[P::LH * P::LW];
   const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
   const JobDesc& d = descs[L.d];
   const SolverState* st = d.st;
@@ -500,31 +698,54 @@ __global__ __launch_bounds__(P::NT) void k_cg_b(LaunchList ll, const JobDesc* __
   const TileGeo g = tile_geo<P>(d, L.t);
   const int par = uni(st->par);
   const T alpha = (T)st->alpha;
-  const auto* __restrict__ ro = gpc<T>(d.r[par]);
-  auto* __restrict__ rn = gp<T>(d.r[par ^ 1]);
-  const auto* __restrict__ q = gpc<T>(d.q[0]);
-  const auto* __restrict__ pn = gpc<T>(d.p[par ^ 1]);
-  auto* __restrict__ u = gp<T>(d.u);
-  auto* __restrict__ s = gp<T>(d.s);
+  const auto ro = gpc<T>(d.r[par]);
+  auto rn = gp<T>(d.r[par ^ 1]);
+  const auto q = gpc<T>(d.q[0]);
+  const auto pn = gpc<T>(d.p[par ^ 1]);
+  auto u = gp<T>(d.u);
+  auto s = gp<T>(d.s);
   double part[2] = {0.0, 0.0};
-  load_tile<T, P>(
-      tile, g, [&](unsigned o) { return Two<T>{ro[o], q[o]}; }, [&](Two<T> x) { return fma(-alpha, x.b, x.a); });
-  for_interior<P>(
-      g, [&](unsigned o) { return Two<T>{u[o], pn[o]}; },
-      [&](Two<T> x, unsigned o, int) { u[o] = fma(alpha, x.b, x.a); });
-  __syncthreads();
-  tile_interior<T, P>(tile, g, pol_R<P>(g), [&](T v, unsigned o, bool in) {
-    if (in) rn[o] = v;
-    part[0] += in ? (double)v * (double)v : 0.0;
-  });
-  const int gx = g.x0 + g.lane;
-  P::conv(tile, (const T*)d.taps_t, g.R, g.wave, g.lane, [&](int v, T acc) {
-    const int gy = g.y0 + v;
-    if (gy < g.h && gx < g.w) {
-      s[(unsigned)(gy * g.pitch + gx)] = acc;
-      part[1] += (double)acc * (double)acc;
-    }
-  });
+  auto load = [&](unsigned o) { return Two<T>{ro[o], q[o]}; };
+  auto comb = [&](Two<T> x) { return fma(-alpha, x.b, x.a); };
+  if constexpr (P::kStream) {
+    typename P::St ps;
+    P::init(ps, (const T*)d.taps_t);
+    const unsigned n = (unsigned)(g.h * g.pitch);
+    const auto Ro = bview<T>(d.r[par], n), Rn = bview<T>(d.r[par ^ 1], n), Q = bview<T>(d.q[0], n);
+    const auto Pn = bview<T>(d.p[par ^ 1], n), U = bview<T>(d.u, n), S = bview<T>(d.s, n);
+    stream_strip<T, P>(
+        g, n, ps, [&](unsigned o) { return Two<T>{Ro.ld(o), Q.ld(o)}; }, comb,
+        [&](unsigned o) { return Two<T>{U.ld(o), Pn.ld(o)}; },
+        [&](unsigned o, T v, bool in, Two<T> x) {
+          Rn.st(o, v);
+          U.st(o, fma(alpha, x.b, x.a));
+          part[0] += in ? (double)v * (double)v : 0.0;
+        },
+        NoLoadF{},
+        [&](unsigned o, T acc, bool in, T, NoLoad) {
+          S.st(o, acc);
+          part[1] += in ? (double)acc * (double)acc : 0.0;
+        });
+  } else {
+    __shared__ T tile[P::LH * P::LW];
+    load_tile<T, P>(tile, g, load, comb);
+    for_interior<P>(
+        g, [&](unsigned o) { return Two<T>{u[o], pn[o]}; },
+        [&](Two<T> x, unsigned o, int) { u[o] = fma(alpha, x.b, x.a); });
+    __syncthreads();
+    tile_interior<T, P>(tile, g, pol_R<P>(g), [&](T v, unsigned o, bool in) {
+      if (in) rn[o] = v;
+      part[0] += in ? (double)v * (double)v : 0.0;
+    });
+    const int gx = g.x0 + g.lane;
+    P::conv(tile, (const T*)d.taps_t, g.R, g.wave, g.lane, [&](int v, T acc) {
+      const int gy = g.y0 + v;
+      if (gy < g.h && gx < g.w) {
+        s[(unsigned)(gy * g.pitch + gx)] = acc;
+        part[1] += (double)acc * (double)acc;
+      }
+    });
+  }
   block_sum_store<P::NT, 2>(part, d.partials + (size_t)1 * d.pstride + L.t, d.pstride);
 }
 
@@ -532,46 +753,78 @@ __global__ __launch_bounds__(P::NT) void k_cg_b(LaunchList ll, const JobDesc* __
 // then q_new = H r_new.  Partials <r_new,q_new> (0), <r_new,r_new> (1), <q,q> (2).
 template <typename T, typename P>
 __global__ __launch_bounds__(P::NT) void k_mr_pass(LaunchList ll, const JobDesc* __restrict__ descs) {
-  __shared__ T tile[P::LH * P::LW];
   const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
   const JobDesc& d = descs[L.d];
   const SolverState* st = d.st;
   if (__builtin_amdgcn_readfirstlane(st->done)) return;
   const TileGeo g = tile_geo<P>(d, L.t);
-  const int R = pol_R<P>(g);
   const int par = uni(st->par);
   const bool pending = uni(st->pending) != 0;
   const T alpha = pending ? (T)st->alpha : T(0);
-  const auto* __restrict__ ro = gpc<T>(d.r[par]);
-  const auto* __restrict__ qo = gpc<T>(d.q[par]);
-  auto* __restrict__ rn = gp<T>(d.r[par ^ 1]);
-  auto* __restrict__ qn = gp<T>(d.q[par ^ 1]);
-  auto* __restrict__ u = gp<T>(d.u);
+  const auto ro = gpc<T>(d.r[par]);
+  const auto qo = gpc<T>(d.q[par]);
+  auto rn = gp<T>(d.r[par ^ 1]);
+  auto qn = gp<T>(d.q[par ^ 1]);
+  auto u = gp<T>(d.u);
   double part[3] = {0.0, 0.0, 0.0};
-  if (pending) {
-    load_tile<T, P>(
-        tile, g, [&](unsigned o) { return Two<T>{ro[o], qo[o]}; }, [&](Two<T> x) { return fma(-alpha, x.b, x.a); });
-    for_interior<P>(
-        g, [&](unsigned o) { return Two<T>{u[o], ro[o]}; },
-        [&](Two<T> x, unsigned o, int) { u[o] = fma(alpha, x.b, x.a); });
-  } else {
-    load_tile<T, P>(tile, g, [&](unsigned o) { return ro[o]; }, [](T v) { return v; });
-  }
-  __syncthreads();
-  tile_interior<T, P>(tile, g, R, [&](T v, unsigned o, bool in) {
-    if (in) rn[o] = v;
-    part[1] += in ? (double)v * (double)v : 0.0;
-  });
-  const int gx = g.x0 + g.lane;
-  P::conv(tile, (const T*)d.taps, g.R, g.wave, g.lane, [&](int v, T acc) {
-    const int gy = g.y0 + v;
-    if (gy < g.h && gx < g.w) {
-      qn[(unsigned)(gy * g.pitch + gx)] = acc;
-      const T rc = tile[(v + R) * P::LW + g.lane + R];
-      part[0] += (double)rc * (double)acc;
-      part[2] += (double)acc * (double)acc;
+  if constexpr (P::kStream) {
+    typename P::St ps;
+    P::init(ps, (const T*)d.taps);
+    const unsigned n = (unsigned)(g.h * g.pitch);
+    const auto Ro = bview<T>(d.r[par], n), Qo = bview<T>(d.q[par], n), Rn = bview<T>(d.r[par ^ 1], n);
+    const auto Qn = bview<T>(d.q[par ^ 1], n), U = bview<T>(d.u, n);
+    auto emit = [&](unsigned o, T acc, bool in, T rc, NoLoad) {
+      Qn.st(o, acc);
+      part[0] += in ? (double)rc * (double)acc : 0.0;
+      part[2] += in ? (double)acc * (double)acc : 0.0;
+    };
+    if (pending) {
+      stream_strip<T, P>(
+          g, n, ps, [&](unsigned o) { return Two<T>{Ro.ld(o), Qo.ld(o)}; },
+          [&](Two<T> x) { return fma(-alpha, x.b, x.a); }, [&](unsigned o) { return Two<T>{U.ld(o), Ro.ld(o)}; },
+          [&](unsigned o, T v, bool in, Two<T> x) {
+            Rn.st(o, v);
+            U.st(o, fma(alpha, x.b, x.a));
+            part[1] += in ? (double)v * (double)v : 0.0;
+          },
+          NoLoadF{}, emit);
+    } else {
+      stream_strip<T, P>(
+          g, n, ps, [&](unsigned o) { return Ro.ld(o); }, [](T v) { return v; }, NoLoadF{},
+          [&](unsigned o, T v, bool in, NoLoad) {
+            Rn.st(o, v);
+            part[1] += in ? (double)v * (double)v : 0.0;
+          },
+          NoLoadF{}, emit);
     }
-  });
+  } else {
+    __shared__ T tile[P::LH * P::LW];
+    const int R = pol_R<P>(g);
+    if (pending) {
+      load_tile<T, P>(
+          tile, g, [&](unsigned o) { return Two<T>{ro[o], qo[o]}; }, [&](Two<T> x) { return fma(-alpha, x.b, x.a); });
+      for_interior<P>(
+          g, [&](unsigned o) { return Two<T>{u[o], ro[o]}; },
+          [&](Two<T> x, unsigned o, int) { u[o] = fma(alpha, x.b, x.a); });
+    } else {
+      load_tile<T, P>(tile, g, [&](unsigned o) { return ro[o]; }, [](T v) { return v; });
+    }
+    __syncthreads();
+    tile_interior<T, P>(tile, g, R, [&](T v, unsigned o, bool in) {
+      if (in) rn[o] = v;
+      part[1] += in ? (double)v * (double)v : 0.0;
+    });
+    const int gx = g.x0 + g.lane;
+    P::conv(tile, (const T*)d.taps, g.R, g.wave, g.lane, [&](int v, T acc) {
+      const int gy = g.y0 + v;
+      if (gy < g.h && gx < g.w) {
+        qn[(unsigned)(gy * g.pitch + gx)] = acc;
+        const T rc = tile[(v + R) * P::LW + g.lane + R];
+        part[0] += (double)rc * (double)acc;
+        part[2] += (double)acc * (double)acc;
+      }
+    });
+  }
   block_sum_store<P::NT, 3>(part, d.partials + (size_t)0 * d.pstride + L.t, d.pstride);
 }
 
@@ -579,7 +832,6 @@ __global__ __launch_bounds__(P::NT) void k_mr_pass(LaunchList ll, const JobDesc*
 template <typename T, typename P>
 __global__ __launch_bounds__(P::NT) void k_op_conv(const T* __restrict__ x, T* __restrict__ y, int H, int W,
                                                    const T* __restrict__ taps, int R) {
-  __shared__ T tile[P::LH * P::LW];
   const int tiles_x = (W + P::TW - 1) / P::TW;
   TileGeo g;
   g.R = R;
@@ -590,13 +842,26 @@ __global__ __launch_bounds__(P::NT) void k_op_conv(const T* __restrict__ x, T* _
   g.x0 = (blockIdx.x % tiles_x) * P::TW;
   g.wave = uni(threadIdx.x >> 6);
   g.lane = threadIdx.x & 63;
-  load_tile<T, P>(tile, g, [&](unsigned o) { return x[o]; }, [](T v) { return v; });
-  __syncthreads();
-  const int gx = g.x0 + g.lane;
-  P::conv(tile, taps, R, g.wave, g.lane, [&](int v, T acc) {
-    const int gy = g.y0 + v;
-    if (gy < H && gx < W) y[(unsigned)(gy * W + gx)] = acc;
-  });
+  const auto xg = gpc<T>(x);
+  auto yg = gp<T>(y);
+  if constexpr (P::kStream) {
+    typename P::St st;
+    P::init(st, taps);
+    const unsigned n = (unsigned)(H * W);
+    const auto X = bview<T>(x, n), Y = bview<T>(y, n);
+    stream_strip<T, P>(
+        g, n, st, [&](unsigned o) { return X.ld(o); }, [](T v) { return v; }, NoLoadF{}, NoInterior{}, NoLoadF{},
+        [&](unsigned o, T acc, bool, T, NoLoad) { Y.st(o, acc); });
+  } else {
+    __shared__ T tile[P::LH * P::LW];
+    load_tile<T, P>(tile, g, [&](unsigned o) { return xg[o]; }, [](T v) { return v; });
+    __syncthreads();
+    const int gx = g.x0 + g.lane;
+    P::conv(tile, taps, R, g.wave, g.lane, [&](int v, T acc) {
+      const int gy = g.y0 + v;
+      if (gy < H && gx < W) yg[(unsigned)(gy * W + gx)] = acc;
+    });
+  }
 }
 
 // Dispatch of one smoother stage for one policy.

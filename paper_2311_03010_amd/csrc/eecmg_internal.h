@@ -130,7 +130,22 @@ enum XBuf : int32_t { kBufU = 0, kBufT1 = 1, kBufT2 = 2, kBufUB = 3 };
 
 // Blur-operator implementation families.  A variant id is kind * 100 + R
 // (for kConvGeneral, R is the radius class 3, 6 or 12).
-enum ConvKind : int32_t { kConvGeneral = 0, kConvSep = 1, kConvSymSquare = 2, kConvSymDisk = 3 };
+enum ConvKind : int32_t { kConvGeneral = 0, kConvSep = 1, kConvSymSquare = 2, kConvSymDisk = 3, kConvBoxDisk = 4 };
+
+// Rows per unrolled group of the streaming (sliding-column) families: a
+// multiple of 2R + 1 (the pending-output ring) of at least 4 rows (the
+// prefetch ring).  Output rows per tile: the smallest height >= kTH whose
+// input rows (height + 2R) fill whole groups, so the row loop has no partial
+// group.
+__host__ __device__ constexpr int strip_group(int R) {
+  return (2 * R + 1) * ((4 + 2 * R) / (2 * R + 1));
+}
+__host__ __device__ constexpr int strip_th(int R) {
+  return strip_group(R) * ((kTH + 2 * R + strip_group(R) - 1) / strip_group(R)) - 2 * R;
+}
+__host__ __device__ constexpr int tile_h_for_variant(int variant) {
+  return variant / 100 == kConvGeneral ? kTH : strip_th(variant % 100);
+}
 
 // Host-side launchers (defined in eecmg_kernels.hip).
 hipError_t launch_stage(Stage st, bool f64, int variant, const LaunchList& ll, const JobDesc* descs, int src,

@@ -773,6 +773,8 @@ hipError_t opc_f32_sym(bool disk, const void* x, void* y, int H, int W, const vo
 hipError_t opc_f64_sep(const void* x, void* y, int H, int W, const void* taps, int R, hipStream_t s);
 hipError_t opc_f64_sym(bool disk, const void* x, void* y, int H, int W, const void* taps, int R, hipStream_t s);
 hipError_t opc_gen(bool f64, const void* x, void* y, int H, int W, const void* taps, int R, hipStream_t s);
+hipError_t sm_box(Stage st, bool f64, int R, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
+hipError_t opc_box(bool f64, const void* x, void* y, int H, int W, const void* taps, int R, hipStream_t s);
 
 int rmax_class_for(int r) { return r <= 3 ? 3 : (r <= 6 ? 6 : 12); }
 
@@ -809,6 +811,7 @@ static hipError_t launch_smoother(Stage st, bool f64, int variant, const LaunchL
     case kConvSymSquare:
       return f64 ? sm_f64_sym(st, false, R, ll, descs, s) : sm_f32_sym(st, false, R, ll, descs, s);
     case kConvSymDisk: return f64 ? sm_f64_sym(st, true, R, ll, descs, s) : sm_f32_sym(st, true, R, ll, descs, s);
+    case kConvBoxDisk: return sm_box(st, f64, R, ll, descs, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -881,6 +884,7 @@ hipError_t op_conv(const void* x, void* y, int H, int W, const void* taps, int v
       return f64 ? opc_f64_sym(false, x, y, H, W, taps, R, s) : opc_f32_sym(false, x, y, H, W, taps, R, s);
     case kConvSymDisk:
       return f64 ? opc_f64_sym(true, x, y, H, W, taps, R, s) : opc_f32_sym(true, x, y, H, W, taps, R, s);
+    case kConvBoxDisk: return opc_box(f64, x, y, H, W, taps, R, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -99,14 +99,22 @@ static void choose_variant(LevelPlan& lp, bool f64) {
       return;
     }
   }
-  bool sym = true, disk = true;
+  bool sym = true, disk = true, uniform = R >= 1 && at(0, 0) != 0.0;
   for (int a = -R; a <= R; ++a)
     for (int b = -R; b <= R; ++b) {
       if (at(a, b) != at(-a, b) || at(a, b) != at(a, -b)) sym = false;
       if (a * a + b * b > R * R && at(a, b) != 0.0) disk = false;
+      if (a * a + b * b <= R * R && at(a, b) != at(0, 0)) uniform = false;
     }
   // FP64 disk kernels above R = 6 would spill registers: general kernel instead
   const int disk_max = f64 ? 6 : 8;
+  if (sym && disk && uniform && R <= disk_max) {
+    // uniform disk: one weight, row filters are plain sums over nested spans
+    lp.variant = kConvBoxDisk * 100 + R;
+    lp.taps.assign(1, at(0, 0));
+    lp.taps_t = lp.taps;
+    return;
+  }
   if (sym && ((disk && R <= disk_max) || R <= 6)) {
     const bool use_disk = disk && R <= disk_max;
     lp.variant = (use_disk ? kConvSymDisk : kConvSymSquare) * 100 + R;
@@ -281,8 +289,11 @@ static int build_plan(int H, int W, const double* psf, int r, int L, const int* 
   for (int l = 0; l < L; ++l) {
     LevelPlan& lp = P.lv[l];
     lp.pitch = (int)align_up((size_t)lp.w, pitch_elems);
+    if ((size_t)lp.h * lp.pitch * P.esz >= ((size_t)1 << 32))
+      return fail(EECMG_EINVAL, "a level array would exceed 4 GiB (32-bit offsets)");
+    const int th = tile_h_for_variant(lp.variant);
     lp.tiles_x = (lp.w + kTW - 1) / kTW;
-    lp.ntiles = lp.tiles_x * ((lp.h + kTH - 1) / kTH);
+    lp.ntiles = lp.tiles_x * ((lp.h + th - 1) / th);
     P.max_tiles = std::max(P.max_tiles, lp.ntiles);
     P.off_g[l] = take((size_t)lp.h * lp.pitch * P.esz);
     P.off_u[l] = take((size_t)lp.h * lp.pitch * P.esz);
@@ -1293,6 +1304,8 @@ int eecmg_op_conv_dev(const void* x_dev, void* y_dev, int H, int W, const double
   if (x_dev == y_dev) return fail(EECMG_EINVAL, "x and y must not alias");
   if ((rc = check_dev_ptr(x_dev, "x_dev")) || (rc = check_dev_ptr(y_dev, "y_dev"))) return rc;
   const bool f64 = precision == EECMG_FP64;
+  if ((size_t)H * (size_t)W * (f64 ? 8 : 4) >= ((size_t)1 << 32))
+    return fail(EECMG_EINVAL, "image exceeds 4 GiB (32-bit offsets)");
   void* taps = nullptr;
   int variant = 0;
   rc = op_taps(psf, psf_radius, f64, transpose != 0, &taps, &variant);

@@ -41,14 +41,16 @@ def _psf(kind, r, rng):
         return rng.uniform(-0.2, 1.0, size=(2 * r + 1, 2 * r + 1))
     if kind == "separable":  # rank one (Gaussian)
         return synth.gaussian_psf(max(r, 1) / 2.5, r)
-    if kind == "disk":  # symmetric in both axes, disk support
+    if kind == "disk":  # uniform disk (out-of-focus blur): the uniform-disk kernels
         return synth.disk_psf(r)
-    # symmetric in both axes, full square support
+    # symmetric in both axes, full square support ("symsq") or disk support
+    # with unequal weights ("symdisk")
     q = rng.uniform(0.0, 1.0, size=(r + 1, r + 1))
     full = np.zeros((2 * r + 1, 2 * r + 1))
     for a in range(-r, r + 1):
         for b in range(-r, r + 1):
-            full[a + r, b + r] = q[abs(a), abs(b)]
+            if kind == "symsq" or a * a + b * b <= r * r:
+                full[a + r, b + r] = q[abs(a), abs(b)]
     return full / full.sum()
 
 
@@ -56,7 +58,9 @@ CONV_CASES = [("general", 37, 70, 0), ("general", 64, 64, 1), ("general", 97, 13
               ("general", 130, 65, 7), ("general", 70, 70, 12), ("general", 5, 3, 2), ("general", 1, 1, 4),
               ("separable", 37, 70, 0), ("separable", 97, 130, 4), ("separable", 130, 200, 7),
               ("separable", 70, 33, 12), ("disk", 65, 129, 1), ("disk", 97, 130, 3), ("disk", 200, 130, 6),
-              ("disk", 33, 70, 8), ("symsq", 97, 130, 2), ("symsq", 64, 200, 6), ("symsq", 3, 5, 1)]
+              ("disk", 33, 70, 8), ("disk", 300, 77, 5), ("disk", 2, 70, 2), ("symdisk", 65, 129, 1),
+              ("symdisk", 97, 130, 3), ("symdisk", 200, 130, 6), ("symdisk", 33, 70, 8), ("symsq", 97, 130, 2),
+              ("symsq", 64, 200, 6), ("symsq", 3, 5, 1)]
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])

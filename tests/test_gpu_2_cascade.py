@@ -62,12 +62,23 @@ def _check(p, prec, u, st, u_ref, st_ref):
 
 
 # ------------------------------------------------------------------ smoothers
+def _symdisk(r):
+    """Symmetric PSF on the disk support with unequal weights (selects the
+    symmetric-disk kernels rather than the uniform-disk ones)."""
+    a = np.arange(-r, r + 1)
+    d2 = a[:, None] ** 2 + a[None, :] ** 2
+    w = np.where(d2 <= r * r, 1.0 / (1.0 + d2), 0.0)
+    return w / w.sum()
+
+
 @pytest.mark.parametrize("smoother", ["cgls", "mr"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("H,W,psfname", [(100, 77, "disk3"), (130, 257, "gauss2"), (16, 16, "id")])
+@pytest.mark.parametrize("H,W,psfname", [(100, 77, "disk3"), (101, 90, "symdisk3"), (130, 257, "gauss2"),
+                                         (16, 16, "id")])
 def test_smoother_parity(torch_cuda, smoother, prec, H, W, psfname):
     rng = np.random.Generator(np.random.PCG64(H * W))
-    psf = {"disk3": synth.disk_psf(3), "gauss2": synth.gaussian_psf(2.0, 4), "id": np.ones((1, 1))}[psfname]
+    psf = {"disk3": synth.disk_psf(3), "symdisk3": _symdisk(3), "gauss2": synth.gaussian_psf(2.0, 4),
+           "id": np.ones((1, 1))}[psfname]
     u_true = synth.scene(H, W, 12, rng)
     g = (synth.blur(u_true, psf) + rng.standard_normal((H, W))).astype(_dt(prec)).astype(np.float64)
     u0 = synth.blur(g, synth.gaussian_psf(1.0, 2)).astype(_dt(prec)).astype(np.float64)

@@ -1,52 +1,86 @@
-"""CPU model of the sliding-column register scheme of the separable and
-symmetric blur kernels (circular buffer of 2R+1 pending outputs).  Checks,
-for every radius the library instantiates, that each emitted output receives
-exactly the contributions a = R..-R in that order starting with an
-assignment, that no slot is reused while its output is pending, and that
-every LDS row read lies inside the padded tile."""
+"""CPU model of the streaming sliding-column scheme of the separable,
+symmetric and uniform-disk blur kernels (circular buffer of 2R+1 pending
+outputs, a register ring of prefetched rows, a centre ring, a two-row LDS
+buffer).  Checks, for every radius the library instantiates, that the strip
+height fills whole row groups, that each emitted output receives exactly the
+contributions a = R..-R in that order starting with an assignment, that no
+output or prefetch slot is reused while still pending, that every interior
+row is handled once, and that every LDS access lies inside the row buffer."""
 import pytest
 
-TH = 32
+KTH, KTW, PREFETCH = 32, 64, 2
+
+
+def strip_group(R):
+    """Mirror of strip_group(): a multiple of 2R + 1 of at least 4 rows."""
+    NW = 2 * R + 1
+    return NW * ((4 + 2 * R) // NW)
+
+
+def strip_th(R):
+    """Mirror of strip_th(): smallest height >= 32 with (height + 2R) a
+    multiple of the group size."""
+    GS = strip_group(R)
+    return GS * ((KTH + 2 * R + GS - 1) // GS) - 2 * R
 
 
 def _model(R):
     NW = 2 * R + 1
+    TH = strip_th(R)
     LH = TH + 2 * R
-    NG = (LH + NW - 1) // NW
-    LH_PAD = NG * NW
+    LW = KTW + 2 * R
+    GS = strip_group(R)
+    assert GS % NW == 0 and GS >= 4
+    assert TH >= KTH and TH < KTH + GS and LH % GS == 0
+    NG = LH // GS
+    D = min(GS, PREFETCH)
     slot_owner = [None] * NW
     contrib = {}
-    emitted = []
+    emitted, interior = [], []
+    ring = {}  # prefetch slot -> row it holds
+    cen = {}   # centre slot -> input row
+    for t in range(D):
+        ring[t % GS] = t
     for gi in range(NG):
-        for k in range(NW):
-            t = gi * NW + k
-            assert 0 <= t < LH_PAD
-            # the 2R+1 outputs fed by one row occupy distinct slots
-            assert len({((k - R + a) % NW + NW) % NW for a in range(-R, R + 1)}) == NW
+        for kg in range(GS):
+            t = gi * GS + kg
+            k = kg % NW
+            assert k == t % NW
+            # consume the prefetched row of this step, then refill D ahead
+            assert ring.get(kg) == t, (t, ring)
+            ring[(kg + D) % GS] = t + D
+            if R <= t < R + TH:
+                interior.append(t - R)
+            # LDS: writes at lane and 64 + lane (lane < 2R), reads lane + 0..2R
+            assert KTW - 1 < LW and (2 * R == 0 or KTW + 2 * R - 1 < LW)
+            assert 63 + 2 * R < LW
+            cen[k] = t
             for a in range(R, -R - 1, -1):
                 v = t - R + a
                 s = ((k - R + a) % NW + NW) % NW
                 assert s == v % NW
                 if a == R:
-                    # assignment starts output v; the slot's previous output is done
                     prev = slot_owner[s]
                     assert prev is None or prev + 2 * R < t
                     slot_owner[s] = v
                     contrib[v] = [a]
                 else:
-                    # outputs above the tile (v < 0) start mid-window: junk, never emitted
                     if v >= 0:
                         assert slot_owner[s] == v
                         contrib[v].append(a)
-            vd = t - 2 * R
-            if 0 <= vd < TH:
+            if t >= 2 * R:
+                vd = t - 2 * R
                 s = ((k - R - R) % NW + NW) % NW
                 assert slot_owner[s] == vd
                 assert contrib[vd] == list(range(R, -R - 1, -1))
+                # the centre of output row vd is input row vd + R
+                assert cen[((k - R) % NW + NW) % NW] == vd + R
                 emitted.append(vd)
-    return emitted
+    assert interior == list(range(TH))
+    return emitted, TH
 
 
 @pytest.mark.parametrize("R", list(range(0, 13)))
-def test_sliding_scheme(R):
-    assert _model(R) == list(range(TH))
+def test_streaming_scheme(R):
+    emitted, TH = _model(R)
+    assert emitted == list(range(TH))
