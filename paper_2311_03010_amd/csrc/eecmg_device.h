@@ -162,6 +162,7 @@ template <typename T, int RMAX>
 struct ConvGeneral {
   static constexpr int NT = 256, TW = kTW, TH = kTH, LW = kTW + 2 * RMAX, LH = kTH + 2 * RMAX, RC = RMAX;
   static constexpr bool kRuntimeR = true, kStream = false;
+  static constexpr int kWavesPerEU = 1;
   template <typename Emit>
   __device__ static __forceinline__ void conv(const T* __restrict__ tile, const T* __restrict__ taps, int R, int wave,
                                               int lane, Emit emit) {
@@ -218,6 +219,14 @@ struct Slide {
   }
 };
 
+// Minimum waves per SIMD requested for a streaming kernel holding `regs`
+// values of per-lane state besides its pending outputs (FP32 only: the FP64
+// state is twice as large and left to the allocator).
+template <typename T>
+constexpr int stream_waves(int R, int regs) {
+  return sizeof(T) != 4 ? 1 : (2 * R + 1 + regs <= 22 ? 6 : (2 * R + 1 + regs <= 40 ? 4 : 1));
+}
+
 // Rank-one PSF psf(a,b) = col(a) row(b) (the Gaussian of Section 5 and its
 // coarse levels).  For each input row the lane forms the horizontal filter
 // h = sum_b row(b) x(., j-b) once and adds col(a) h to the pending outputs.
@@ -227,6 +236,10 @@ struct ConvSep {
   using S = Slide<R>;
   static constexpr int NT = 64, TW = kTW, TH = strip_th(R), LW = kTW + 2 * R, RC = R;
   static constexpr bool kRuntimeR = false, kStream = true;
+  // streaming kernels hide memory latency with waves: ask the register
+  // allocator for at least this many per SIMD where the state fits (it
+  // otherwise trades occupancy for instruction-level parallelism)
+  static constexpr int kWavesPerEU = stream_waves<T>(R, 2 * (2 * R + 1));
   struct St {
     T rw[S::NW], cl[S::NW], acc[S::NW];
   };
@@ -280,7 +293,11 @@ struct ConvSym {
   using S = Slide<R>;
   static constexpr int NT = 64, TW = kTW, TH = strip_th(R), LW = kTW + 2 * R, RC = R;
   static constexpr bool kRuntimeR = false, kStream = true;
+  // streaming kernels hide memory latency with waves: ask the register
+  // allocator for at least this many per SIMD where the state fits (it
+  // otherwise trades occupancy for instruction-level parallelism)
   static constexpr int NTAPS = sym_ntaps(R, DISK);
+  static constexpr int kWavesPerEU = stream_waves<T>(R, NTAPS);
   struct St {
     T wt[NTAPS], acc[S::NW];
   };
@@ -326,6 +343,10 @@ struct ConvBox {
   using S = Slide<R>;
   static constexpr int NT = 64, TW = kTW, TH = strip_th(R), LW = kTW + 2 * R, RC = R;
   static constexpr bool kRuntimeR = false, kStream = true;
+  // streaming kernels hide memory latency with waves: ask the register
+  // allocator for at least this many per SIMD where the state fits (it
+  // otherwise trades occupancy for instruction-level parallelism)
+  static constexpr int kWavesPerEU = stream_waves<T>(R, R + 1);
   struct St {
     T w, acc[S::NW];
   };
@@ -546,6 +567,196 @@ __device__ __forceinline__ void stream_strip(const TileGeo& g, unsigned none, ty
 }
 
 // ---------------------------------------------------------------------------
+// Finalize: the scalar Krylov recurrences in FP64, run on the device by one
+// 256-thread block per job after each pass.  Partials are summed in a fixed
+// order that depends only on the job's tile count, so results are
+// deterministic and independent of how many jobs share a launch.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool finite_d(double x) { return isfinite(x); }
+
+// Fixed-order sum of selected components of the tile partials of one job,
+// returned to every thread of the NT-thread block.  Thread i sums the
+// contiguous chunk [i*ch, (i+1)*ch) of each component in index order, then
+// the chunk sums are combined by a fixed tree.
+template <int NV, int NT>
+__device__ __forceinline__ void sum_partials(const double* __restrict__ part, int ntiles, int stride,
+                                             const int (&comp)[NV], double (&out)[NV]) {
+  constexpr int NWV = NT / 64;
+  const int ch = (ntiles + NT - 1) / NT;
+  const int t0 = min((int)threadIdx.x * ch, ntiles), t1 = min(t0 + ch, ntiles);
+  double acc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const double* __restrict__ c = part + (size_t)comp[i] * stride;
+    double a = 0.0;
+    int t = t0;
+    for (; t + 4 <= t1; t += 4) {
+      const double v0 = c[t], v1 = c[t + 1], v2 = c[t + 2], v3 = c[t + 3];
+      a = (((a + v0) + v1) + v2) + v3;
+    }
+    for (; t < t1; ++t) a += c[t];
+    acc[i] = wave_sum(a);
+  }
+  if constexpr (NWV == 1) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) out[i] = acc[i];
+  } else {
+    __shared__ double red[NWV][NV];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) red[wave][i] = acc[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double v = red[0][i];
+#pragma unroll
+      for (int w = 1; w < NWV; ++w) v += red[w][i];
+      out[i] = v;
+    }
+  }
+}
+
+// Publish the job's progress (level tag, iterations, stop reason) to pinned
+// host memory as one 64-bit system-scope store; the host only uses it to
+// decide how many more iterations to enqueue.
+__device__ __forceinline__ void publish(const JobDesc& d, const SolverState* st) {
+  __hip_atomic_store(d.mirror, mirror_word(d.tag, st->k, st->done), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Stopping tests of the smoother, in the order: non-finite, discrepancy
+// principle ||r|| <= c delta (RMS norm), iteration cap m_l, convergence guard.
+__device__ __forceinline__ void check_stop(SolverState* st, const JobDesc& d, double rr, double guard_val,
+                                           double guard_ref, bool nonfinite) {
+  const double rms = sqrt(rr / ((double)d.h * (double)d.w));
+  int reason = kStopNone;
+  if (nonfinite)
+    reason = kStopNonFinite;
+  else if (d.stop_rule && rms <= d.cdelta)
+    reason = kStopDiscrepancy;
+  else if (st->k >= d.cap)
+    reason = kStopCap;
+  else if (guard_val == 0.0 || guard_val <= d.eps2 * guard_ref)
+    reason = kStopGuard;
+  st->rr = rr;
+  if (reason != kStopNone) {
+    st->done = reason;
+    d.rec[d.level].iters = st->k;
+    d.rec[d.level].reason = reason;
+    d.rec[d.level].rms = rms;
+  }
+}
+
+// The scalar updates run in one thread with the summed partials v.
+// CGLS start: partials <r,r> (1) and <s,s> (2) of r = g - H u0, s = H^T r.
+constexpr int kCompCgInit[2] = {1, 2};
+__device__ inline void fin_cg_init(const JobDesc& d, const double (&v)[2]) {
+  SolverState* st = d.st;
+  st->k = 0;
+  st->par = 0;
+  st->beta = 0.0;
+  st->alpha = 0.0;
+  st->done = kStopNone;
+  st->pending = 0;
+  st->level = d.level;
+  st->gamma = v[1];
+  st->gamma0 = v[1];
+  st->rr0 = v[0];
+  d.rec[d.level].iters = 0;
+  d.rec[d.level].reason = kStopNone;
+  d.rec[d.level].rms = sqrt(v[0] / ((double)d.h * (double)d.w));
+  check_stop(st, d, v[0], v[1], v[1], !finite_d(v[0]) || !finite_d(v[1]));
+  publish(d, st);
+}
+
+// After pass A: eta = <q,q> (0), alpha = gamma / eta.
+constexpr int kCompCgA[1] = {0};
+__device__ inline void fin_cg_a(const JobDesc& d, const double (&v)[1]) {
+  SolverState* st = d.st;
+  const double eta = v[0];
+  st->eta = eta;
+  if (!finite_d(eta) || eta == 0.0) {
+    const int reason = finite_d(eta) ? kStopGuard : kStopNonFinite;
+    st->done = reason;
+    d.rec[d.level].iters = st->k;
+    d.rec[d.level].reason = reason;
+    d.rec[d.level].rms = sqrt(st->rr / ((double)d.h * (double)d.w));
+    publish(d, st);
+    return;
+  }
+  st->alpha = st->gamma / eta;
+}
+
+// After pass B: <r,r> (1), gamma_new = <s,s> (2), beta = gamma_new / gamma.
+constexpr int kCompCgB[2] = {1, 2};
+__device__ inline void fin_cg_b(const JobDesc& d, const double (&v)[2]) {
+  SolverState* st = d.st;
+  const double gnew = v[1];
+  st->beta = gnew / st->gamma;
+  st->gamma = gnew;
+  st->k += 1;
+  st->par ^= 1;
+  st->seq += 1;
+  check_stop(st, d, v[0], gnew, st->gamma0, !finite_d(v[0]) || !finite_d(gnew));
+  publish(d, st);
+}
+
+// MR start: <r,r> (1) of r = g - H u0.
+constexpr int kCompMrInit[1] = {1};
+__device__ inline void fin_mr_init(const JobDesc& d, const double (&v)[1]) {
+  SolverState* st = d.st;
+  st->k = 0;
+  st->par = 0;
+  st->alpha = 0.0;
+  st->beta = 0.0;
+  st->done = kStopNone;
+  st->pending = 0;
+  st->level = d.level;
+  st->rr0 = v[0];
+  d.rec[d.level].iters = 0;
+  d.rec[d.level].reason = kStopNone;
+  d.rec[d.level].rms = sqrt(v[0] / ((double)d.h * (double)d.w));
+  check_stop(st, d, v[0], v[0], v[0], !finite_d(v[0]));
+  publish(d, st);
+}
+
+// After an MR pass: <r,q> (0), <r,r> (1), <q,q> (2); the pending step of the
+// pass counts as an iteration, the next step is alpha = <r,q> / <q,q>.
+constexpr int kCompMr[3] = {0, 1, 2};
+__device__ inline void fin_mr(const JobDesc& d, const double (&v)[3]) {
+  SolverState* st = d.st;
+  if (st->pending) st->k += 1;
+  st->pending = 0;
+  st->par ^= 1;
+  st->seq += 1;
+  const double rq = v[0], rr = v[1], qq = v[2];
+  check_stop(st, d, rr, rr, st->rr0, !finite_d(rr) || !finite_d(rq) || !finite_d(qq));
+  if (!st->done) {
+    st->eta = qq;
+    if (qq == 0.0) {
+      st->done = kStopGuard;
+      d.rec[d.level].iters = st->k;
+      d.rec[d.level].reason = kStopGuard;
+      d.rec[d.level].rms = sqrt(rr / ((double)d.h * (double)d.w));
+    } else {
+      st->rq = rq;
+      st->alpha = rq / qq;
+      st->pending = 1;
+    }
+  }
+  publish(d, st);
+}
+
+// Body of a finalize kernel: sum the partials, then the scalar update.
+template <int NV, typename F>
+__device__ __forceinline__ void finalize_block(const JobDesc& d, const int (&comp)[NV], F fin) {
+  double v[NV];
+  sum_partials<NV, 256>(d.partials, d.ntiles, d.pstride, comp, v);
+  if (threadIdx.x == 0) fin(d, v);
+}
+
+// ---------------------------------------------------------------------------
 // Smoother pass kernels, templated on the element type and blur policy.
 // ---------------------------------------------------------------------------
 
@@ -556,7 +767,7 @@ struct Two {
 
 // r = g - H u0, stored in r[0]; partial <r,r> in slot 1.  (CGLS and MR)
 template <typename T, typename P>
-__global__ __launch_bounds__(P::NT) void k_init1(LaunchList ll, const JobDesc* __restrict__ descs) {
+__global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWavesPerEU))) void k_init1(LaunchList ll, const JobDesc* __restrict__ descs) {
   const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
   const JobDesc& d = descs[L.d];
   const TileGeo g = tile_geo<P>(d, L.t);
@@ -599,7 +810,7 @@ __global__ __launch_bounds__(P::NT) void k_init1(LaunchList ll, const JobDesc* _
 
 // s = H^T r, p[0] = s; partial <s,s> in slot 2.
 template <typename T, typename P>
-__global__ __launch_bounds__(P::NT) void k_cg_init2(LaunchList ll, const JobDesc* __restrict__ descs) {
+__global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWavesPerEU))) void k_cg_init2(LaunchList ll, const JobDesc* __restrict__ descs) {
   const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
   const JobDesc& d = descs[L.d];
   const TileGeo g = tile_geo<P>(d, L.t);
@@ -640,7 +851,7 @@ __global__ __launch_bounds__(P::NT) void k_cg_init2(LaunchList ll, const JobDesc
 // Pass A of iteration k: p_new = s + beta p_old (on tile + halo), q = H p_new;
 // partial <q,q> in slot 0.
 template <typename T, typename P>
-__global__ __launch_bounds__(P::NT) void k_cg_a(LaunchList ll, const JobDesc* __restrict__ descs) {
+__global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWavesPerEU))) void k_cg_a(LaunchList ll, const JobDesc* __restrict__ descs) {
   const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
   const JobDesc& d = descs[L.d];
   const SolverState* st = d.st;
@@ -690,7 +901,7 @@ __global__ __launch_bounds__(P::NT) void k_cg_a(LaunchList ll, const JobDesc* __
 // Pass B of iteration k: r_new = r - alpha q (tile + halo), u += alpha p_new,
 // s = H^T r_new; partials <r,r> (slot 1) and <s,s> (slot 2).
 template <typename T, typename P>
-__global__ __launch_bounds__(P::NT) void k_cg_b(LaunchList ll, const JobDesc* __restrict__ descs) {
+__global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWavesPerEU))) void k_cg_b(LaunchList ll, const JobDesc* __restrict__ descs) {
   const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
   const JobDesc& d = descs[L.d];
   const SolverState* st = d.st;
@@ -830,7 +1041,7 @@ __global__ __launch_bounds__(P::NT) void k_mr_pass(LaunchList ll, const JobDesc*
 
 // Operator form: y = H x on one dense image with the given taps layout.
 template <typename T, typename P>
-__global__ __launch_bounds__(P::NT) void k_op_conv(const T* __restrict__ x, T* __restrict__ y, int H, int W,
+__global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWavesPerEU))) void k_op_conv(const T* __restrict__ x, T* __restrict__ y, int H, int W,
                                                    const T* __restrict__ taps, int R) {
   const int tiles_x = (W + P::TW - 1) / P::TW;
   TileGeo g;

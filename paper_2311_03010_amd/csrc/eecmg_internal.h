@@ -39,6 +39,7 @@ struct SolverState {
   int32_t pad[2];
 };
 
+
 struct LevelRecord {
   int32_t iters, reason;
   double rms;

@@ -1,11 +1,6 @@
 // HIP kernels (gfx950, wave64) of the EECMG cascade, other than the smoother
-// passes: the finalize kernels that run the scalar Krylov recurrences on the
-// device, the level-transfer operators, restriction, output copy, and the
+// passes: the level-transfer operators, restriction, output copy, and the
 // top-level launch dispatch.
-//
-// Finalize kernels sum the per-tile FP64 partials of one job in a fixed
-// order, so every result is deterministic and independent of how many jobs
-// share a launch.
 #include <math.h>
 
 #include "eecmg_device.h"
@@ -13,190 +8,34 @@
 namespace eecmg {
 
 // ---------------------------------------------------------------------------
-// Finalize kernels: one block per job, scalar recurrences in FP64.
+// Finalize kernels: one 256-thread block per job, scalar recurrences in FP64.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool finite_d(double x) { return isfinite(x); }
-
-// Fixed-order sum of selected components of the tile partials of one job,
-// returned to every thread of the 256-thread block.  Thread i sums the
-// contiguous chunk [i*ch, (i+1)*ch) of each component in index order, then the
-// 256 chunk sums are combined by a fixed tree: the result depends only on the
-// job's own partials.
-template <int NV>
-__device__ __forceinline__ void sum_partials(const double* __restrict__ part, int ntiles, int stride,
-                                             const int (&comp)[NV], double (&out)[NV]) {
-  __shared__ double red[4][NV];
-  const int ch = (ntiles + 255) / 256;
-  const int t0 = min((int)threadIdx.x * ch, ntiles), t1 = min(t0 + ch, ntiles);
-  double acc[NV];
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    const double* __restrict__ c = part + (size_t)comp[i] * stride;
-    double a = 0.0;
-    int t = t0;
-    for (; t + 4 <= t1; t += 4) {
-      const double v0 = c[t], v1 = c[t + 1], v2 = c[t + 2], v3 = c[t + 3];
-      a = (((a + v0) + v1) + v2) + v3;
-    }
-    for (; t < t1; ++t) a += c[t];
-    acc[i] = a;
-  }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) acc[i] = wave_sum(acc[i]);
-  if (lane == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) red[wave][i] = acc[i];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < NV; ++i) out[i] = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
-}
-
-// Publish the job's progress (level tag, iterations, stop reason) to pinned
-// host memory as one 64-bit system-scope store; the host only uses it to
-// decide how many more iterations to enqueue.
-__device__ __forceinline__ void publish(const JobDesc& d, const SolverState* st) {
-  __hip_atomic_store(d.mirror, mirror_word(d.tag, st->k, st->done), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-
-// Stopping tests of the smoother, in the order: non-finite, discrepancy
-// principle ||r|| <= c delta (RMS norm), iteration cap m_l, convergence guard.
-__device__ __forceinline__ void check_stop(SolverState* st, const JobDesc& d, double rr, double guard_val,
-                                           double guard_ref, bool nonfinite) {
-  const double rms = sqrt(rr / ((double)d.h * (double)d.w));
-  int reason = kStopNone;
-  if (nonfinite)
-    reason = kStopNonFinite;
-  else if (d.stop_rule && rms <= d.cdelta)
-    reason = kStopDiscrepancy;
-  else if (st->k >= d.cap)
-    reason = kStopCap;
-  else if (guard_val == 0.0 || guard_val <= d.eps2 * guard_ref)
-    reason = kStopGuard;
-  st->rr = rr;
-  if (reason != kStopNone) {
-    st->done = reason;
-    d.rec[d.level].iters = st->k;
-    d.rec[d.level].reason = reason;
-    d.rec[d.level].rms = rms;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_cg_fin_init(LaunchList ll, const JobDesc* __restrict__ descs) {
+__global__ __launch_bounds__(256) void k_fin_cg_init(LaunchList ll, const JobDesc* __restrict__ descs) {
   const JobDesc& d = descs[ll.job[blockIdx.x]];
-  double v[2];
-  const int comp[2] = {1, 2};
-  sum_partials<2>(d.partials, d.ntiles, d.pstride, comp, v);
-  if (threadIdx.x != 0) return;
-  SolverState* st = d.st;
-  st->k = 0;
-  st->par = 0;
-  st->beta = 0.0;
-  st->alpha = 0.0;
-  st->done = kStopNone;
-  st->pending = 0;
-  st->level = d.level;
-  st->gamma = v[1];
-  st->gamma0 = v[1];
-  st->rr0 = v[0];
-  d.rec[d.level].iters = 0;
-  d.rec[d.level].reason = kStopNone;
-  d.rec[d.level].rms = sqrt(v[0] / ((double)d.h * (double)d.w));
-  check_stop(st, d, v[0], v[1], v[1], !finite_d(v[0]) || !finite_d(v[1]));
-  publish(d, st);
+  finalize_block(d, kCompCgInit, [](const JobDesc& dd, const double(&v)[2]) { fin_cg_init(dd, v); });
 }
 
-__global__ __launch_bounds__(256) void k_cg_fin_a(LaunchList ll, const JobDesc* __restrict__ descs) {
+__global__ __launch_bounds__(256) void k_fin_cg_a(LaunchList ll, const JobDesc* __restrict__ descs) {
   const JobDesc& d = descs[ll.job[blockIdx.x]];
-  SolverState* st = d.st;
-  if (st->done) return;
-  double v[1];
-  const int comp[1] = {0};
-  sum_partials<1>(d.partials, d.ntiles, d.pstride, comp, v);
-  if (threadIdx.x != 0) return;
-  const double eta = v[0];
-  st->eta = eta;
-  if (!finite_d(eta) || eta == 0.0) {
-    const int reason = finite_d(eta) ? kStopGuard : kStopNonFinite;
-    st->done = reason;
-    d.rec[d.level].iters = st->k;
-    d.rec[d.level].reason = reason;
-    d.rec[d.level].rms = sqrt(st->rr / ((double)d.h * (double)d.w));
-    publish(d, st);
-    return;
-  }
-  st->alpha = st->gamma / eta;
+  if (__builtin_amdgcn_readfirstlane(d.st->done)) return;
+  finalize_block(d, kCompCgA, [](const JobDesc& dd, const double(&v)[1]) { fin_cg_a(dd, v); });
 }
 
-__global__ __launch_bounds__(256) void k_cg_fin_b(LaunchList ll, const JobDesc* __restrict__ descs) {
+__global__ __launch_bounds__(256) void k_fin_cg_b(LaunchList ll, const JobDesc* __restrict__ descs) {
   const JobDesc& d = descs[ll.job[blockIdx.x]];
-  SolverState* st = d.st;
-  if (st->done) return;
-  double v[2];
-  const int comp[2] = {1, 2};
-  sum_partials<2>(d.partials, d.ntiles, d.pstride, comp, v);
-  if (threadIdx.x != 0) return;
-  const double gnew = v[1];
-  st->beta = gnew / st->gamma;
-  st->gamma = gnew;
-  st->k += 1;
-  st->par ^= 1;
-  st->seq += 1;
-  check_stop(st, d, v[0], gnew, st->gamma0, !finite_d(v[0]) || !finite_d(gnew));
-  publish(d, st);
+  if (__builtin_amdgcn_readfirstlane(d.st->done)) return;
+  finalize_block(d, kCompCgB, [](const JobDesc& dd, const double(&v)[2]) { fin_cg_b(dd, v); });
 }
 
-__global__ __launch_bounds__(256) void k_mr_fin_init(LaunchList ll, const JobDesc* __restrict__ descs) {
+__global__ __launch_bounds__(256) void k_fin_mr_init(LaunchList ll, const JobDesc* __restrict__ descs) {
   const JobDesc& d = descs[ll.job[blockIdx.x]];
-  double v[1];
-  const int comp[1] = {1};
-  sum_partials<1>(d.partials, d.ntiles, d.pstride, comp, v);
-  if (threadIdx.x != 0) return;
-  SolverState* st = d.st;
-  st->k = 0;
-  st->par = 0;
-  st->alpha = 0.0;
-  st->beta = 0.0;
-  st->done = kStopNone;
-  st->pending = 0;
-  st->level = d.level;
-  st->rr0 = v[0];
-  d.rec[d.level].iters = 0;
-  d.rec[d.level].reason = kStopNone;
-  d.rec[d.level].rms = sqrt(v[0] / ((double)d.h * (double)d.w));
-  check_stop(st, d, v[0], v[0], v[0], !finite_d(v[0]));
-  publish(d, st);
+  finalize_block(d, kCompMrInit, [](const JobDesc& dd, const double(&v)[1]) { fin_mr_init(dd, v); });
 }
 
-__global__ __launch_bounds__(256) void k_mr_fin(LaunchList ll, const JobDesc* __restrict__ descs) {
+__global__ __launch_bounds__(256) void k_fin_mr(LaunchList ll, const JobDesc* __restrict__ descs) {
   const JobDesc& d = descs[ll.job[blockIdx.x]];
-  SolverState* st = d.st;
-  if (st->done) return;
-  double v[3];
-  const int comp[3] = {0, 1, 2};
-  sum_partials<3>(d.partials, d.ntiles, d.pstride, comp, v);
-  if (threadIdx.x != 0) return;
-  if (st->pending) st->k += 1;
-  st->pending = 0;
-  st->par ^= 1;
-  st->seq += 1;
-  const double rq = v[0], rr = v[1], qq = v[2];
-  check_stop(st, d, rr, rr, st->rr0, !finite_d(rr) || !finite_d(rq) || !finite_d(qq));
-  if (!st->done) {
-    st->eta = qq;
-    if (qq == 0.0) {
-      st->done = kStopGuard;
-      d.rec[d.level].iters = st->k;
-      d.rec[d.level].reason = kStopGuard;
-      d.rec[d.level].rms = sqrt(rr / ((double)d.h * (double)d.w));
-    } else {
-      st->rq = rq;
-      st->alpha = rq / qq;
-      st->pending = 1;
-    }
-  }
-  publish(d, st);
+  if (__builtin_amdgcn_readfirstlane(d.st->done)) return;
+  finalize_block(d, kCompMr, [](const JobDesc& dd, const double(&v)[3]) { fin_mr(dd, v); });
 }
 
 // ---------------------------------------------------------------------------
@@ -863,11 +702,11 @@ hipError_t launch_stage(Stage st, bool f64, int variant, const LaunchList& ll, c
   if (ll.n <= 0) return hipSuccess;
   const dim3 block(256);
   switch (st) {
-    case kCgFinInit: hipLaunchKernelGGL(k_cg_fin_init, dim3(ll.n), block, 0, s, ll, descs); return hipGetLastError();
-    case kCgFinA: hipLaunchKernelGGL(k_cg_fin_a, dim3(ll.n), block, 0, s, ll, descs); return hipGetLastError();
-    case kCgFinB: hipLaunchKernelGGL(k_cg_fin_b, dim3(ll.n), block, 0, s, ll, descs); return hipGetLastError();
-    case kMrFinInit: hipLaunchKernelGGL(k_mr_fin_init, dim3(ll.n), block, 0, s, ll, descs); return hipGetLastError();
-    case kMrFin: hipLaunchKernelGGL(k_mr_fin, dim3(ll.n), block, 0, s, ll, descs); return hipGetLastError();
+    case kCgFinInit: hipLaunchKernelGGL(k_fin_cg_init, dim3(ll.n), block, 0, s, ll, descs); return hipGetLastError();
+    case kCgFinA: hipLaunchKernelGGL(k_fin_cg_a, dim3(ll.n), block, 0, s, ll, descs); return hipGetLastError();
+    case kCgFinB: hipLaunchKernelGGL(k_fin_cg_b, dim3(ll.n), block, 0, s, ll, descs); return hipGetLastError();
+    case kMrFinInit: hipLaunchKernelGGL(k_fin_mr_init, dim3(ll.n), block, 0, s, ll, descs); return hipGetLastError();
+    case kMrFin: hipLaunchKernelGGL(k_fin_mr, dim3(ll.n), block, 0, s, ll, descs); return hipGetLastError();
     default: break;
   }
   return f64 ? launch_typed<double>(st, variant, ll, descs, src, dst, s)

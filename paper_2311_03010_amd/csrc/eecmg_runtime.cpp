@@ -913,6 +913,10 @@ class Engine {
     }
   }
 
+  void launch_fin(Stage st, const std::vector<Job*>& jobs) {
+    if (!jobs.empty()) launch_group(st, jobs, -1, jobs.front()->plan.f64, 0, -1, -1);
+  }
+
   void issue_inits(const std::vector<Job*>& js) {
     std::map<std::pair<int, int>, std::vector<Job*>> groups;  // (smoother, variant)
     for (Job* j : js) groups[{j->plan.prm.smoother, variant_key(j)}].push_back(j);
@@ -922,10 +926,10 @@ class Engine {
       if (kv.first.first == EECMG_SMOOTHER_CGLS) {
         launch_group(kCgInit1, kv.second, -1, f64, rc, -1, -1);
         launch_group(kCgInit2, kv.second, -1, f64, rc, -1, -1);
-        launch_group(kCgFinInit, kv.second, -1, f64, rc, -1, -1);
+        launch_fin(kCgFinInit, kv.second);
       } else {
         launch_group(kMrInit, kv.second, -1, f64, rc, -1, -1);
-        launch_group(kMrFinInit, kv.second, -1, f64, rc, -1, -1);
+        launch_fin(kMrFinInit, kv.second);
       }
     }
   }
@@ -948,12 +952,12 @@ class Engine {
         const std::vector<int>* ki = &kidx[kv.first];
         if (kv.first.first == EECMG_SMOOTHER_CGLS) {
           launch_group(kCgA, kv.second, -1, f64, rc, -1, -1, ki);
-          launch_group(kCgFinA, kv.second, -1, f64, rc, -1, -1);
+          launch_fin(kCgFinA, kv.second);
           launch_group(kCgB, kv.second, -1, f64, rc, -1, -1, ki);
-          launch_group(kCgFinB, kv.second, -1, f64, rc, -1, -1);
+          launch_fin(kCgFinB, kv.second);
         } else {
           launch_group(kMrPass, kv.second, -1, f64, rc, -1, -1, ki);
-          launch_group(kMrFin, kv.second, -1, f64, rc, -1, -1);
+          launch_fin(kMrFin, kv.second);
         }
       }
     }
