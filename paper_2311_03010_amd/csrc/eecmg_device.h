@@ -648,11 +648,11 @@ __device__ __forceinline__ void check_stop(SolverState* st, const JobDesc& d, do
   }
 }
 
-// The scalar updates run in one thread with the summed partials v.
+// The scalar updates run in one thread with the summed partials v, on the
+// job's solver state st (pub: publish the progress word to the host).
 // CGLS start: partials <r,r> (1) and <s,s> (2) of r = g - H u0, s = H^T r.
 constexpr int kCompCgInit[2] = {1, 2};
-__device__ inline void fin_cg_init(const JobDesc& d, const double (&v)[2]) {
-  SolverState* st = d.st;
+__device__ inline void fin_cg_init(const JobDesc& d, SolverState* st, const double (&v)[2], bool pub = true) {
   st->k = 0;
   st->par = 0;
   st->beta = 0.0;
@@ -667,13 +667,12 @@ __device__ inline void fin_cg_init(const JobDesc& d, const double (&v)[2]) {
   d.rec[d.level].reason = kStopNone;
   d.rec[d.level].rms = sqrt(v[0] / ((double)d.h * (double)d.w));
   check_stop(st, d, v[0], v[1], v[1], !finite_d(v[0]) || !finite_d(v[1]));
-  publish(d, st);
+  if (pub) publish(d, st);
 }
 
 // After pass A: eta = <q,q> (0), alpha = gamma / eta.
 constexpr int kCompCgA[1] = {0};
-__device__ inline void fin_cg_a(const JobDesc& d, const double (&v)[1]) {
-  SolverState* st = d.st;
+__device__ inline void fin_cg_a(const JobDesc& d, SolverState* st, const double (&v)[1], bool pub = true) {
   const double eta = v[0];
   st->eta = eta;
   if (!finite_d(eta) || eta == 0.0) {
@@ -682,7 +681,7 @@ __device__ inline void fin_cg_a(const JobDesc& d, const double (&v)[1]) {
     d.rec[d.level].iters = st->k;
     d.rec[d.level].reason = reason;
     d.rec[d.level].rms = sqrt(st->rr / ((double)d.h * (double)d.w));
-    publish(d, st);
+    if (pub) publish(d, st);
     return;
   }
   st->alpha = st->gamma / eta;
@@ -690,8 +689,7 @@ __device__ inline void fin_cg_a(const JobDesc& d, const double (&v)[1]) {
 
 // After pass B: <r,r> (1), gamma_new = <s,s> (2), beta = gamma_new / gamma.
 constexpr int kCompCgB[2] = {1, 2};
-__device__ inline void fin_cg_b(const JobDesc& d, const double (&v)[2]) {
-  SolverState* st = d.st;
+__device__ inline void fin_cg_b(const JobDesc& d, SolverState* st, const double (&v)[2], bool pub = true) {
   const double gnew = v[1];
   st->beta = gnew / st->gamma;
   st->gamma = gnew;
@@ -699,13 +697,12 @@ __device__ inline void fin_cg_b(const JobDesc& d, const double (&v)[2]) {
   st->par ^= 1;
   st->seq += 1;
   check_stop(st, d, v[0], gnew, st->gamma0, !finite_d(v[0]) || !finite_d(gnew));
-  publish(d, st);
+  if (pub) publish(d, st);
 }
 
 // MR start: <r,r> (1) of r = g - H u0.
 constexpr int kCompMrInit[1] = {1};
-__device__ inline void fin_mr_init(const JobDesc& d, const double (&v)[1]) {
-  SolverState* st = d.st;
+__device__ inline void fin_mr_init(const JobDesc& d, SolverState* st, const double (&v)[1], bool pub = true) {
   st->k = 0;
   st->par = 0;
   st->alpha = 0.0;
@@ -718,14 +715,13 @@ __device__ inline void fin_mr_init(const JobDesc& d, const double (&v)[1]) {
   d.rec[d.level].reason = kStopNone;
   d.rec[d.level].rms = sqrt(v[0] / ((double)d.h * (double)d.w));
   check_stop(st, d, v[0], v[0], v[0], !finite_d(v[0]));
-  publish(d, st);
+  if (pub) publish(d, st);
 }
 
 // After an MR pass: <r,q> (0), <r,r> (1), <q,q> (2); the pending step of the
 // pass counts as an iteration, the next step is alpha = <r,q> / <q,q>.
 constexpr int kCompMr[3] = {0, 1, 2};
-__device__ inline void fin_mr(const JobDesc& d, const double (&v)[3]) {
-  SolverState* st = d.st;
+__device__ inline void fin_mr(const JobDesc& d, SolverState* st, const double (&v)[3], bool pub = true) {
   if (st->pending) st->k += 1;
   st->pending = 0;
   st->par ^= 1;
@@ -745,7 +741,7 @@ __device__ inline void fin_mr(const JobDesc& d, const double (&v)[3]) {
       st->pending = 1;
     }
   }
-  publish(d, st);
+  if (pub) publish(d, st);
 }
 
 // Body of a finalize kernel: sum the partials, then the scalar update.

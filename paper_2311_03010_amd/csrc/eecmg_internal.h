@@ -21,6 +21,10 @@ constexpr int kTH = 4 * kV;
 constexpr int kXW = 64;
 constexpr int kXH = 16;
 
+// Smoother and cascade ids (same values as eecmg_smoother / eecmg_cascade).
+enum : int32_t { kSmootherCgls = 0, kSmootherMr = 1 };
+enum : int32_t { kCascadeEecmg = 0, kCascadeIecmgL = 1, kCascadeIecmgP = 2 };
+
 // Stop reasons (same values as eecmg_stop_reason).
 enum : int32_t { kStopNone = 0, kStopDiscrepancy = 1, kStopCap = 2, kStopGuard = 3, kStopNonFinite = 4 };
 
@@ -62,6 +66,9 @@ struct JobDesc {
   int32_t tiles_x, ntiles;  // smoother tiles (kTH x kTW)
   int32_t cap, level;
   int32_t stop_rule, smoother;
+  int32_t cascade, pm_steps;
+  int32_t coarse_levels;  // level 0 only: leading levels solved by the coarse kernel
+  int32_t pad0;
   double cdelta, eps2;
   SolverState* st;
   LevelRecord* rec;  // kMaxLevels records of this job
@@ -123,6 +130,7 @@ enum Stage : int32_t {
   kOutCopy,         // u (finest, pitched) -> dense u_out
   kXfFused,         // prolongation -> S (-> one D step), fused; variant bit 0 quadratic, bit 1 with D
   kXfFusedSmall,    // the same with short tiles, for small levels
+  kCoarse,          // the leading small levels of each job in one block per job
   kNumStages
 };
 

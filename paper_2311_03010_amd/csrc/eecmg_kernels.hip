@@ -12,30 +12,30 @@ namespace eecmg {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_fin_cg_init(LaunchList ll, const JobDesc* __restrict__ descs) {
   const JobDesc& d = descs[ll.job[blockIdx.x]];
-  finalize_block(d, kCompCgInit, [](const JobDesc& dd, const double(&v)[2]) { fin_cg_init(dd, v); });
+  finalize_block(d, kCompCgInit, [](const JobDesc& dd, const double(&v)[2]) { fin_cg_init(dd, dd.st, v); });
 }
 
 __global__ __launch_bounds__(256) void k_fin_cg_a(LaunchList ll, const JobDesc* __restrict__ descs) {
   const JobDesc& d = descs[ll.job[blockIdx.x]];
   if (__builtin_amdgcn_readfirstlane(d.st->done)) return;
-  finalize_block(d, kCompCgA, [](const JobDesc& dd, const double(&v)[1]) { fin_cg_a(dd, v); });
+  finalize_block(d, kCompCgA, [](const JobDesc& dd, const double(&v)[1]) { fin_cg_a(dd, dd.st, v); });
 }
 
 __global__ __launch_bounds__(256) void k_fin_cg_b(LaunchList ll, const JobDesc* __restrict__ descs) {
   const JobDesc& d = descs[ll.job[blockIdx.x]];
   if (__builtin_amdgcn_readfirstlane(d.st->done)) return;
-  finalize_block(d, kCompCgB, [](const JobDesc& dd, const double(&v)[2]) { fin_cg_b(dd, v); });
+  finalize_block(d, kCompCgB, [](const JobDesc& dd, const double(&v)[2]) { fin_cg_b(dd, dd.st, v); });
 }
 
 __global__ __launch_bounds__(256) void k_fin_mr_init(LaunchList ll, const JobDesc* __restrict__ descs) {
   const JobDesc& d = descs[ll.job[blockIdx.x]];
-  finalize_block(d, kCompMrInit, [](const JobDesc& dd, const double(&v)[1]) { fin_mr_init(dd, v); });
+  finalize_block(d, kCompMrInit, [](const JobDesc& dd, const double(&v)[1]) { fin_mr_init(dd, dd.st, v); });
 }
 
 __global__ __launch_bounds__(256) void k_fin_mr(LaunchList ll, const JobDesc* __restrict__ descs) {
   const JobDesc& d = descs[ll.job[blockIdx.x]];
   if (__builtin_amdgcn_readfirstlane(d.st->done)) return;
-  finalize_block(d, kCompMr, [](const JobDesc& dd, const double(&v)[3]) { fin_mr(dd, v); });
+  finalize_block(d, kCompMr, [](const JobDesc& dd, const double(&v)[3]) { fin_mr(dd, dd.st, v); });
 }
 
 // ---------------------------------------------------------------------------
@@ -77,7 +77,7 @@ struct PiD {
 
 // New extrapolation Pi (Section 3.2): output on grid B.
 template <typename T>
-__device__ __forceinline__ void pi_point(const XArgs& x, int p, int q) {
+__device__ __forceinline__ double pi_value(const XArgs& x, int p, int q) {
   const T* uA = (const T*)x.s0;
   const T* uB = (const T*)x.s1;
   const PiD<T> D{uA, uB, x.h0, x.w0, x.p0, x.p1};
@@ -91,7 +91,12 @@ __device__ __forceinline__ void pi_point(const XArgs& x, int p, int q) {
     corr = (D(a, b) + D(a + 1, b)) * 0.125;
   else
     corr = (D(a, b) + D(a + 1, b) + D(a, b + 1) + D(a + 1, b + 1)) * 0.0625;
-  ((T*)x.dst)[(size_t)p * x.pd + q] = to_t<T>((double)uB[(size_t)p * x.p1 + q] + corr);
+  return (double)uB[(size_t)p * x.p1 + q] + corr;
+}
+
+template <typename T>
+__device__ __forceinline__ void pi_point(const XArgs& x, int p, int q) {
+  ((T*)x.dst)[(size_t)p * x.pd + q] = to_t<T>(pi_value<T>(x, p, q));
 }
 
 // Source of the quadratic interpolation extended by two virtual nodes per
@@ -140,9 +145,13 @@ __device__ __forceinline__ double quad_value(int I, int J, F E) {
 }
 
 template <typename T>
-__device__ __forceinline__ void quad_point(const XArgs& x, int I, int J) {
+__device__ __forceinline__ double quad_at(const XArgs& x, int I, int J) {
   const QExt<T> E{(const T*)x.s0, x.h0, x.w0, x.p0};
-  ((T*)x.dst)[(size_t)I * x.pd + J] = to_t<T>(quad_value(I, J, E));
+  return quad_value(I, J, E);
+}
+template <typename T>
+__device__ __forceinline__ void quad_point(const XArgs& x, int I, int J) {
+  ((T*)x.dst)[(size_t)I * x.pd + J] = to_t<T>(quad_at<T>(x, I, J));
 }
 
 // Source of the linear prolongation extended by one linearly extrapolated
@@ -172,9 +181,13 @@ __device__ __forceinline__ double linear_value(int I, int J, F E) {
 }
 
 template <typename T>
-__device__ __forceinline__ void linear_point(const XArgs& x, int I, int J) {
+__device__ __forceinline__ double linear_at(const XArgs& x, int I, int J) {
   const LExt<T> E{(const T*)x.s0, x.h0, x.w0, x.p0};
-  ((T*)x.dst)[(size_t)I * x.pd + J] = to_t<T>(linear_value(I, J, E));
+  return linear_value(I, J, E);
+}
+template <typename T>
+__device__ __forceinline__ void linear_point(const XArgs& x, int I, int J) {
+  ((T*)x.dst)[(size_t)I * x.pd + J] = to_t<T>(linear_at<T>(x, I, J));
 }
 
 // Local smoothing S (Section 3.3, eq. 18-19): weighted LS fit of
@@ -268,12 +281,15 @@ __device__ __forceinline__ double smooth_value(int i, int j, int H, int W, doubl
 }
 
 template <typename T>
-__device__ __forceinline__ void smooth_point(const XArgs& x, int i, int j) {
+__device__ __forceinline__ double smooth_at(const XArgs& x, int i, int j) {
   const T* u = (const T*)x.s0;
   const int P = x.p0;
-  const double v = smooth_value<sizeof(T) == 4>(i, j, x.h0, x.w0, 1.0 / x.a0,
-                                                [&](int ii, int jj) { return (double)u[(size_t)ii * P + jj]; });
-  ((T*)x.dst)[(size_t)i * x.pd + j] = to_t<T>(v);
+  return smooth_value<sizeof(T) == 4>(i, j, x.h0, x.w0, 1.0 / x.a0,
+                                      [&](int ii, int jj) { return (double)u[(size_t)ii * P + jj]; });
+}
+template <typename T>
+__device__ __forceinline__ void smooth_point(const XArgs& x, int i, int j) {
+  ((T*)x.dst)[(size_t)i * x.pd + j] = to_t<T>(smooth_at<T>(x, i, j));
 }
 
 // One explicit Perona-Malik step (Section 4, eq. 21, 23-25):
@@ -307,13 +323,16 @@ __device__ __forceinline__ double pm_value(int i, int j, int H, int W, double ta
 }
 
 template <typename T>
-__device__ __forceinline__ void pm_point(const XArgs& x, int i, int j) {
+__device__ __forceinline__ double pm_at(const XArgs& x, int i, int j) {
   const T* u = (const T*)x.s0;
   const int P = x.p0, H = x.h0, W = x.w0;
   const double ik2 = 1.0 / (x.a0 * x.a0);
   auto U = [&](int ii, int jj) { return (double)u[(size_t)ii * P + jj]; };
-  const double v = pm_value(i, j, H, W, x.a1, U, [&](int ii, int jj) { return pm_c(ii, jj, H, W, ik2, U); });
-  ((T*)x.dst)[(size_t)i * x.pd + j] = to_t<T>(v);
+  return pm_value(i, j, H, W, x.a1, U, [&](int ii, int jj) { return pm_c(ii, jj, H, W, ik2, U); });
+}
+template <typename T>
+__device__ __forceinline__ void pm_point(const XArgs& x, int i, int j) {
+  ((T*)x.dst)[(size_t)i * x.pd + j] = to_t<T>(pm_at<T>(x, i, j));
 }
 
 // Pixel loop of one 64 x 16 tile of the destination grid.
@@ -348,11 +367,9 @@ __device__ __forceinline__ void* xbuf(const JobDesc& d, int sel) {
   }
 }
 
-// Engine form: the job's descriptor supplies the grids and buffers.
-template <typename T, int OP>
-__global__ __launch_bounds__(256) void k_xfer(LaunchList ll, const JobDesc* __restrict__ descs, int src, int dst) {
-  const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
-  const JobDesc& d = descs[L.d];
+// Grids and buffers of one transfer stage from the job's descriptor.
+template <int OP>
+__device__ __forceinline__ XArgs make_xargs(const JobDesc& d, int src, int dst) {
   XArgs x;
   if (OP == kXfExtrap) {
     x.s0 = d.uA;
@@ -376,7 +393,14 @@ __global__ __launch_bounds__(256) void k_xfer(LaunchList ll, const JobDesc* __re
   }
   x.a0 = (OP == kXfSmooth) ? d.smooth_h : d.pm_k;
   x.a1 = d.tau;
-  xfer_tile<T, OP>(x, L.t);
+  return x;
+}
+
+// Engine form: the job's descriptor supplies the grids and buffers.
+template <typename T, int OP>
+__global__ __launch_bounds__(256) void k_xfer(LaunchList ll, const JobDesc* __restrict__ descs, int src, int dst) {
+  const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
+  xfer_tile<T, OP>(make_xargs<OP>(descs[L.d], src, dst), L.t);
 }
 
 // Operator form on one dense image.
@@ -542,6 +566,379 @@ __global__ __launch_bounds__(256) void k_xfer_fused_op(FArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Coarse cascade: the leading small levels of one job solved by a single
+// 1024-thread block -- each level's transfer (the stages above, one after
+// another), the smoother's initialisation and every iteration with its
+// stopping test -- so they cost one launch instead of a dozen per level, and
+// the coarse levels of a batch of images run side by side.  The scalar
+// recurrences are the finalize functions of the multi-block passes, run by
+// thread 0 on block-reduced partials (fixed order: deterministic) and on a
+// solver state kept in LDS; the host does not follow these levels, so no
+// progress word is published.
+// ---------------------------------------------------------------------------
+constexpr int kCoarseThreads = 1024;
+constexpr int kCoarseWaves = kCoarseThreads / 64;
+
+// Sum NV per-thread values over the block; every thread gets the sums.
+template <int NV>
+__device__ __forceinline__ void coarse_reduce(double (&v)[NV]) {
+  __shared__ double red[kCoarseWaves][NV];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) red[wave][i] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double a = red[0][i];
+#pragma unroll
+    for (int w = 1; w < kCoarseWaves; ++w) a += red[w][i];
+    v[i] = a;
+  }
+  __syncthreads();
+}
+
+// Every sweep hands each thread kCoarseU pixels at a time (k, k + 1024, ...)
+// and issues all of their loads before using any, so one block keeps enough
+// memory requests in flight on the small levels.
+constexpr int kCoarseU = 4;
+
+struct Px {
+  int i, j;
+  bool ok;   // inside the level (k < h w)
+  size_t o;  // pitched offset (of pixel 0 when !ok)
+};
+
+__device__ __forceinline__ Px px_at(int k, int n, int w, int P) {
+  Px p;
+  p.ok = k < n;
+  const int kk = p.ok ? k : 0;
+  p.i = kk / w;
+  p.j = kk - p.i * w;
+  p.o = (size_t)p.i * P + p.j;
+  return p;
+}
+
+template <int U = kCoarseU, typename F>
+__device__ __forceinline__ void coarse_sweep(int n, int w, int P, F body) {
+  for (int k0 = threadIdx.x; k0 < n; k0 += U * kCoarseThreads) {
+    Px px[U];
+#pragma unroll
+    for (int m = 0; m < U; ++m) px[m] = px_at(k0 + m * kCoarseThreads, n, w, P);
+    body(px);
+  }
+}
+
+// (H x)(i, j) = sum_{a,b} psf(a,b) x(i-a, j-b), zero outside the image, from
+// the full (2R+1)^2 taps (H^T: the flipped taps), for kCoarseU pixels: each
+// tap's loads (from clamped, always valid positions) are issued together.
+template <typename T>
+__device__ __forceinline__ void coarse_conv(const T* __restrict__ x, int pitch, int h, int w,
+                                            const T* __restrict__ taps, int R, const Px (&px)[kCoarseU],
+                                            T (&acc)[kCoarseU]) {
+  const int n = 2 * R + 1;
+#pragma unroll
+  for (int m = 0; m < kCoarseU; ++m) acc[m] = T(0);
+  for (int a = -R; a <= R; ++a) {
+    for (int b = -R; b <= R; ++b) {
+      const T wt = taps[(a + R) * n + (b + R)];
+      T v[kCoarseU];
+#pragma unroll
+      for (int m = 0; m < kCoarseU; ++m) {
+        const int y = px[m].i - a, xx = px[m].j - b;
+        const bool in = y >= 0 && y < h && xx >= 0 && xx < w;
+        const T t = x[(size_t)min(max(y, 0), h - 1) * pitch + min(max(xx, 0), w - 1)];
+        v[m] = in ? t : T(0);
+      }
+#pragma unroll
+      for (int m = 0; m < kCoarseU; ++m) acc[m] = fma(wt, v[m], acc[m]);
+    }
+  }
+}
+
+// One transfer stage over its destination grid, then a block barrier.  The
+// point operators keep a few dozen values live each, so the stages take two
+// pixels at a time (S, the largest, one).
+template <typename T, int OP>
+__device__ __forceinline__ void coarse_stage(const JobDesc& d, int src, int dst) {
+  constexpr int U = OP == kXfSmooth ? 1 : 2;
+  const XArgs x = make_xargs<OP>(d, src, dst);
+  coarse_sweep<U>(x.hd * x.wd, x.wd, x.pd, [&](const Px (&px)[U]) {
+    double v[U];
+#pragma unroll
+    for (int m = 0; m < U; ++m) {
+      if (OP == kXfExtrap)
+        v[m] = pi_value<T>(x, px[m].i, px[m].j);
+      else if (OP == kXfQuad)
+        v[m] = quad_at<T>(x, px[m].i, px[m].j);
+      else if (OP == kXfLinear)
+        v[m] = linear_at<T>(x, px[m].i, px[m].j);
+      else if (OP == kXfSmooth)
+        v[m] = smooth_at<T>(x, px[m].i, px[m].j);
+      else
+        v[m] = pm_at<T>(x, px[m].i, px[m].j);
+    }
+#pragma unroll
+    for (int m = 0; m < U; ++m)
+      if (px[m].ok) ((T*)x.dst)[px[m].o] = to_t<T>(v[m]);
+  });
+  __syncthreads();
+}
+
+// Transfer into the level (the stage sequence of the multi-level engine).
+template <typename T>
+__device__ void coarse_transfer(const JobDesc& d) {
+  const int l = d.level, n = d.pm_steps;
+  int src;
+  if (d.cascade == kCascadeEecmg) {
+    if (l < 2) return;  // the two coarsest levels start from zero
+    coarse_stage<T, kXfExtrap>(d, -1, kBufT2);
+    src = kBufT2;
+  } else {
+    if (l < 1) return;
+    src = kBufUB;
+  }
+  if (d.cascade == kCascadeIecmgL)
+    coarse_stage<T, kXfLinear>(d, src, kBufT1);
+  else
+    coarse_stage<T, kXfQuad>(d, src, kBufT1);
+  coarse_stage<T, kXfSmooth>(d, kBufT1, n == 0 ? kBufU : kBufT2);
+  for (int s = 0; s < n; ++s) {
+    const int a = (s % 2 == 0) ? kBufT2 : kBufT1;
+    const int b = (s == n - 1) ? kBufU : ((s % 2 == 0) ? kBufT1 : kBufT2);
+    coarse_stage<T, kXfPm>(d, a, b);
+  }
+}
+
+// CGLS on one level: the arithmetic of the multi-block passes (init, pass A
+// with p = s + beta p and q = H p, pass B with r -= alpha q, u += alpha p and
+// s = H^T r), with a block barrier between dependent sweeps.
+template <typename T>
+__device__ void coarse_cgls(const JobDesc& d) {
+  const int h = d.h, w = d.w, P = d.pitch, R = d.rad, n = h * w;
+  const T* __restrict__ g = (const T*)d.g;
+  T* __restrict__ u = (T*)d.u;
+  T* __restrict__ r = (T*)d.r[0];
+  T* __restrict__ p = (T*)d.p[0];
+  T* __restrict__ s = (T*)d.s;
+  T* __restrict__ q = (T*)d.q[0];
+  const T* __restrict__ tp = (const T*)d.taps;
+  const T* __restrict__ tt = (const T*)d.taps_t;
+  __shared__ SolverState state;  // the level's scalars stay on chip
+  SolverState* st = &state;
+  __shared__ double sc[2];
+  __shared__ int done;
+  double v[2] = {0.0, 0.0};
+  coarse_sweep(n, w, P, [&](const Px (&px)[kCoarseU]) {
+    T hv[kCoarseU], gv[kCoarseU];
+#pragma unroll
+    for (int m = 0; m < kCoarseU; ++m) gv[m] = g[px[m].o];
+    coarse_conv(u, P, h, w, tp, R, px, hv);
+#pragma unroll
+    for (int m = 0; m < kCoarseU; ++m)
+      if (px[m].ok) {
+        const T rv = gv[m] - hv[m];
+        r[px[m].o] = rv;
+        v[0] += (double)rv * (double)rv;
+      }
+  });
+  __syncthreads();
+  coarse_sweep(n, w, P, [&](const Px (&px)[kCoarseU]) {
+    T sv[kCoarseU];
+    coarse_conv(r, P, h, w, tt, R, px, sv);
+#pragma unroll
+    for (int m = 0; m < kCoarseU; ++m)
+      if (px[m].ok) {
+        s[px[m].o] = sv[m];
+        p[px[m].o] = sv[m];
+        v[1] += (double)sv[m] * (double)sv[m];
+      }
+  });
+  coarse_reduce(v);
+  if (threadIdx.x == 0) {
+    fin_cg_init(d, st, v, false);
+    done = st->done;
+  }
+  __syncthreads();
+  bool first = true;
+  while (!done) {
+    if (!first) {
+      const T beta = (T)sc[1];
+      coarse_sweep(n, w, P, [&](const Px (&px)[kCoarseU]) {
+        T a[kCoarseU], b[kCoarseU];
+#pragma unroll
+        for (int m = 0; m < kCoarseU; ++m) {
+          a[m] = p[px[m].o];
+          b[m] = s[px[m].o];
+        }
+#pragma unroll
+        for (int m = 0; m < kCoarseU; ++m)
+          if (px[m].ok) p[px[m].o] = fma(beta, a[m], b[m]);
+      });
+      __syncthreads();
+    }
+    first = false;
+    double e[1] = {0.0};
+    coarse_sweep(n, w, P, [&](const Px (&px)[kCoarseU]) {
+      T qv[kCoarseU];
+      coarse_conv(p, P, h, w, tp, R, px, qv);
+#pragma unroll
+      for (int m = 0; m < kCoarseU; ++m)
+        if (px[m].ok) {
+          q[px[m].o] = qv[m];
+          e[0] += (double)qv[m] * (double)qv[m];
+        }
+    });
+    coarse_reduce(e);
+    if (threadIdx.x == 0) {
+      fin_cg_a(d, st, e, false);
+      done = st->done;
+      sc[0] = st->alpha;
+    }
+    __syncthreads();
+    if (done) break;
+    const T alpha = (T)sc[0];
+    double b[2] = {0.0, 0.0};
+    coarse_sweep(n, w, P, [&](const Px (&px)[kCoarseU]) {
+      T qv[kCoarseU], rv[kCoarseU], pv[kCoarseU], uv[kCoarseU];
+#pragma unroll
+      for (int m = 0; m < kCoarseU; ++m) {
+        qv[m] = q[px[m].o];
+        rv[m] = r[px[m].o];
+        pv[m] = p[px[m].o];
+        uv[m] = u[px[m].o];
+      }
+#pragma unroll
+      for (int m = 0; m < kCoarseU; ++m)
+        if (px[m].ok) {
+          const T rn = fma(-alpha, qv[m], rv[m]);
+          r[px[m].o] = rn;
+          u[px[m].o] = fma(alpha, pv[m], uv[m]);
+          b[0] += (double)rn * (double)rn;
+        }
+    });
+    __syncthreads();
+    coarse_sweep(n, w, P, [&](const Px (&px)[kCoarseU]) {
+      T sv[kCoarseU];
+      coarse_conv(r, P, h, w, tt, R, px, sv);
+#pragma unroll
+      for (int m = 0; m < kCoarseU; ++m)
+        if (px[m].ok) {
+          s[px[m].o] = sv[m];
+          b[1] += (double)sv[m] * (double)sv[m];
+        }
+    });
+    coarse_reduce(b);
+    if (threadIdx.x == 0) {
+      fin_cg_b(d, st, b, false);
+      done = st->done;
+      sc[1] = st->beta;
+    }
+    __syncthreads();
+  }
+}
+
+// MR on one level (the arithmetic of the multi-block MR pass).
+template <typename T>
+__device__ void coarse_mr(const JobDesc& d) {
+  const int h = d.h, w = d.w, P = d.pitch, R = d.rad, n = h * w;
+  const T* __restrict__ g = (const T*)d.g;
+  T* __restrict__ u = (T*)d.u;
+  T* __restrict__ r = (T*)d.r[0];
+  T* __restrict__ q = (T*)d.q[0];
+  const T* __restrict__ tp = (const T*)d.taps;
+  __shared__ SolverState state;  // the level's scalars stay on chip
+  SolverState* st = &state;
+  __shared__ double sc[1];
+  __shared__ int done, pending;
+  double v[1] = {0.0};
+  coarse_sweep(n, w, P, [&](const Px (&px)[kCoarseU]) {
+    T hv[kCoarseU], gv[kCoarseU];
+#pragma unroll
+    for (int m = 0; m < kCoarseU; ++m) gv[m] = g[px[m].o];
+    coarse_conv(u, P, h, w, tp, R, px, hv);
+#pragma unroll
+    for (int m = 0; m < kCoarseU; ++m)
+      if (px[m].ok) {
+        const T rv = gv[m] - hv[m];
+        r[px[m].o] = rv;
+        v[0] += (double)rv * (double)rv;
+      }
+  });
+  coarse_reduce(v);
+  if (threadIdx.x == 0) {
+    fin_mr_init(d, st, v, false);
+    done = st->done;
+    pending = 0;
+  }
+  __syncthreads();
+  while (!done) {
+    if (pending) {
+      const T alpha = (T)sc[0];
+      coarse_sweep(n, w, P, [&](const Px (&px)[kCoarseU]) {
+        T rv[kCoarseU], qv[kCoarseU], uv[kCoarseU];
+#pragma unroll
+        for (int m = 0; m < kCoarseU; ++m) {
+          rv[m] = r[px[m].o];
+          qv[m] = q[px[m].o];
+          uv[m] = u[px[m].o];
+        }
+#pragma unroll
+        for (int m = 0; m < kCoarseU; ++m)
+          if (px[m].ok) {
+            u[px[m].o] = fma(alpha, rv[m], uv[m]);
+            r[px[m].o] = fma(-alpha, qv[m], rv[m]);
+          }
+      });
+      __syncthreads();
+    }
+    double mm[3] = {0.0, 0.0, 0.0};
+    coarse_sweep(n, w, P, [&](const Px (&px)[kCoarseU]) {
+      T qv[kCoarseU], rc[kCoarseU];
+#pragma unroll
+      for (int m = 0; m < kCoarseU; ++m) rc[m] = r[px[m].o];
+      coarse_conv(r, P, h, w, tp, R, px, qv);
+#pragma unroll
+      for (int m = 0; m < kCoarseU; ++m)
+        if (px[m].ok) {
+          q[px[m].o] = qv[m];
+          mm[0] += (double)rc[m] * (double)qv[m];
+          mm[1] += (double)rc[m] * (double)rc[m];
+          mm[2] += (double)qv[m] * (double)qv[m];
+        }
+    });
+    coarse_reduce(mm);
+    if (threadIdx.x == 0) {
+      fin_mr(d, st, mm, false);
+      done = st->done;
+      pending = st->pending;
+      sc[0] = st->alpha;
+    }
+    __syncthreads();
+  }
+}
+
+// descs[ll.job[e]] is level 0 of job e; its coarse_levels leading levels are
+// solved here, level by level.
+template <typename T>
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse(LaunchList ll, const JobDesc* __restrict__ descs) {
+  const int d0 = ll.job[blockIdx.x];
+  const int nl = descs[d0].coarse_levels;
+  for (int l = 0; l < nl; ++l) {
+    const JobDesc& d = descs[d0 + l];
+    coarse_transfer<T>(d);
+    if (d.smoother == kSmootherMr)
+      coarse_mr<T>(d);
+    else
+      coarse_cgls<T>(d);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Restriction (eq. 12-13) and output copy
 // ---------------------------------------------------------------------------
 // One pass over the dense finest-level input writes every level's
@@ -637,6 +1034,7 @@ int blocks_for_stage(Stage st, const JobDesc& d) {
     case kXfExtrap: return tiles2(d.hB, d.wB, kXH, kXW);
     case kXfFused: return tiles2(d.h, d.w, kFY, kFX);
     case kXfFusedSmall: return tiles2(d.h, d.w, kFYSmall, kFX);
+    case kCoarse: return 1;
     default: return tiles2(d.h, d.w, kXH, kXW);
   }
 }
@@ -689,6 +1087,9 @@ static hipError_t launch_typed(Stage st, int variant, const LaunchList& ll, cons
       return hipGetLastError();
     case kXfPm:
       hipLaunchKernelGGL((k_xfer<T, kXfPm>), grid, block, 0, s, ll, descs, src, dst);
+      return hipGetLastError();
+    case kCoarse:
+      hipLaunchKernelGGL(k_coarse<T>, dim3(ll.n), dim3(kCoarseThreads), 0, s, ll, descs);
       return hipGetLastError();
     case kXfFused: return launch_fused<T, kFY>(variant, grid, ll, descs, src, dst, s);
     case kXfFusedSmall: return launch_fused<T, kFYSmall>(variant, grid, ll, descs, src, dst, s);

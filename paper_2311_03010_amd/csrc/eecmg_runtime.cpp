@@ -68,10 +68,23 @@ static int sym_span_h(int R, bool disk, int a) {
 //   symmetric in both axes, disk support -> row-filter kernel on the quadrant
 //   symmetric in both axes               -> same with square support (R <= 6)
 //   otherwise                            -> general (all taps)
-static void choose_variant(LevelPlan& lp, bool f64) {
+// Small levels with small radii always take the general kernels: their
+// whole-tile loads (four waves per tile, all rows at once) have far less
+// latency per launch than one wave streaming down each strip.
+constexpr long kSmallLevelPixels = 1024L * 1024L;
+// Levels up to this many pixels (the leading ones of a cascade) are solved
+// by one block per job in a single launch.
+constexpr long kCoarsePixels = 64L * 64L;
+static void choose_variant(LevelPlan& lp, bool f64, bool by_size) {
   const int R = lp.rad, n = 2 * R + 1;
   const std::vector<double>& P = lp.psf;
   auto at = [&](int a, int b) { return P[(a + R) * n + (b + R)]; };
+  if (by_size && (long)lp.h * lp.w <= kSmallLevelPixels && R <= 3) {
+    lp.variant = kConvGeneral * 100 + rmax_class_for(R);
+    lp.taps = P;
+    lp.taps_t.assign(P.rbegin(), P.rend());
+    return;
+  }
   int a0 = 0, b0 = 0;
   double mx = 0.0;
   for (int a = -R; a <= R; ++a)
@@ -145,6 +158,7 @@ struct Plan {
   size_t off_work[7] = {};  // r0 r1 p0 p1 s q0 q1
   size_t bytes = 0;
   int max_tiles = 0;
+  int coarse = 0;  // leading levels solved by the coarse-cascade kernel
 };
 
 // Economic iteration counts (Section 2): for l > L/2,
@@ -269,6 +283,9 @@ static int build_plan(int H, int W, const double* psf, int r, int L, const int* 
   // solve order
   P.order.clear();
   for (int l = 0; l < L; ++l) P.order.push_back(l);
+  // leading small levels go to the coarse-cascade kernel (full taps)
+  P.coarse = 0;
+  while (P.coarse < L && (long)P.lv[P.coarse].h * P.lv[P.coarse].w <= kCoarsePixels) P.coarse += 1;
   // tiles and layout
   const size_t pitch_elems = P.f64 ? 32 : 64;  // 256-byte rows
   size_t off = 0;
@@ -278,7 +295,14 @@ static int build_plan(int H, int W, const double* psf, int r, int L, const int* 
     return o;
   };
   for (int l = 0; l < L; ++l) {
-    choose_variant(P.lv[l], P.f64);
+    if (l < P.coarse) {
+      LevelPlan& lp = P.lv[l];
+      lp.variant = kConvGeneral * 100 + rmax_class_for(lp.rad);
+      lp.taps = lp.psf;
+      lp.taps_t.assign(lp.psf.rbegin(), lp.psf.rend());
+    } else {
+      choose_variant(P.lv[l], P.f64, true);
+    }
     P.off_taps[l] = take(P.lv[l].taps.size() * P.esz);
     P.off_tapst[l] = take(P.lv[l].taps_t.size() * P.esz);
   }
@@ -450,7 +474,7 @@ static Profiler& profiler() {
 static bool profiled_stage(Stage st) {
   return st == kCgInit1 || st == kCgInit2 || st == kCgA || st == kCgB || st == kMrInit || st == kMrPass ||
          st == kXfExtrap || st == kXfQuad || st == kXfLinear || st == kXfSmooth || st == kXfPm || st == kXfFused ||
-         st == kXfFusedSmall;
+         st == kXfFusedSmall || st == kCoarse;
 }
 
 // ---------------------------------------------------------------------------
@@ -483,7 +507,8 @@ struct Job {
   size_t host_bytes = 0;
   std::atomic<bool> cancelled{false};
   double t_submit = 0.0, t_done = 0.0;
-  int cur_level() const { return plan.order[oi]; }
+  // valid while the job is on a level (phases kStartLevel and kIter)
+  int cur_level() const { return oi < (int)plan.order.size() ? plan.order[oi] : -1; }
 };
 
 static double now_s() {
@@ -594,7 +619,7 @@ class Engine {
     poll_mirror();
     finished.clear();
     // action lists
-    std::vector<Job*> restrict_l, out_l;
+    std::vector<Job*> restrict_l, out_l, coarse_l;
     std::vector<std::pair<Job*, int>> xfer_l;  // job, level
     std::vector<Job*> init_l;
     std::vector<std::pair<Job*, int>> iter_l;  // job, chunk
@@ -610,6 +635,17 @@ class Engine {
             restrict_l.push_back(j);
             j->phase = Job::kStartLevel;
             j->oi = 0;
+            if (j->plan.coarse > 0) {
+              // the leading small levels in one launch, stream-ordered
+              // before everything issued for the levels after them
+              coarse_l.push_back(j);
+              j->oi = j->plan.coarse;
+              if (j->oi >= (int)j->plan.order.size()) {
+                out_l.push_back(j);
+                j->phase = Job::kOutput;
+                break;
+              }
+            }
             again = true;
             break;
           case Job::kStartLevel: {
@@ -667,7 +703,18 @@ class Engine {
     }
     // launches, in dependency order
     if (!restrict_l.empty()) {
-      launch_group(kRestrict, restrict_l, -1, false, 0, -1, -1);
+      // level 0's descriptor: the restriction fields are the same on every
+      // level, and a job whose levels are all coarse has no current level
+      launch_group(kRestrict, restrict_l, 0, false, 0, -1, -1);
+      launched = true;
+    }
+    if (!coarse_l.empty()) {
+      for (int f64 = 0; f64 < 2; ++f64) {
+        std::vector<Job*> js;
+        for (Job* j : coarse_l)
+          if ((int)j->plan.f64 == f64) js.push_back(j);
+        if (!js.empty()) launch_group(kCoarse, js, 0, f64 != 0, 0, -1, -1);
+      }
       launched = true;
     }
     if (!xfer_l.empty()) {
@@ -794,6 +841,9 @@ class Engine {
     d.level = l;
     d.stop_rule = P.prm.stop_rule;
     d.smoother = P.prm.smoother;
+    d.cascade = P.prm.cascade;
+    d.pm_steps = P.prm.pm_steps;
+    d.coarse_levels = l == 0 ? P.coarse : 0;
     d.cdelta = P.prm.c * P.prm.delta;
     d.eps2 = P.eps2;
     d.st = d_state_ + j->slot;
@@ -845,6 +895,10 @@ class Engine {
     ll.total = 0;
     for (Job* j : jobs) {
       const int l = level >= 0 ? level : j->cur_level();
+      if (l < 0 || l >= j->plan.L) {  // never launch with a descriptor that does not exist
+        if (err_ == hipSuccess) err_ = hipErrorInvalidValue;
+        return;
+      }
       const int di = j->slot * kMaxLevels + l;
       const JobDesc& hd = h_desc_[di];
       ll.job[ll.n] = di;
@@ -1279,7 +1333,7 @@ static int op_taps(const double* psf, int r, bool f64, bool flip, void** d_taps,
   LevelPlan lp;
   lp.rad = r;
   lp.psf.assign(psf, psf + (size_t)n * n);
-  choose_variant(lp, f64);
+  choose_variant(lp, f64, false);  // operator calls: by the PSF only
   *variant = lp.variant;
   const std::vector<double>& t = flip ? lp.taps_t : lp.taps;
   const size_t bytes = t.size() * (f64 ? 8 : 4);
