@@ -7,7 +7,18 @@ discrepancy stopping rule (c = 1.1).  A step is one complete restore
 (restriction, every level's smoother and transfer) of a device-resident
 input into a device-resident output.
 
-Prints one JSON line.  Besides the throughput it reports
+Prints one JSON line.  Besides the throughput (`value`, the plain form) it
+reports
+  batched:       the same image restored as a batch of copies in one
+                 batched cascade;
+  uneven_set:    256 images with sides log-uniform in [128, 2048] and a mix
+                 of Gaussian and disk PSFs, restored one call per image
+                 (plain) and as one batched cascade, with the bitwise
+                 agreement of the two;
+  served:        requests (sides log-uniform in [64, 4096]) through the
+                 create/submit/poll loop: closed-loop capacity, then Poisson
+                 arrivals at 0.7 of it, with p50/p99 latency from arrival to
+                 the poll that returns the result;
   roofline:      the finest-level CGLS pass B kernel (dominant), algorithmic
                  HBM bytes per launch / its mean duration from HIP events on
                  the library's launch stream during the timed region (launches
@@ -91,6 +102,153 @@ def cpu_baseline(p, stats):
                       f"oracle iterations per level {st['iters']} (GPU {stats['iters']})"}
 
 
+def _pct(xs, q):
+    return float(np.percentile(np.asarray(xs), q))
+
+
+def set_leg(torch, eecmg, synth, n_images, steps):
+    """The uneven batch: n_images images with sides log-uniform in
+    [128, 2048] and a mix of Gaussian and disk PSFs, each restored with its
+    own level count.  Plain = one restore call per image in turn; batched =
+    one batched cascade for the whole set.  Both read device-resident inputs
+    and write device-resident outputs; their results must agree bit for bit."""
+    probs = synth.batch_problems(n_images)
+    gs = [torch.from_numpy(q.g_delta.astype(np.float32)).to("cuda:0") for q in probs]
+    px = sum(q.g_delta.size for q in probs)
+    po = [torch.empty_like(g) for g in gs]
+    bo = [torch.empty_like(g) for g in gs]
+    psfs = [q.psf for q in probs]
+    Ls = [q.n_levels for q in probs]
+    ks = [q.k for q in probs]
+    prm = [{"delta": q.delta} for q in probs]
+
+    def plain():
+        for q, g, o in zip(probs, gs, po):
+            eecmg.restore_dev(g, q.psf, q.n_levels, out=o, precision="f32", delta=q.delta, k=q.k)
+
+    def batched():
+        eecmg.restore_batch_dev(gs, psfs, Ls, ks=ks, outs=bo, precision="f32", params=prm)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    tp = timed(plain)
+    tb = timed(batched)
+    equal = all(torch.equal(a, b) for a, b in zip(po, bo))
+    return {"workload": f"uneven batch of {n_images} images, sides log-uniform in [128, 2048], "
+                        "Gaussian sigma U[1,4] / disk r U{2..6} PSFs, FP32",
+            "images": n_images, "mpixels": round(px / 1e6, 3), "steps": steps,
+            "plain": {"value": round(px / tp / 1e6, 3), "unit": "Mpixel/s", "ms_per_step": round(tp * 1e3, 3)},
+            "batched": {"value": round(px / tb / 1e6, 3), "unit": "Mpixel/s", "ms_per_step": round(tb * 1e3, 3)},
+            "speedup_vs_plain": round(tp / tb, 3), "bitwise_equal_to_plain": bool(equal)}
+
+
+def served_leg(torch, eecmg, synth, n_req, pool_n, load=0.7, check_every=8):
+    """Served requests through the create/submit/poll loop.  Request images
+    come from a pool of pool_n distinct images with sides log-uniform in
+    [64, 4096]; each request is host in, host out (the context stages it
+    through pinned memory).  First the closed-loop capacity (the whole pool
+    submitted at once), then Poisson arrivals at `load` times that capacity;
+    latency runs from a request's scheduled arrival to the poll that returns
+    its result.  Every check_every-th served result is compared bit for bit
+    with a plain device restore of the same image."""
+    import threading
+
+    pool = synth.served_pool(pool_n)
+    ins = [np.ascontiguousarray(q.g_delta.astype(np.float32)) for q in pool]
+    pxs = [q.g_delta.size for q in pool]
+    kw = [dict(precision="f32", delta=q.delta, k=q.k) for q in pool]
+    # plain: one host-in / host-out restore call per image in turn
+    eecmg.restore(ins[0], pool[0].psf, pool[0].n_levels, **kw[0])
+    t0 = time.perf_counter()
+    refs = [eecmg.restore(x, q.psf, q.n_levels, **k)[0] for q, x, k in zip(pool, ins, kw)]
+    dt_plain = time.perf_counter() - t0
+    budget = 24 << 30
+    with eecmg.Context(hbm_budget_bytes=budget, max_slots=64, max_queue=n_req + pool_n) as ctx:
+        def closed():
+            t0 = time.perf_counter()
+            rs = [ctx.submit(x, q.psf, q.n_levels, **k) for q, x, k in zip(pool, ins, kw)]
+            outs = [ctx.wait(r)[0] for r in rs]
+            return time.perf_counter() - t0, outs
+
+        closed()
+        dt_c, outs = closed()
+        closed_ok = all(np.array_equal(a, b) for a, b in zip(outs, refs))
+        cap_qps = pool_n / dt_c
+        qps = load * cap_qps
+        arr = synth.poisson_arrivals(n_req, qps)
+        scratch = [np.empty_like(x) for x in ins]
+        done_t = np.zeros(n_req)
+        checked = {}
+        pending = []
+        lock = threading.Lock()
+        finished = threading.Event()
+        submitted = [0]
+
+        def poller():
+            live = []
+            n_done = 0
+            while n_done < n_req:
+                with lock:
+                    live.extend(pending)
+                    pending.clear()
+                hit = False
+                still = []
+                for i, req, buf in live:
+                    if ctx.poll(req, out=buf) is not None:
+                        done_t[i] = time.perf_counter()
+                        n_done += 1
+                        hit = True
+                    else:
+                        still.append((i, req, buf))
+                live = still
+                if not hit:
+                    time.sleep(0.0001)
+            finished.set()
+
+        th = threading.Thread(target=poller, daemon=True)
+        th.start()
+        start = time.perf_counter()
+        for i in range(n_req):
+            wait = start + arr[i] - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            j = i % pool_n
+            buf = scratch[j]
+            if i % check_every == 0:
+                buf = np.empty_like(ins[j])
+                checked[i] = buf
+            req = ctx.submit(ins[j], pool[j].psf, pool[j].n_levels, **kw[j])
+            with lock:
+                pending.append((i, req, buf))
+            submitted[0] += 1
+        finished.wait()
+        th.join()
+    lat = (done_t - (start + arr)) * 1e3
+    span = done_t.max() - start
+    px_total = sum(pxs[i % pool_n] for i in range(n_req))
+    served_ok = all(np.array_equal(buf, refs[i % pool_n]) for i, buf in checked.items())
+    return {"workload": f"{n_req} requests, Poisson arrivals, image sides log-uniform in [64, 4096] "
+                        f"(pool of {pool_n} distinct images), Gaussian/disk PSF mix, FP32, host in / host out",
+            "requests": n_req, "pool_images": pool_n, "hbm_budget_bytes": budget, "max_slots": 64,
+            "closed_loop_capacity": {"value": round(sum(pxs) / dt_c / 1e6, 3), "unit": "Mpixel/s",
+                                     "requests_per_s": round(cap_qps, 2)},
+            "offered_qps": round(qps, 2), "load_vs_capacity": load,
+            "value": round(px_total / span / 1e6, 3), "unit": "Mpixel/s",
+            "latency_ms": {"p50": round(_pct(lat, 50), 3), "p99": round(_pct(lat, 99), 3),
+                           "mean": round(float(lat.mean()), 3), "max": round(float(lat.max()), 3)},
+            "plain": {"value": round(sum(pxs) / dt_plain / 1e6, 3), "unit": "Mpixel/s",
+                      "form": "one eecmg_restore call (host in / host out) per pool image in turn"},
+            "closed_loop_speedup_vs_plain": round(dt_plain / dt_c, 3),
+            "bitwise_equal_to_plain": bool(closed_ok and served_ok), "checked": len(checked) + pool_n}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +257,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", type=int, default=3, choices=[1, 2, 3])
     ap.add_argument("--batch", type=int, default=4, help="images in the batched leg (0 = skip)")
+    ap.add_argument("--set-images", type=int, default=256,
+                    help="images in the uneven plain-vs-batched set (0 = skip)")
+    ap.add_argument("--set-steps", type=int, default=2)
+    ap.add_argument("--served-requests", type=int, default=2000, help="served requests (0 = skip)")
+    ap.add_argument("--served-pool", type=int, default=64)
     ap.add_argument("--copy-probe", action="store_true", help="only run the HBM counter calibration copy")
     args = ap.parse_args()
     if args.copy_probe:
@@ -191,19 +354,32 @@ def main():
                    "unit": "Mpixel/s", "ms_per_step": round(bdt / args.steps * 1e3, 3),
                    "speedup_vs_plain": round(len(gs) * H * W * args.steps / bdt / 1e6 / value, 3)}
 
+    uneven = None
+    if args.set_images > 0:
+        _log(f"bench: uneven set, {args.set_images} images, plain vs batched")
+        uneven = set_leg(torch, eecmg, synth, args.set_images, args.set_steps)
+
+    served = None
+    if args.served_requests > 0:
+        _log(f"bench: served, {args.served_requests} requests")
+        served = served_leg(torch, eecmg, synth, args.served_requests, args.served_pool)
+
     cpu = None
     if not args.no_cpu_baseline:
         _log("bench: cpu baseline (oracle sample)")
         cpu = cpu_baseline(p, stats)
 
-    line = {"metric": "restored Mpixel/s (plain EECMG, 4096^2)" if args.workload == 3 else "restored Mpixel/s",
+    metric = ("restored Mpixel/s plain vs batched at 4096\u00b2; p50/p99 latency; % HBM roofline"
+              if args.workload == 3 else "restored Mpixel/s")
+    line = {"metric": metric,
             "value": round(value, 3), "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f32" if prec != "f64" else "f64", "data": "synthetic",
             "config": {"workload": p.name, "H": H, "W": W, "psf": "disk r=6" if args.workload == 3 else "gaussian",
                        "n_levels": p.n_levels, "precision": prec, "stop_rule": "discrepancy c=1.1",
                        "caps": "economic m_l rule", "form": "plain"},
-            "roofline": roofline, "cpu_baseline": cpu, "batched": batched, "detail": extra}
+            "roofline": roofline, "cpu_baseline": cpu, "batched": batched, "uneven_set": uneven,
+            "served": served, "detail": extra}
     print(json.dumps(line), flush=True)
 
 

@@ -138,6 +138,10 @@ int eecmg_restore(const void* g_delta, int H, int W, const double* psf, int psf_
 
 /* As eecmg_restore with device-resident g_delta_dev / u_out_dev (dense H x W)
  * enqueued on hip_stream.  Statistics (params->stats) are complete on return.
+ * When a row of H x W is a multiple of 256 bytes and the two buffers are
+ * 256-byte aligned and disjoint, the finest level reads g_delta_dev and
+ * updates u_out_dev in place (no copies); u_out_dev may be the same buffer as
+ * g_delta_dev.  On an error status the contents of u_out_dev are unspecified.
  * Additional error: EINVAL if a pointer is not device memory. */
 int eecmg_restore_dev(const void* g_delta_dev, int H, int W, const double* psf, int psf_radius, int n_levels,
                       const int* iters_per_level, double k, const eecmg_params* params, void* u_out_dev,

@@ -68,7 +68,7 @@ struct JobDesc {
   int32_t stop_rule, smoother;
   int32_t cascade, pm_steps;
   int32_t coarse_levels;  // level 0 only: leading levels solved by the coarse kernel
-  int32_t pad0;
+  int32_t zero_u;         // bit l: level l's smoother starts from zero (no transfer into it)
   double cdelta, eps2;
   SolverState* st;
   LevelRecord* rec;  // kMaxLevels records of this job

@@ -942,8 +942,10 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse(LaunchList ll, const 
 // Restriction (eq. 12-13) and output copy
 // ---------------------------------------------------------------------------
 // One pass over the dense finest-level input writes every level's
-// right-hand side g_l(i, j) = g(2^(L-l) i, 2^(L-l) j) and initialises the
-// solution pyramid (zero, or the given initial guess on the finest level).
+// right-hand side g_l(i, j) = g(2^(L-l) i, 2^(L-l) j) and sets the starting
+// solution of every level that receives no transfer (zero, or the given
+// initial guess on the finest level); the other levels are written whole by
+// their transfer before their smoother reads them.
 template <typename T>
 __global__ __launch_bounds__(256) void k_restrict(LaunchList ll, const JobDesc* __restrict__ descs) {
   const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
@@ -955,16 +957,29 @@ __global__ __launch_bounds__(256) void k_restrict(LaunchList ll, const JobDesc* 
   if (x >= W) return;
   const T* gin = (const T*)d.g_in;
   const T* uin = (const T*)d.u_in;
+  const int zero = d.zero_u;
+  // the finest level reads the dense input in place when its rows already
+  // have the level's pitch; otherwise it gets a pitched copy
+  const bool copy_fine = d.g_lv[NL - 1] != d.g_in;
+  const bool init_fine = (zero >> (NL - 1)) & 1;
+  // with neither, only the even rows feed coarser levels
+  const int skip_odd = (copy_fine || init_fine) ? 0 : 1;
+  if (skip_odd && NL == 1) return;
   for (int k = 0; k < kXH / 4; ++k) {
     const int y = ty * kXH + (threadIdx.x >> 6) * (kXH / 4) + k;
     if (y >= H) break;
-    const T v = gin[(size_t)y * W + x];
-    for (int l = NL - 1; l >= 0; --l) {
+    if (y & skip_odd) continue;
+    const size_t fo = (size_t)y * W + x;
+    const T v = gin[fo];
+    const size_t of = (size_t)y * d.fine_pitch + x;
+    if (copy_fine) ((T*)d.g_lv[NL - 1])[of] = v;
+    if (init_fine) ((T*)d.u_lv[NL - 1])[of] = uin ? uin[fo] : T(0);
+    for (int l = NL - 2; l >= 0; --l) {
       const int sh = NL - 1 - l, m = (1 << sh) - 1;
       if ((y & m) || (x & m)) break;
       const size_t o = (size_t)(y >> sh) * d.lp[l] + (x >> sh);
       ((T*)d.g_lv[l])[o] = v;
-      ((T*)d.u_lv[l])[o] = (l == NL - 1 && uin) ? uin[(size_t)y * W + x] : T(0);
+      if ((zero >> l) & 1) ((T*)d.u_lv[l])[o] = T(0);
     }
   }
 }

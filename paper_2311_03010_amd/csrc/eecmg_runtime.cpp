@@ -507,6 +507,8 @@ struct Job {
   size_t host_bytes = 0;
   std::atomic<bool> cancelled{false};
   double t_submit = 0.0, t_done = 0.0;
+  // the finest level reads g_in_dev / writes u_out_dev in place (see alias_io)
+  bool alias_in = false, alias_out = false;
   // valid while the job is on a level (phases kStartLevel and kIter)
   int cur_level() const { return oi < (int)plan.order.size() ? plan.order[oi] : -1; }
 };
@@ -607,6 +609,7 @@ class Engine {
     chk(hipMemcpyAsync(mem, tb, P.taps_bytes, hipMemcpyHostToDevice, stream_));
     if (P.own_gin) j->g_in_dev = mem + P.off_gin;
     if (P.own_uout) j->u_out_dev = mem + P.off_uout;
+    alias_io(j);
     JobDesc* hd = h_desc_ + (size_t)slot * kMaxLevels;
     for (int l = 0; l < P.L; ++l) fill_desc(j, l, hd[l]);
     chk(hipMemcpyAsync(d_desc_ + (size_t)slot * kMaxLevels, hd, sizeof(JobDesc) * P.L, hipMemcpyHostToDevice, stream_));
@@ -731,7 +734,7 @@ class Engine {
     }
     for (Job* j : out_l) {
       std::vector<Job*> one{j};
-      launch_group(kOutCopy, one, j->plan.L - 1, j->plan.f64, 0, -1, -1);
+      if (!j->alias_out) launch_group(kOutCopy, one, j->plan.L - 1, j->plan.f64, 0, -1, -1);
       chk(hipMemcpyAsync(h_rec_ + (size_t)j->slot * kMaxLevels, d_rec_ + (size_t)j->slot * kMaxLevels,
                      sizeof(LevelRecord) * kMaxLevels, hipMemcpyDeviceToHost, stream_));
       if (j->host_out)
@@ -815,13 +818,33 @@ class Engine {
     return j->plan.prm.cascade == EECMG_CASCADE_EECMG ? l >= 2 : l >= 1;
   }
 
+  // The finest level's right-hand side and solution live in the caller's
+  // dense input and output when those already have the level's row pitch and
+  // alignment and do not overlap (saves the pitched copy in and out).  An
+  // initial guess keeps the separate solution buffer.
+  static void alias_io(Job* j) {
+    const Plan& P = j->plan;
+    const size_t n = (size_t)P.H * P.W * P.esz;
+    const char* g = (const char*)j->g_in_dev;
+    const char* u = (const char*)j->u_out_dev;
+    const bool dense = P.lv[P.L - 1].pitch == P.W;
+    const bool disjoint = g && u && (g + n <= u || u + n <= g);
+    j->alias_in = dense && disjoint && ((uintptr_t)g & 255) == 0;
+    j->alias_out = dense && disjoint && ((uintptr_t)u & 255) == 0 && !j->u_init_dev;
+  }
+
   void fill_desc(const Job* j, int l, JobDesc& d) {
     const Plan& P = j->plan;
     const LevelPlan& lp = P.lv[l];
     char* m = j->mem;
+    const int Lf = P.L - 1;
+    auto g_at = [&](int k) -> void* {
+      return k == Lf && j->alias_in ? const_cast<void*>(j->g_in_dev) : (void*)(m + P.off_g[k]);
+    };
+    auto u_at = [&](int k) -> void* { return k == Lf && j->alias_out ? j->u_out_dev : (void*)(m + P.off_u[k]); };
     std::memset(&d, 0, sizeof(d));
-    d.g = m + P.off_g[l];
-    d.u = m + P.off_u[l];
+    d.g = g_at(l);
+    d.u = u_at(l);
     d.r[0] = m + P.off_work[0];
     d.r[1] = m + P.off_work[1];
     d.p[0] = m + P.off_work[2];
@@ -844,6 +867,8 @@ class Engine {
     d.cascade = P.prm.cascade;
     d.pm_steps = P.prm.pm_steps;
     d.coarse_levels = l == 0 ? P.coarse : 0;
+    for (int k = 0; k < P.L; ++k)
+      if (!needs_transfer(j, k)) d.zero_u |= 1 << k;
     d.cdelta = P.prm.c * P.prm.delta;
     d.eps2 = P.eps2;
     d.st = d_state_ + j->slot;
@@ -853,13 +878,13 @@ class Engine {
     d.mirror = d_mirror_ + j->slot;
     d.tag = level_tag(j, l);
     if (l >= 1) {
-      d.uB = m + P.off_u[l - 1];
+      d.uB = u_at(l - 1);
       d.hB = P.lv[l - 1].h;
       d.wB = P.lv[l - 1].w;
       d.pB = P.lv[l - 1].pitch;
     }
     if (l >= 2) {
-      d.uA = m + P.off_u[l - 2];
+      d.uA = u_at(l - 2);
       d.hA = P.lv[l - 2].h;
       d.wA = P.lv[l - 2].w;
       d.pA = P.lv[l - 2].pitch;
@@ -878,8 +903,8 @@ class Engine {
     d.L = P.L;
     d.fine_pitch = P.lv[P.L - 1].pitch;
     for (int k = 0; k < P.L; ++k) {
-      d.g_lv[k] = m + P.off_g[k];
-      d.u_lv[k] = m + P.off_u[k];
+      d.g_lv[k] = g_at(k);
+      d.u_lv[k] = u_at(k);
       d.lh[k] = P.lv[k].h;
       d.lw[k] = P.lv[k].w;
       d.lp[k] = P.lv[k].pitch;

@@ -430,9 +430,12 @@ class Context:
                                   ctypes.byref(p), ctypes.byref(rid)))
         return Request(rid.value, g.shape, dt)
 
-    def poll(self, req: Request):
-        """None while pending, else (u, stats)."""
-        u = np.empty(req.shape, dtype=req.dtype)
+    def poll(self, req: Request, out=None):
+        """None while pending, else (u, stats).  out: optional preallocated
+        array of the request's shape and dtype that receives u."""
+        u = np.empty(req.shape, dtype=req.dtype) if out is None else out
+        if u.shape != tuple(req.shape) or u.dtype != req.dtype or not u.flags.c_contiguous:
+            raise ValueError("out must be a contiguous array of the request's shape and dtype")
         st = Stats()
         rc = lib().eecmg_poll(self._h, req.id, u.ctypes.data, ctypes.byref(st))
         if rc == PENDING:

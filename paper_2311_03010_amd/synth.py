@@ -205,6 +205,13 @@ def batch_problems(n_images: int = 256, lo: int = 128, hi: int = 2048, wid: int 
     return out
 
 
+def served_pool(n_images: int = 64, lo: int = 64, hi: int = 4096, precision: str = "f32"):
+    """Distinct request images of the served workload: sides log-uniform in
+    [lo, hi], the PSF mix of the uneven batch.  Requests draw from this pool
+    in turn (generating every request's image would dominate the run)."""
+    return batch_problems(n_images, lo, hi, wid=5, precision=precision)
+
+
 def poisson_arrivals(n: int, qps: float, seed: int = SEED_BASE + 5) -> np.ndarray:
     """Arrival times (seconds from 0) of a Poisson process at rate qps."""
     rng = np.random.Generator(np.random.PCG64(seed))

@@ -169,6 +169,33 @@ def test_host_restore_equals_dev(torch_cuda):
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_in_place_finest_level_paths_agree(torch_cuda, prec):
+    """Dense aligned buffers are used in place by the finest level; a
+    misaligned view of the same data takes the pitched-copy path, and an
+    output that is the input buffer itself must still work.  All three give
+    the same result bit for bit."""
+    t = torch_cuda
+    p = synth.workload(3, H=128, W=128, n_levels=4, n_shapes=20, n_textures=2, precision=prec)
+    dt = t.float64 if prec == "f64" else t.float32
+    g = t.from_numpy(p.g_delta.astype(_dt(prec))).to("cuda:0")
+    u_a, st_a = eecmg.restore_dev(g, p.psf, 4, precision=prec, delta=p.delta)
+    # 64 bytes into a larger allocation: not 256-byte aligned
+    off = 64 // g.element_size()
+    big_in = t.zeros(g.numel() + off, dtype=dt, device="cuda:0")
+    big_out = t.zeros(g.numel() + off, dtype=dt, device="cuda:0")
+    g_mis = big_in[off:].view(g.shape)
+    g_mis.copy_(g)
+    u_mis = big_out[off:].view(g.shape)
+    _, st_b = eecmg.restore_dev(g_mis, p.psf, 4, out=u_mis, precision=prec, delta=p.delta)
+    g_same = g.clone()
+    _, st_c = eecmg.restore_dev(g_same, p.psf, 4, out=g_same, precision=prec, delta=p.delta)
+    t.cuda.synchronize()
+    np.testing.assert_array_equal(u_a.cpu().numpy(), u_mis.cpu().numpy())
+    np.testing.assert_array_equal(u_a.cpu().numpy(), g_same.cpu().numpy())
+    assert st_a == st_b == st_c
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_batch_equals_alone_bitwise(torch_cuda, prec):
     t = torch_cuda
     probs = [synth.workload(1, H=64, W=64), synth.workload(1, H=97, W=50),
