@@ -155,40 +155,43 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NV], double* __restr
 // ---------------------------------------------------------------------------
 
 // General PSF: all (2R+1)^2 taps, R known at run time (R <= RMAX).  Four waves
-// share a 64 x 32 tile, kV = 8 output rows each; for each column offset b a
-// lane loads its column segment once into registers (shifted so that every
-// register index is a compile-time constant) and applies every row offset.
-template <typename T, int RMAX>
+// share a 64 x TH_ tile (TH_ = 32, or short tiles on small levels), KV = TH_/4
+// output rows each; for each column offset b a lane loads its column segment
+// once into registers (shifted so that every register index is a
+// compile-time constant) and applies every row offset.
+template <typename T, int RMAX, int TH_ = kTH>
 struct ConvGeneral {
-  static constexpr int NT = 256, TW = kTW, TH = kTH, LW = kTW + 2 * RMAX, LH = kTH + 2 * RMAX, RC = RMAX;
+  static_assert(TH_ % 4 == 0, "four waves share the tile rows");
+  static constexpr int KV = TH_ / 4;
+  static constexpr int NT = 256, TW = kTW, TH = TH_, LW = kTW + 2 * RMAX, LH = TH_ + 2 * RMAX, RC = RMAX;
   static constexpr bool kRuntimeR = true, kStream = false;
   static constexpr int kWavesPerEU = 1;
   template <typename Emit>
   __device__ static __forceinline__ void conv(const T* __restrict__ tile, const T* __restrict__ taps, int R, int wave,
                                               int lane, Emit emit) {
-    T acc[kV];
+    T acc[KV];
 #pragma unroll
-    for (int v = 0; v < kV; ++v) acc[v] = T(0);
+    for (int v = 0; v < KV; ++v) acc[v] = T(0);
     const int n = 2 * R + 1;
     for (int b = -R; b <= R; ++b) {
-      T xc[kV + 2 * RMAX];
+      T xc[KV + 2 * RMAX];
       const int col = lane + R - b;
 #pragma unroll
-      for (int t = 0; t < kV + 2 * RMAX; ++t) {
-        const int lr = wave * kV + t - (RMAX - R);
-        xc[t] = (t >= RMAX - R && t < RMAX + R + kV) ? tile[lr * LW + col] : T(0);
+      for (int t = 0; t < KV + 2 * RMAX; ++t) {
+        const int lr = wave * KV + t - (RMAX - R);
+        xc[t] = (t >= RMAX - R && t < RMAX + R + KV) ? tile[lr * LW + col] : T(0);
       }
 #pragma unroll
       for (int a = -RMAX; a <= RMAX; ++a) {
         if (a >= -R && a <= R) {
           const T wt = taps[(a + R) * n + (b + R)];
 #pragma unroll
-          for (int v = 0; v < kV; ++v) acc[v] = fma(wt, xc[v + RMAX - a], acc[v]);
+          for (int v = 0; v < KV; ++v) acc[v] = fma(wt, xc[v + RMAX - a], acc[v]);
         }
       }
     }
 #pragma unroll
-    for (int v = 0; v < kV; ++v) emit(wave * kV + v, acc[v]);
+    for (int v = 0; v < KV; ++v) emit(wave * KV + v, acc[v]);
   }
 };
 

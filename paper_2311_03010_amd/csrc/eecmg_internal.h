@@ -139,7 +139,19 @@ enum XBuf : int32_t { kBufU = 0, kBufT1 = 1, kBufT2 = 2, kBufUB = 3 };
 
 // Blur-operator implementation families.  A variant id is kind * 100 + R
 // (for kConvGeneral, R is the radius class 3, 6 or 12).
-enum ConvKind : int32_t { kConvGeneral = 0, kConvSep = 1, kConvSymSquare = 2, kConvSymDisk = 3, kConvBoxDisk = 4 };
+enum ConvKind : int32_t {
+  kConvGeneral = 0,
+  kConvSep = 1,
+  kConvSymSquare = 2,
+  kConvSymDisk = 3,
+  kConvBoxDisk = 4,
+  kConvGenShort = 5  // general policy on short tiles (small levels: more blocks per launch)
+};
+// Tile height of the short general tiles.
+#ifndef EECMG_SHORT_TH
+#define EECMG_SHORT_TH 16
+#endif
+constexpr int kTHShort = EECMG_SHORT_TH;
 
 // Rows per unrolled group of the streaming (sliding-column) families: a
 // multiple of 2R + 1 (the pending-output ring) of at least 4 rows (the
@@ -153,7 +165,7 @@ __host__ __device__ constexpr int strip_th(int R) {
   return strip_group(R) * ((kTH + 2 * R + strip_group(R) - 1) / strip_group(R)) - 2 * R;
 }
 __host__ __device__ constexpr int tile_h_for_variant(int variant) {
-  return variant / 100 == kConvGeneral ? kTH : strip_th(variant % 100);
+  return variant / 100 == kConvGeneral ? kTH : variant / 100 == kConvGenShort ? kTHShort : strip_th(variant % 100);
 }
 
 // Host-side launchers (defined in eecmg_kernels.hip).

@@ -1019,6 +1019,7 @@ hipError_t sm_f32_sym(Stage st, bool disk, int R, const LaunchList& ll, const Jo
 hipError_t sm_f64_sep(Stage st, int R, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
 hipError_t sm_f64_sym(Stage st, bool disk, int R, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
 hipError_t sm_gen(Stage st, bool f64, int rclass, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
+hipError_t sm_gen_short(Stage st, bool f64, int rclass, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
 hipError_t opc_f32_sep(const void* x, void* y, int H, int W, const void* taps, int R, hipStream_t s);
 hipError_t opc_f32_sym(bool disk, const void* x, void* y, int H, int W, const void* taps, int R, hipStream_t s);
 hipError_t opc_f64_sep(const void* x, void* y, int H, int W, const void* taps, int R, hipStream_t s);
@@ -1059,6 +1060,7 @@ static hipError_t launch_smoother(Stage st, bool f64, int variant, const LaunchL
   const int kind = variant / 100, R = variant % 100;
   switch (kind) {
     case kConvGeneral: return sm_gen(st, f64, R, ll, descs, s);
+    case kConvGenShort: return sm_gen_short(st, f64, R, ll, descs, s);
     case kConvSep: return f64 ? sm_f64_sep(st, R, ll, descs, s) : sm_f32_sep(st, R, ll, descs, s);
     case kConvSymSquare:
       return f64 ? sm_f64_sym(st, false, R, ll, descs, s) : sm_f32_sym(st, false, R, ll, descs, s);

@@ -68,9 +68,10 @@ static int sym_span_h(int R, bool disk, int a) {
 //   symmetric in both axes, disk support -> row-filter kernel on the quadrant
 //   symmetric in both axes               -> same with square support (R <= 6)
 //   otherwise                            -> general (all taps)
-// Small levels with small radii always take the general kernels: their
-// whole-tile loads (four waves per tile, all rows at once) have far less
-// latency per launch than one wave streaming down each strip.
+// Small levels with small radii always take the general kernels on short
+// tiles: their whole-tile loads (four waves per tile, all rows at once) have
+// far less latency per launch than one wave streaming down each strip, and
+// short tiles give a small level enough blocks to fill the chip.
 constexpr long kSmallLevelPixels = 1024L * 1024L;
 // Levels up to this many pixels (the leading ones of a cascade) are solved
 // by one block per job in a single launch.
@@ -80,7 +81,7 @@ static void choose_variant(LevelPlan& lp, bool f64, bool by_size) {
   const std::vector<double>& P = lp.psf;
   auto at = [&](int a, int b) { return P[(a + R) * n + (b + R)]; };
   if (by_size && (long)lp.h * lp.w <= kSmallLevelPixels && R <= 3) {
-    lp.variant = kConvGeneral * 100 + rmax_class_for(R);
+    lp.variant = kConvGenShort * 100 + rmax_class_for(R);
     lp.taps = P;
     lp.taps_t.assign(P.rbegin(), P.rend());
     return;
