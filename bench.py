@@ -82,6 +82,24 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 5}))
 
 
+def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
+    """Measured HBM bandwidth of a plain device copy (bytes read + written per
+    second), the practical ceiling the roofline fraction is also quoted against."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -328,8 +346,10 @@ def main():
     roofline = None
     if rb:
         ach = rb["gbs"]
+        cbw = copy_bandwidth(torch)
         roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                    "copy_gbs": round(cbw, 1), "frac_vs_copy": round(ach / cbw, 4),
                     "kernel": "k_cg_b<float, ConvBox<float, 6>> (finest level, 4096^2)",
                     "avg_launch_us": round(rb["avg_us"], 2), "alg_bytes_per_launch": int(20 * H * W)}
     extra = {"kernels": kern, "iters_per_level": stats["iters"], "stop_reason": stats["reason"]}

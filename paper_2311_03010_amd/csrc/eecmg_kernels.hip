@@ -190,6 +190,52 @@ __device__ __forceinline__ void linear_point(const XArgs& x, int I, int J) {
   ((T*)x.dst)[(size_t)I * x.pd + J] = to_t<T>(linear_at<T>(x, I, J));
 }
 
+// Arithmetic of S and D in a compute type C: FP64 with IEEE division and
+// exp(), or FP32 (the FP32 storage mode) with the hardware reciprocal,
+// reciprocal square root and base-2 exponential.
+template <typename C>
+struct Ar;
+template <>
+struct Ar<double> {
+  __device__ static double div(double a, double b) { return a / b; }
+  __device__ static double rsqrt(double x) { return 1.0 / sqrt(x); }
+  // eigenvalues below this fraction of the largest are rounding noise
+  static constexpr double kEig = 1e-12;
+};
+template <>
+struct Ar<float> {
+  __device__ static float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+  __device__ static float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+  static constexpr float kEig = 1e-5f;
+};
+
+// Weight w = exp(-(v/h)^2) of a neighbour at difference v, exactly 0 beyond
+// (v/h)^2 > 30 or outside the image.
+template <typename C>
+struct SWeight;
+template <>
+struct SWeight<double> {
+  double inv_h;
+  __device__ explicit SWeight(double h) : inv_h(1.0 / h) {}
+  __device__ double operator()(double v, bool in) const {
+    const double z = v * inv_h;
+    const double e = z * z;
+    const double x = exp(-e);
+    return (in && !(e > 30.0)) ? x : 0.0;
+  }
+};
+template <>
+struct SWeight<float> {
+  float nl, cut;  // -log2(e) / h^2 and 30 h^2: w = 2^(v^2 nl)
+  __device__ explicit SWeight(double h)
+      : nl((float)(-1.4426950408889634 / (h * h))), cut((float)(30.0 * h * h)) {}
+  __device__ float operator()(float v, bool in) const {
+    const float d2 = v * v;
+    const float x = __builtin_amdgcn_exp2f(d2 * nl);
+    return (in && !(d2 > cut)) ? x : 0.0f;
+  }
+};
+
 // Local smoothing S (Section 3.3, eq. 18-19): weighted LS fit of
 // a0 + a1 s + a2 t on the 3x3 window with w = exp(-((u_c - u_n)/h)^2)
 // (exactly 0 beyond (./h)^2 > 30, out-of-image neighbours dropped), output
@@ -200,139 +246,128 @@ __device__ __forceinline__ void linear_point(const XArgs& x, int I, int J) {
 // S a = c for the slopes and a0 = u_c + vb - (sb, tb) . a.  A well
 // conditioned S (det > 1e-3 tr^2, so both eigenvalues exceed 1e-3 of the
 // larger) is solved by its adjugate; otherwise through its eigen-decomposition
-// (one Jacobi rotation, no trigonometric calls) with eigenvalues below 1e-12
-// of the largest dropped, so near-collinear weight patterns stay accurate.
-// The window moments are formed from row and column sums (the offsets are
-// -1, 0, 1).  The FP32 path evaluates the weights with the hardware
-// exponential.
-template <bool F32>
-__device__ __forceinline__ double smooth_core(const double (&nb)[9], bool up, bool down, bool left, bool right,
-                                              double inv_h) {
-  const double uc = nb[4];
-  double w[9], wv[9];
+// (one Jacobi rotation, no trigonometric calls) with eigenvalues below the
+// compute type's noise level (Ar<C>::kEig of the largest) dropped, so
+// near-collinear weight patterns stay accurate.  The window moments are
+// formed from row and column sums (the offsets are -1, 0, 1).
+template <typename C>
+__device__ __forceinline__ C smooth_core(const C (&nb)[9], bool up, bool down, bool left, bool right,
+                                         const SWeight<C>& W) {
+  const C uc = nb[4];
+  C w[9], wv[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
     if (k == 4) {
-      w[k] = wv[k] = 0.0;
+      w[k] = wv[k] = C(0);
       continue;
     }
     const int si = k / 3 - 1, ti = k % 3 - 1;
     const bool in = (si < 0 ? up : (si > 0 ? down : true)) && (ti < 0 ? left : (ti > 0 ? right : true));
-    const double v = nb[k] - uc;
-    const double z = v * inv_h;
-    const double e = z * z;
-    const bool keep = in && !(e > 30.0);
-    double wt;
-    if (F32) {
-      const float x = __expf(-(float)e);
-      wt = (double)(keep ? x : 0.0f);
-    } else {
-      const double x = exp(-e);
-      wt = keep ? x : 0.0;
-    }
+    const C v = nb[k] - uc;
+    const C wt = W(v, in);
     w[k] = wt;
     wv[k] = wt * v;
   }
-  const double rA = (w[0] + w[1]) + w[2], rB = (w[6] + w[7]) + w[8];
-  const double cL = (w[0] + w[3]) + w[6], cR = (w[2] + w[5]) + w[8];
-  const double m00 = ((1.0 + rA) + rB) + (w[3] + w[5]);
-  const double m01 = rB - rA, m11 = rA + rB, m02 = cR - cL, m22 = cL + cR;
-  const double m12 = (w[8] + w[0]) - (w[6] + w[2]);
-  const double RA = (wv[0] + wv[1]) + wv[2], RB = (wv[6] + wv[7]) + wv[8];
-  const double CL = (wv[0] + wv[3]) + wv[6], CR = (wv[2] + wv[5]) + wv[8];
-  const double b0 = (RA + RB) + (wv[3] + wv[5]), b1 = RB - RA, b2 = CR - CL;
+  const C rA = (w[0] + w[1]) + w[2], rB = (w[6] + w[7]) + w[8];
+  const C cL = (w[0] + w[3]) + w[6], cR = (w[2] + w[5]) + w[8];
+  const C m00 = ((C(1) + rA) + rB) + (w[3] + w[5]);
+  const C m01 = rB - rA, m11 = rA + rB, m02 = cR - cL, m22 = cL + cR;
+  const C m12 = (w[8] + w[0]) - (w[6] + w[2]);
+  const C RA = (wv[0] + wv[1]) + wv[2], RB = (wv[6] + wv[7]) + wv[8];
+  const C CL = (wv[0] + wv[3]) + wv[6], CR = (wv[2] + wv[5]) + wv[8];
+  const C b0 = (RA + RB) + (wv[3] + wv[5]), b1 = RB - RA, b2 = CR - CL;
 
-  const double inv0 = 1.0 / m00;
-  const double sb = m01 * inv0, tb = m02 * inv0, vb = b0 * inv0;
-  const double S11 = fma(-m01, sb, m11), S12 = fma(-m01, tb, m12), S22 = fma(-m02, tb, m22);
-  const double c1 = fma(-m01, vb, b1), c2 = fma(-m02, vb, b2);
-  const double det = fma(S11, S22, -S12 * S12), tr = S11 + S22;
-  double corr;
-  if (det > 1e-3 * tr * tr) {
-    corr = (sb * fma(S22, c1, -S12 * c2) + tb * fma(S11, c2, -S12 * c1)) / det;
+  const C inv0 = Ar<C>::div(C(1), m00);
+  const C sb = m01 * inv0, tb = m02 * inv0, vb = b0 * inv0;
+  const C S11 = fma(-m01, sb, m11), S12 = fma(-m01, tb, m12), S22 = fma(-m02, tb, m22);
+  const C c1 = fma(-m01, vb, b1), c2 = fma(-m02, vb, b2);
+  const C det = fma(S11, S22, -S12 * S12), tr = S11 + S22;
+  C corr;
+  if (det > C(1e-3) * tr * tr) {
+    corr = Ar<C>::div(sb * fma(S22, c1, -S12 * c2) + tb * fma(S11, c2, -S12 * c1), det);
   } else {
     // symmetric 2x2 Schur decomposition by one Jacobi rotation (t = tan of
     // the rotation angle from tau = (S22 - S11) / (2 S12), the smaller root)
-    double cs = 1.0, sn = 0.0, l1 = S11, l2 = S22;
-    if (S12 != 0.0) {
-      const double tau = (S22 - S11) / (2.0 * S12);
-      const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-      cs = 1.0 / sqrt(1.0 + t * t);
+    C cs = C(1), sn = C(0), l1 = S11, l2 = S22;
+    if (S12 != C(0)) {
+      const C tau = Ar<C>::div(S22 - S11, C(2) * S12);
+      const C t = Ar<C>::div(tau >= C(0) ? C(1) : C(-1), fabs(tau) + sqrt(C(1) + tau * tau));
+      cs = Ar<C>::rsqrt(C(1) + t * t);
       sn = t * cs;
       l1 = S11 - t * S12;
       l2 = S22 + t * S12;
     }
     // eigenvectors (cs, -sn) for l1 and (sn, cs) for l2
-    const double lmax = fmax(fabs(l1), fabs(l2));
-    corr = 0.0;
-    if (l1 > 1e-12 * lmax && l1 > 0.0) corr += (sb * cs - tb * sn) * (c1 * cs - c2 * sn) / l1;
-    if (l2 > 1e-12 * lmax && l2 > 0.0) corr += (sb * sn + tb * cs) * (c1 * sn + c2 * cs) / l2;
+    const C lmax = fmax(fabs(l1), fabs(l2));
+    corr = C(0);
+    if (l1 > Ar<C>::kEig * lmax && l1 > C(0)) corr += Ar<C>::div((sb * cs - tb * sn) * (c1 * cs - c2 * sn), l1);
+    if (l2 > Ar<C>::kEig * lmax && l2 > C(0)) corr += Ar<C>::div((sb * sn + tb * cs) * (c1 * sn + c2 * cs), l2);
   }
   return uc + (vb - corr);
 }
 
 // S at (i, j) of an H x W image read through U(ii, jj) (in-image positions
 // only: outside neighbours are read at the clamped position and dropped).
-template <bool F32, typename F>
-__device__ __forceinline__ double smooth_value(int i, int j, int H, int W, double inv_h, F U) {
+template <typename C, typename F>
+__device__ __forceinline__ C smooth_value(int i, int j, int H, int W, const SWeight<C>& Wt, F U) {
   const int im = max(i - 1, 0), ip = min(i + 1, H - 1), jm = max(j - 1, 0), jp = min(j + 1, W - 1);
-  const double nb[9] = {U(im, jm), U(im, j), U(im, jp), U(i, jm), U(i, j), U(i, jp), U(ip, jm), U(ip, j), U(ip, jp)};
-  return smooth_core<F32>(nb, i > 0, i + 1 < H, j > 0, j + 1 < W, inv_h);
+  const C nb[9] = {U(im, jm), U(im, j), U(im, jp), U(i, jm), U(i, j), U(i, jp), U(ip, jm), U(ip, j), U(ip, jp)};
+  return smooth_core<C>(nb, i > 0, i + 1 < H, j > 0, j + 1 < W, Wt);
 }
 
+// S and D compute in the storage type: FP64 in FP64 mode, FP32 in FP32 mode.
 template <typename T>
-__device__ __forceinline__ double smooth_at(const XArgs& x, int i, int j) {
+__device__ __forceinline__ T smooth_at(const XArgs& x, int i, int j) {
   const T* u = (const T*)x.s0;
   const int P = x.p0;
-  return smooth_value<sizeof(T) == 4>(i, j, x.h0, x.w0, 1.0 / x.a0,
-                                      [&](int ii, int jj) { return (double)u[(size_t)ii * P + jj]; });
+  return smooth_value<T>(i, j, x.h0, x.w0, SWeight<T>(x.a0), [&](int ii, int jj) { return u[(size_t)ii * P + jj]; });
 }
 template <typename T>
 __device__ __forceinline__ void smooth_point(const XArgs& x, int i, int j) {
-  ((T*)x.dst)[(size_t)i * x.pd + j] = to_t<T>(smooth_at<T>(x, i, j));
+  ((T*)x.dst)[(size_t)i * x.pd + j] = smooth_at<T>(x, i, j);
 }
 
 // One explicit Perona-Malik step (Section 4, eq. 21, 23-25):
 // out = u + tau sum_{in-image nb} (c_nb + c)/2 (u_nb - u), c = 1/(1+|grad u|^2/k^2)
 // with |grad u| from central differences on a replicated border.
-template <typename F>
-__device__ __forceinline__ double pm_c(int i, int j, int H, int W, double ik2, F U) {
+template <typename C, typename F>
+__device__ __forceinline__ C pm_c(int i, int j, int H, int W, C ik2, F U) {
   const int ip = i + 1 < H ? i + 1 : H - 1, im = i > 0 ? i - 1 : 0;
   const int jp = j + 1 < W ? j + 1 : W - 1, jm = j > 0 ? j - 1 : 0;
-  const double ux = 0.5 * (U(ip, j) - U(im, j));
-  const double uy = 0.5 * (U(i, jp) - U(i, jm));
-  return 1.0 / fma(fma(ux, ux, uy * uy), ik2, 1.0);
+  const C ux = C(0.5) * (U(ip, j) - U(im, j));
+  const C uy = C(0.5) * (U(i, jp) - U(i, jm));
+  return Ar<C>::div(C(1), fma(fma(ux, ux, uy * uy), ik2, C(1)));
 }
 
 // C(i, j) supplies the diffusivity (pm_c) at in-image pixels.
 // Out-of-image neighbours contribute nothing: they are read at the clamped
 // (in-image) position and dropped through a select.
-template <typename F, typename G>
-__device__ __forceinline__ double pm_value(int i, int j, int H, int W, double tau, F U, G C) {
-  const double uc = U(i, j);
-  const double cc = C(i, j);
+template <typename C, typename F, typename G>
+__device__ __forceinline__ C pm_value(int i, int j, int H, int W, C tau, F U, G Cf) {
+  const C uc = U(i, j);
+  const C cc = Cf(i, j);
   const int ip = min(i + 1, H - 1), im = max(i - 1, 0), jp = min(j + 1, W - 1), jm = max(j - 1, 0);
-  const double cn = C(ip, j), cs = C(im, j), ce = C(i, jp), cw = C(i, jm);
-  const double un = U(ip, j), us = U(im, j), ue = U(i, jp), uw = U(i, jm);
-  double acc = 0.0;
-  acc = (i + 1 < H) ? fma(0.5 * (cn + cc), un - uc, acc) : acc;
-  acc = (i > 0) ? fma(0.5 * (cs + cc), us - uc, acc) : acc;
-  acc = (j + 1 < W) ? fma(0.5 * (ce + cc), ue - uc, acc) : acc;
-  acc = (j > 0) ? fma(0.5 * (cw + cc), uw - uc, acc) : acc;
+  const C cn = Cf(ip, j), cs = Cf(im, j), ce = Cf(i, jp), cw = Cf(i, jm);
+  const C un = U(ip, j), us = U(im, j), ue = U(i, jp), uw = U(i, jm);
+  C acc = C(0);
+  acc = (i + 1 < H) ? fma(C(0.5) * (cn + cc), un - uc, acc) : acc;
+  acc = (i > 0) ? fma(C(0.5) * (cs + cc), us - uc, acc) : acc;
+  acc = (j + 1 < W) ? fma(C(0.5) * (ce + cc), ue - uc, acc) : acc;
+  acc = (j > 0) ? fma(C(0.5) * (cw + cc), uw - uc, acc) : acc;
   return fma(tau, acc, uc);
 }
 
 template <typename T>
-__device__ __forceinline__ double pm_at(const XArgs& x, int i, int j) {
+__device__ __forceinline__ T pm_at(const XArgs& x, int i, int j) {
   const T* u = (const T*)x.s0;
   const int P = x.p0, H = x.h0, W = x.w0;
-  const double ik2 = 1.0 / (x.a0 * x.a0);
-  auto U = [&](int ii, int jj) { return (double)u[(size_t)ii * P + jj]; };
-  return pm_value(i, j, H, W, x.a1, U, [&](int ii, int jj) { return pm_c(ii, jj, H, W, ik2, U); });
+  const T ik2 = (T)(1.0 / (x.a0 * x.a0));
+  auto U = [&](int ii, int jj) { return u[(size_t)ii * P + jj]; };
+  return pm_value<T>(i, j, H, W, (T)x.a1, U, [&](int ii, int jj) { return pm_c<T>(ii, jj, H, W, ik2, U); });
 }
 template <typename T>
 __device__ __forceinline__ void pm_point(const XArgs& x, int i, int j) {
-  ((T*)x.dst)[(size_t)i * x.pd + j] = to_t<T>(pm_at<T>(x, i, j));
+  ((T*)x.dst)[(size_t)i * x.pd + j] = pm_at<T>(x, i, j);
 }
 
 // Pixel loop of one 64 x 16 tile of the destination grid.
@@ -497,43 +532,42 @@ __device__ __forceinline__ void fused_tile(const FArgs& a, int t) {
   }
   __syncthreads();
 
-  const double inv_h = 1.0 / a.smooth_h;
+  const SWeight<T> Wt(a.smooth_h);
   // S at (I, J) from the P tile: the whole window lies inside the tile
   // (out-of-image entries hold the filler), so no clamping is needed.
   auto S_at = [&](int I, int J) {
     const T* c = pt + (I - pi0) * G::PW + (J - pj0);
-    const double nb[9] = {(double)c[-G::PW - 1], (double)c[-G::PW], (double)c[-G::PW + 1],
-                          (double)c[-1],         (double)c[0],      (double)c[1],
-                          (double)c[G::PW - 1],  (double)c[G::PW],  (double)c[G::PW + 1]};
-    return smooth_core<sizeof(T) == 4>(nb, I > 0, I + 1 < h, J > 0, J + 1 < w, inv_h);
+    const T nb[9] = {c[-G::PW - 1], c[-G::PW], c[-G::PW + 1], c[-1],          c[0],
+                     c[1],          c[G::PW - 1], c[G::PW],   c[G::PW + 1]};
+    return smooth_core<T>(nb, I > 0, I + 1 < h, J > 0, J + 1 < w, Wt);
   };
   T* out = (T*)a.dst;
   if constexpr (!DO_D) {
     for (int k = threadIdx.x; k < TY * kFX; k += 256) {
       const int I = I0 + k / kFX, J = J0 + k % kFX;
-      if (I < h && J < w) out[(size_t)I * a.pitch + J] = to_t<T>(S_at(I, J));
+      if (I < h && J < w) out[(size_t)I * a.pitch + J] = S_at(I, J);
     }
   } else {
     const int si0 = I0 - G::HS, sj0 = J0 - G::HS;
     for (int k = threadIdx.x; k < G::SH * G::SW; k += 256) {
       const int r = k / G::SW, c = k - r * G::SW;
       const int I = si0 + r, J = sj0 + c;
-      if (I >= 0 && I < h && J >= 0 && J < w) stl[k] = to_t<T>(S_at(I, J));
+      if (I >= 0 && I < h && J >= 0 && J < w) stl[k] = S_at(I, J);
     }
     __syncthreads();
-    const double ik2 = 1.0 / (a.pm_k * a.pm_k);
-    auto Us = [&](int ii, int jj) { return (double)stl[(ii - si0) * G::SW + (jj - sj0)]; };
-    double* ct = xs;
+    const T ik2 = (T)(1.0 / (a.pm_k * a.pm_k));
+    auto Us = [&](int ii, int jj) { return stl[(ii - si0) * G::SW + (jj - sj0)]; };
+    T* ct = reinterpret_cast<T*>(xs);  // the P panels are no longer needed
     for (int k = threadIdx.x; k < G::CH * G::CW; k += 256) {
       const int r = k / G::CW, c = k - r * G::CW;
       const int I = I0 - 1 + r, J = J0 - 1 + c;
-      if (I >= 0 && I < h && J >= 0 && J < w) ct[k] = pm_c(I, J, h, w, ik2, Us);
+      if (I >= 0 && I < h && J >= 0 && J < w) ct[k] = pm_c<T>(I, J, h, w, ik2, Us);
     }
     __syncthreads();
     auto Cc = [&](int ii, int jj) { return ct[(ii - (I0 - 1)) * G::CW + (jj - (J0 - 1))]; };
     for (int k = threadIdx.x; k < TY * kFX; k += 256) {
       const int I = I0 + k / kFX, J = J0 + k % kFX;
-      if (I < h && J < w) out[(size_t)I * a.pitch + J] = to_t<T>(pm_value(I, J, h, w, a.tau, Us, Cc));
+      if (I < h && J < w) out[(size_t)I * a.pitch + J] = pm_value<T>(I, J, h, w, (T)a.tau, Us, Cc);
     }
   }
 }
