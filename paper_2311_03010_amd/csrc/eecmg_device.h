@@ -578,26 +578,25 @@ __device__ __forceinline__ void stream_strip(const TileGeo& g, unsigned none, ty
 __device__ __forceinline__ bool finite_d(double x) { return isfinite(x); }
 
 // Fixed-order sum of selected components of the tile partials of one job,
-// returned to every thread of the NT-thread block.  Thread i sums the
-// contiguous chunk [i*ch, (i+1)*ch) of each component in index order, then
-// the chunk sums are combined by a fixed tree.
+// returned to every thread of the NT-thread block.  Thread i sums tiles
+// i, i + NT, i + 2 NT, ... in that order, eight independent (coalesced)
+// loads at a time, then the thread sums are combined by a fixed tree.
 template <int NV, int NT>
 __device__ __forceinline__ void sum_partials(const double* __restrict__ part, int ntiles, int stride,
                                              const int (&comp)[NV], double (&out)[NV]) {
-  constexpr int NWV = NT / 64;
-  const int ch = (ntiles + NT - 1) / NT;
-  const int t0 = min((int)threadIdx.x * ch, ntiles), t1 = min(t0 + ch, ntiles);
+  constexpr int NWV = NT / 64, B = 8;
   double acc[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     const double* __restrict__ c = part + (size_t)comp[i] * stride;
     double a = 0.0;
-    int t = t0;
-    for (; t + 4 <= t1; t += 4) {
-      const double v0 = c[t], v1 = c[t + 1], v2 = c[t + 2], v3 = c[t + 3];
-      a = (((a + v0) + v1) + v2) + v3;
+    for (int t = threadIdx.x; t < ntiles; t += B * NT) {
+      double v[B];
+#pragma unroll
+      for (int m = 0; m < B; ++m) v[m] = t + m * NT < ntiles ? c[t + m * NT] : 0.0;
+#pragma unroll
+      for (int m = 0; m < B; ++m) a += v[m];
     }
-    for (; t < t1; ++t) a += c[t];
     acc[i] = wave_sum(a);
   }
   if constexpr (NWV == 1) {
@@ -807,7 +806,8 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
   block_sum_store<P::NT, 1>(part, d.partials + (size_t)1 * d.pstride + L.t, d.pstride);
 }
 
-// s = H^T r, p[0] = s; partial <s,s> in slot 2.
+// s = H^T r; partial <s,s> in slot 2.  The first direction p_0 = s is formed
+// by the first pass A, which reads no previous direction.
 template <typename T, typename P>
 __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWavesPerEU))) void k_cg_init2(LaunchList ll, const JobDesc* __restrict__ descs) {
   const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
@@ -815,23 +815,20 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
   const TileGeo g = tile_geo<P>(d, L.t);
   const auto r = gpc<T>(d.r[0]);
   auto s = gp<T>(d.s);
-  auto p = gp<T>(d.p[0]);
   double part[1] = {0.0};
   auto put = [&](unsigned o, T acc) {
     s[o] = acc;
-    p[o] = acc;
     part[0] += (double)acc * (double)acc;
   };
   if constexpr (P::kStream) {
     typename P::St st;
     P::init(st, (const T*)d.taps_t);
     const unsigned n = (unsigned)(g.h * g.pitch);
-    const auto Rr = bview<T>(d.r[0], n), S = bview<T>(d.s, n), Pp = bview<T>(d.p[0], n);
+    const auto Rr = bview<T>(d.r[0], n), S = bview<T>(d.s, n);
     stream_strip<T, P>(
         g, n, st, [&](unsigned o) { return Rr.ld(o); }, [](T v) { return v; }, NoLoadF{}, NoInterior{}, NoLoadF{},
         [&](unsigned o, T acc, bool in, T, NoLoad) {
           S.st(o, acc);
-          Pp.st(o, acc);
           part[0] += in ? (double)acc * (double)acc : 0.0;
         });
   } else {
@@ -848,7 +845,8 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
 }
 
 // Pass A of iteration k: p_new = s + beta p_old (on tile + halo), q = H p_new;
-// partial <q,q> in slot 0.
+// partial <q,q> in slot 0.  Iteration 0 has beta = 0 and no previous
+// direction: p_old reads as zero (an empty buffer range), so p_0 = s.
 template <typename T, typename P>
 __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWavesPerEU))) void k_cg_a(LaunchList ll, const JobDesc* __restrict__ descs) {
   const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
@@ -858,18 +856,19 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
   const TileGeo g = tile_geo<P>(d, L.t);
   const int par = uni(st->par);
   const T beta = (T)st->beta;
+  const bool first = uni(st->k) == 0;
   const auto s = gpc<T>(d.s);
   const auto po = gpc<T>(d.p[par]);
   auto pn = gp<T>(d.p[par ^ 1]);
   auto q = gp<T>(d.q[0]);
   double part[1] = {0.0};
-  auto load = [&](unsigned o) { return Two<T>{s[o], po[o]}; };
+  auto load = [&](unsigned o) { return Two<T>{s[o], first ? T(0) : po[o]}; };
   auto comb = [&](Two<T> x) { return fma(beta, x.b, x.a); };
   if constexpr (P::kStream) {
     typename P::St ps;
     P::init(ps, (const T*)d.taps);
     const unsigned n = (unsigned)(g.h * g.pitch);
-    const auto S = bview<T>(d.s, n), Po = bview<T>(d.p[par], n), Pn = bview<T>(d.p[par ^ 1], n);
+    const auto S = bview<T>(d.s, n), Po = bview<T>(d.p[par], first ? 0u : n), Pn = bview<T>(d.p[par ^ 1], n);
     const auto Q = bview<T>(d.q[0], n);
     stream_strip<T, P>(
         g, n, ps, [&](unsigned o) { return Two<T>{S.ld(o), Po.ld(o)}; }, comb, NoLoadF{},
