@@ -327,10 +327,12 @@ def main():
     # dominant kernel: finest-level CGLS pass B (r -= alpha q, s = H^T r, u += alpha p).
     # Algorithmic HBM bytes per pixel and iteration are 32 (u, r, p, s each
     # read and written once): 12 in pass A (read s, p; write p) and 20 in
-    # pass B (read r, u; write r, u, s).  The two passes actually move 16 and
-    # 28 (q is stored by A and read by B, p is read again by B).
+    # pass B (read r, u; write r, u, s).  The two passes actually move 16 and,
+    # on average, 26 bytes: q is stored by A and read by B; B reads p again;
+    # on levels of >= 1024^2 pixels B updates u every second iteration
+    # (alternately 20 bytes without u and p, 32 with u and two directions).
     kern = {}
-    for name, bpp, moved in (("cg_pass_a", 12, 16), ("cg_pass_b", 20, 28)):
+    for name, bpp, moved in (("cg_pass_a", 12, 16), ("cg_pass_b", 20, 26)):
         n, ms, px = eecmg.profile_read(name)
         if n:
             avg_ms = ms / n

@@ -659,6 +659,7 @@ __device__ inline void fin_cg_init(const JobDesc& d, SolverState* st, const doub
   st->par = 0;
   st->beta = 0.0;
   st->alpha = 0.0;
+  st->alpha_prev = 0.0;
   st->done = kStopNone;
   st->pending = 0;
   st->level = d.level;
@@ -686,6 +687,7 @@ __device__ inline void fin_cg_a(const JobDesc& d, SolverState* st, const double 
     if (pub) publish(d, st);
     return;
   }
+  st->alpha_prev = st->alpha;
   st->alpha = st->gamma / eta;
 }
 
@@ -761,6 +763,10 @@ __device__ __forceinline__ void finalize_block(const JobDesc& d, const int (&com
 template <typename T>
 struct Two {
   T a, b;
+};
+template <typename T>
+struct Three {
+  T a, b, c;
 };
 
 // r = g - H u0, stored in r[0]; partial <r,r> in slot 1.  (CGLS and MR)
@@ -896,24 +902,27 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
   block_sum_store<P::NT, 1>(part, d.partials + (size_t)0 * d.pstride + L.t, d.pstride);
 }
 
-// Pass B of iteration k: r_new = r - alpha q (tile + halo), u += alpha p_new,
-// s = H^T r_new; partials <r,r> (slot 1) and <s,s> (slot 2).
-template <typename T, typename P>
-__global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWavesPerEU))) void k_cg_b(LaunchList ll, const JobDesc* __restrict__ descs) {
-  const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
-  const JobDesc& d = descs[L.d];
-  const SolverState* st = d.st;
-  if (__builtin_amdgcn_readfirstlane(st->done)) return;
-  const TileGeo g = tile_geo<P>(d, L.t);
-  const int par = uni(st->par);
-  const T alpha = (T)st->alpha;
+// Pass B of iteration k: r_new = r - alpha q (tile + halo), s = H^T r_new,
+// and the solution update; partials <r,r> (slot 1) and <s,s> (slot 2).
+// The solution update u += alpha_k p_k is applied per iteration (kUOne), or,
+// on levels the host marks lazy_u, every second iteration: even k defer
+// their term (kUDefer: no u or p traffic) and odd k apply both,
+// u = (u + alpha_{k-1} p_{k-1}) + alpha_k p_k, rounded to T after each term
+// exactly as two single updates; p_{k-1} is still in p[par] because pass A
+// writes p_k to the other buffer.  A level that stops with a deferred term
+// is completed by k_flush_u.
+enum : int { kUOne = 0, kUDefer = 1, kUTwo = 2 };
+
+template <typename T, typename P, int UM>
+__device__ __forceinline__ void cg_b_body(const JobDesc& d, const TileGeo& g, int par, T alpha, T alpha_prev,
+                                          double (&part)[2]) {
   const auto ro = gpc<T>(d.r[par]);
   auto rn = gp<T>(d.r[par ^ 1]);
   const auto q = gpc<T>(d.q[0]);
   const auto pn = gpc<T>(d.p[par ^ 1]);
+  const auto po = gpc<T>(d.p[par]);
   auto u = gp<T>(d.u);
   auto s = gp<T>(d.s);
-  double part[2] = {0.0, 0.0};
   auto load = [&](unsigned o) { return Two<T>{ro[o], q[o]}; };
   auto comb = [&](Two<T> x) { return fma(-alpha, x.b, x.a); };
   if constexpr (P::kStream) {
@@ -921,26 +930,52 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
     P::init(ps, (const T*)d.taps_t);
     const unsigned n = (unsigned)(g.h * g.pitch);
     const auto Ro = bview<T>(d.r[par], n), Rn = bview<T>(d.r[par ^ 1], n), Q = bview<T>(d.q[0], n);
-    const auto Pn = bview<T>(d.p[par ^ 1], n), U = bview<T>(d.u, n), S = bview<T>(d.s, n);
-    stream_strip<T, P>(
-        g, n, ps, [&](unsigned o) { return Two<T>{Ro.ld(o), Q.ld(o)}; }, comb,
-        [&](unsigned o) { return Two<T>{U.ld(o), Pn.ld(o)}; },
-        [&](unsigned o, T v, bool in, Two<T> x) {
-          Rn.st(o, v);
-          U.st(o, fma(alpha, x.b, x.a));
-          part[0] += in ? (double)v * (double)v : 0.0;
-        },
-        NoLoadF{},
-        [&](unsigned o, T acc, bool in, T, NoLoad) {
-          S.st(o, acc);
-          part[1] += in ? (double)acc * (double)acc : 0.0;
-        });
+    const auto Pn = bview<T>(d.p[par ^ 1], n), Po = bview<T>(d.p[par], n), U = bview<T>(d.u, n);
+    const auto S = bview<T>(d.s, n);
+    auto emit = [&](unsigned o, T acc, bool in, T, NoLoad) {
+      S.st(o, acc);
+      part[1] += in ? (double)acc * (double)acc : 0.0;
+    };
+    auto ld_in = [&](unsigned o) { return Two<T>{Ro.ld(o), Q.ld(o)}; };
+    if constexpr (UM == kUDefer) {
+      stream_strip<T, P>(
+          g, n, ps, ld_in, comb, NoLoadF{},
+          [&](unsigned o, T v, bool in, NoLoad) {
+            Rn.st(o, v);
+            part[0] += in ? (double)v * (double)v : 0.0;
+          },
+          NoLoadF{}, emit);
+    } else if constexpr (UM == kUTwo) {
+      stream_strip<T, P>(
+          g, n, ps, ld_in, comb, [&](unsigned o) { return Three<T>{U.ld(o), Pn.ld(o), Po.ld(o)}; },
+          [&](unsigned o, T v, bool in, Three<T> x) {
+            Rn.st(o, v);
+            U.st(o, fma(alpha, x.b, fma(alpha_prev, x.c, x.a)));
+            part[0] += in ? (double)v * (double)v : 0.0;
+          },
+          NoLoadF{}, emit);
+    } else {
+      stream_strip<T, P>(
+          g, n, ps, ld_in, comb, [&](unsigned o) { return Two<T>{U.ld(o), Pn.ld(o)}; },
+          [&](unsigned o, T v, bool in, Two<T> x) {
+            Rn.st(o, v);
+            U.st(o, fma(alpha, x.b, x.a));
+            part[0] += in ? (double)v * (double)v : 0.0;
+          },
+          NoLoadF{}, emit);
+    }
   } else {
     __shared__ T tile[P::LH * P::LW];
     load_tile<T, P>(tile, g, load, comb);
-    for_interior<P>(
-        g, [&](unsigned o) { return Two<T>{u[o], pn[o]}; },
-        [&](Two<T> x, unsigned o, int) { u[o] = fma(alpha, x.b, x.a); });
+    if constexpr (UM == kUTwo) {
+      for_interior<P>(
+          g, [&](unsigned o) { return Three<T>{u[o], pn[o], po[o]}; },
+          [&](Three<T> x, unsigned o, int) { u[o] = fma(alpha, x.b, fma(alpha_prev, x.c, x.a)); });
+    } else if constexpr (UM == kUOne) {
+      for_interior<P>(
+          g, [&](unsigned o) { return Two<T>{u[o], pn[o]}; },
+          [&](Two<T> x, unsigned o, int) { u[o] = fma(alpha, x.b, x.a); });
+    }
     __syncthreads();
     tile_interior<T, P>(tile, g, pol_R<P>(g), [&](T v, unsigned o, bool in) {
       if (in) rn[o] = v;
@@ -955,6 +990,25 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
       }
     });
   }
+}
+
+template <typename T, typename P>
+__global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWavesPerEU))) void k_cg_b(LaunchList ll, const JobDesc* __restrict__ descs) {
+  const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
+  const JobDesc& d = descs[L.d];
+  const SolverState* st = d.st;
+  if (__builtin_amdgcn_readfirstlane(st->done)) return;
+  const TileGeo g = tile_geo<P>(d, L.t);
+  const int par = uni(st->par);
+  const T alpha = (T)st->alpha;
+  const int um = uni(d.lazy_u) == 0 ? kUOne : ((uni(st->k) & 1) ? kUTwo : kUDefer);
+  double part[2] = {0.0, 0.0};
+  if (um == kUDefer)
+    cg_b_body<T, P, kUDefer>(d, g, par, alpha, T(0), part);
+  else if (um == kUTwo)
+    cg_b_body<T, P, kUTwo>(d, g, par, alpha, (T)st->alpha_prev, part);
+  else
+    cg_b_body<T, P, kUOne>(d, g, par, alpha, T(0), part);
   block_sum_store<P::NT, 2>(part, d.partials + (size_t)1 * d.pstride + L.t, d.pstride);
 }
 

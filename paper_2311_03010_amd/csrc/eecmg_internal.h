@@ -34,6 +34,7 @@ enum : int32_t { kStopNone = 0, kStopDiscrepancy = 1, kStopCap = 2, kStopGuard =
 struct SolverState {
   double gamma, gamma0, alpha, beta;  // CGLS: <s,s>, initial <s,s>, step, direction update
   double rr, rr0, rq, eta;            // <r,r>, initial <r,r>, <r,q> (MR), <q,q>
+  double alpha_prev;                  // CGLS: the previous iteration's step
   int32_t k;                          // iterations completed on this level
   int32_t done;                       // stop reason, 0 while running
   int32_t par;                        // ping-pong parity of r/p/q buffers
@@ -69,6 +70,8 @@ struct JobDesc {
   int32_t cascade, pm_steps;
   int32_t coarse_levels;  // level 0 only: leading levels solved by the coarse kernel
   int32_t zero_u;         // bit l: level l's smoother starts from zero (no transfer into it)
+  int32_t lazy_u;         // CGLS pass B updates u every second iteration (see k_cg_b)
+  int32_t pad1;
   double cdelta, eps2;
   SolverState* st;
   LevelRecord* rec;  // kMaxLevels records of this job
@@ -131,6 +134,7 @@ enum Stage : int32_t {
   kXfFused,         // prolongation -> S (-> one D step), fused; variant bit 0 quadratic, bit 1 with D
   kXfFusedSmall,    // the same with short tiles, for small levels
   kCoarse,          // the leading small levels of each job in one block per job
+  kFlushU,          // apply a deferred CGLS solution update when a lazy_u level stops
   kNumStages
 };
 

@@ -1018,6 +1018,31 @@ __global__ __launch_bounds__(256) void k_restrict(LaunchList ll, const JobDesc* 
   }
 }
 
+// A lazy_u level (see k_cg_b) that stopped with k odd still owes the update
+// u += alpha_k p_k of its last even iteration: alpha is that step (a stop in
+// the next pass A leaves it unchanged) and p_k sits in p[par] (pass B flipped
+// the parity, or the stopping pass A never wrote over it).
+template <typename T>
+__global__ __launch_bounds__(256) void k_flush_u(LaunchList ll, const JobDesc* __restrict__ descs) {
+  const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
+  const JobDesc& d = descs[L.d];
+  const SolverState* st = d.st;
+  if (!__builtin_amdgcn_readfirstlane(d.lazy_u) || !(__builtin_amdgcn_readfirstlane(st->k) & 1)) return;
+  const int tiles_x = (d.w + kXW - 1) / kXW;
+  const int ty = L.t / tiles_x, tx = L.t - ty * tiles_x;
+  const int x = tx * kXW + (threadIdx.x & 63);
+  if (x >= d.w) return;
+  const T a = (T)st->alpha;
+  const T* p = (const T*)d.p[__builtin_amdgcn_readfirstlane(st->par)];
+  T* u = (T*)d.u;
+  for (int k = 0; k < kXH / 4; ++k) {
+    const int y = ty * kXH + (threadIdx.x >> 6) * (kXH / 4) + k;
+    if (y >= d.h) break;
+    const size_t o = (size_t)y * d.pitch + x;
+    u[o] = fma(a, p[o], u[o]);
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_out_copy(LaunchList ll, const JobDesc* __restrict__ descs) {
   const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
@@ -1084,6 +1109,7 @@ int blocks_for_stage(Stage st, const JobDesc& d) {
     case kXfExtrap: return tiles2(d.hB, d.wB, kXH, kXW);
     case kXfFused: return tiles2(d.h, d.w, kFY, kFX);
     case kXfFusedSmall: return tiles2(d.h, d.w, kFYSmall, kFX);
+    case kFlushU: return tiles2(d.h, d.w, kXH, kXW);
     case kCoarse: return 1;
     default: return tiles2(d.h, d.w, kXH, kXW);
   }
@@ -1124,6 +1150,7 @@ static hipError_t launch_typed(Stage st, int variant, const LaunchList& ll, cons
   switch (st) {
     case kRestrict: hipLaunchKernelGGL(k_restrict<T>, grid, block, 0, s, ll, descs); return hipGetLastError();
     case kOutCopy: hipLaunchKernelGGL(k_out_copy<T>, grid, block, 0, s, ll, descs); return hipGetLastError();
+    case kFlushU: hipLaunchKernelGGL(k_flush_u<T>, grid, block, 0, s, ll, descs); return hipGetLastError();
     case kXfExtrap:
       hipLaunchKernelGGL((k_xfer<T, kXfExtrap>), grid, block, 0, s, ll, descs, src, dst);
       return hipGetLastError();

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -49,6 +50,7 @@ constexpr size_t kTapsSlotBytes = 32 << 10;  // pinned staging of one job's PSF 
 struct LevelPlan {
   int h = 0, w = 0, pitch = 0, rad = 0, cap = 0, ntiles = 0, tiles_x = 0;
   int variant = 0;                    // blur-operator kernel family (ConvKind * 100 + R)
+  bool lazy = false;                  // CGLS solution update every second iteration
   std::vector<double> psf;            // (2 rad + 1)^2, FP64
   std::vector<double> taps, taps_t;   // the variant's tap layout for H and H^T
 };
@@ -76,6 +78,16 @@ constexpr long kSmallLevelPixels = 1024L * 1024L;
 // Levels up to this many pixels (the leading ones of a cascade) are solved
 // by one block per job in a single launch.
 constexpr long kCoarsePixels = 64L * 64L;
+// CGLS levels of at least this many pixels update the solution every second
+// iteration (k_cg_b's lazy_u mode): it saves 8 bytes per pixel per pair of
+// iterations and costs one flush launch when the level ends.
+constexpr long kLazyPixels = 1024L * 1024L;
+// The threshold can be moved with EECMG_LAZY_MIN_PIXELS (tests use it to run
+// both update schedules on small images).
+static long lazy_min_pixels() {
+  const char* e = std::getenv("EECMG_LAZY_MIN_PIXELS");
+  return e ? std::atol(e) : kLazyPixels;
+}
 static void choose_variant(LevelPlan& lp, bool f64, bool by_size) {
   const int R = lp.rad, n = 2 * R + 1;
   const std::vector<double>& P = lp.psf;
@@ -303,6 +315,7 @@ static int build_plan(int H, int W, const double* psf, int r, int L, const int* 
       lp.taps_t.assign(lp.psf.rbegin(), lp.psf.rend());
     } else {
       choose_variant(P.lv[l], P.f64, true);
+      P.lv[l].lazy = P.prm.smoother == EECMG_SMOOTHER_CGLS && (long)P.lv[l].h * P.lv[l].w >= lazy_min_pixels();
     }
     P.off_taps[l] = take(P.lv[l].taps.size() * P.esz);
     P.off_tapst[l] = take(P.lv[l].taps_t.size() * P.esz);
@@ -627,6 +640,7 @@ class Engine {
     std::vector<std::pair<Job*, int>> xfer_l;  // job, level
     std::vector<Job*> init_l;
     std::vector<std::pair<Job*, int>> iter_l;  // job, chunk
+    std::vector<std::pair<Job*, int>> flush_l;  // job, level left with a possibly deferred update
     bool launched = false;
     for (int s = 0; s < kMaxSlots; ++s) {
       Job* j = slots_[s];
@@ -674,6 +688,7 @@ class Engine {
             // more pass, because its first pass only forms q = H r
             const int limit = j->plan.lv[j->cur_level()].cap + (j->plan.prm.smoother == EECMG_SMOOTHER_MR ? 1 : 0);
             if (j->cancelled || j->level_done_seen || j->issued >= limit) {
+              if (lazy_level(j, j->cur_level())) flush_l.push_back({j, j->cur_level()});
               if (!j->cancelled && j->oi + 1 < (int)j->plan.order.size()) {
                 j->oi += 1;
                 j->phase = Job::kStartLevel;
@@ -718,6 +733,20 @@ class Engine {
         for (Job* j : coarse_l)
           if ((int)j->plan.f64 == f64) js.push_back(j);
         if (!js.empty()) launch_group(kCoarse, js, 0, f64 != 0, 0, -1, -1);
+      }
+      launched = true;
+    }
+    if (!flush_l.empty()) {
+      // stream-ordered after the level's last pass, before anything reads u
+      for (int f64 = 0; f64 < 2; ++f64) {
+        std::vector<Job*> js;
+        std::vector<int> lv;
+        for (auto& x : flush_l)
+          if ((int)x.first->plan.f64 == f64) {
+            js.push_back(x.first);
+            lv.push_back(x.second);
+          }
+        if (!js.empty()) launch_group(kFlushU, js, -1, f64 != 0, 0, -1, -1, nullptr, &lv);
       }
       launched = true;
     }
@@ -815,6 +844,8 @@ class Engine {
     }
   }
 
+  static bool lazy_level(const Job* j, int l) { return j->plan.lv[l].lazy; }
+
   bool needs_transfer(const Job* j, int l) const {
     return j->plan.prm.cascade == EECMG_CASCADE_EECMG ? l >= 2 : l >= 1;
   }
@@ -868,6 +899,7 @@ class Engine {
     d.cascade = P.prm.cascade;
     d.pm_steps = P.prm.pm_steps;
     d.coarse_levels = l == 0 ? P.coarse : 0;
+    d.lazy_u = lazy_level(j, l) ? 1 : 0;
     for (int k = 0; k < P.L; ++k)
       if (!needs_transfer(j, k)) d.zero_u |= 1 << k;
     d.cdelta = P.prm.c * P.prm.delta;
@@ -915,12 +947,14 @@ class Engine {
   // Launch `stage` for jobs at the given level (-1: each job's current level),
   // splitting by nothing: caller groups jobs of one precision / variant.
   void launch_group(Stage st, const std::vector<Job*>& jobs, int level, bool f64, int variant, int src, int dst,
-                    const std::vector<int>* kidx = nullptr) {
+                    const std::vector<int>* kidx = nullptr, const std::vector<int>* levels = nullptr) {
     LaunchList ll;
     ll.n = 0;
     ll.total = 0;
-    for (Job* j : jobs) {
-      const int l = level >= 0 ? level : j->cur_level();
+    auto level_of = [&](size_t i) { return levels ? (*levels)[i] : level >= 0 ? level : jobs[i]->cur_level(); };
+    for (size_t i = 0; i < jobs.size(); ++i) {
+      Job* j = jobs[i];
+      const int l = level_of(i);
       if (l < 0 || l >= j->plan.L) {  // never launch with a descriptor that does not exist
         if (err_ == hipSuccess) err_ = hipErrorInvalidValue;
         return;
@@ -938,8 +972,9 @@ class Engine {
     Profiler& pr = profiler();
     if (pr.on.load(std::memory_order_relaxed) && profiled_stage(st) && ll.total >= pr.min_blocks) {
       double px = 0.0;
-      for (Job* j : jobs) {
-        const int l = level >= 0 ? level : j->cur_level();
+      for (size_t i = 0; i < jobs.size(); ++i) {
+        const Job* j = jobs[i];
+        const int l = level_of(i);
         px += st == kXfExtrap ? (double)j->plan.lv[l - 1].h * j->plan.lv[l - 1].w
                               : (double)j->plan.lv[l].h * j->plan.lv[l].w;
       }

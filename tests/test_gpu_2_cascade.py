@@ -169,6 +169,37 @@ def test_host_restore_equals_dev(torch_cuda):
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("caps", ["rule", "odd", "even"])
+def test_lazy_solution_update_is_bitwise_identical(torch_cuda, monkeypatch, prec, caps):
+    """Large CGLS levels update u every second iteration (a deferred term is
+    applied with the next one, or by a flush when the level stops).  Forced on
+    every level of a small cascade it must reproduce the per-iteration
+    schedule bit for bit, for odd and even iteration counts and for
+    data-dependent stops; so must the one-level smoother call."""
+    t = torch_cuda
+    p = synth.workload(3, H=200, W=160, n_levels=3, n_shapes=20, n_textures=2, precision=prec)
+    g = t.from_numpy(p.g_delta.astype(_dt(prec))).to("cuda:0")
+    kw = dict(precision=prec, delta=p.delta)
+    if caps == "rule":
+        cl = None
+    else:
+        cl = [3, 5, 7] if caps == "odd" else [2, 4, 6]
+        kw["stop_rule"] = False
+    res = {}
+    for mode, thr in (("lazy", "1"), ("eager", str(1 << 40))):
+        monkeypatch.setenv("EECMG_LAZY_MIN_PIXELS", thr)
+        u, st = eecmg.restore_dev(g, p.psf, 3, caps=cl, **kw)
+        u0 = t.zeros_like(g)
+        _, su = eecmg.smoother_dev(g, u0, p.psf, 5 if caps != "even" else 4, precision=prec, delta=p.delta)
+        t.cuda.synchronize()
+        res[mode] = (u.cpu().numpy(), st, u0.cpu().numpy(), su)
+    np.testing.assert_array_equal(res["lazy"][0], res["eager"][0])
+    assert res["lazy"][1] == res["eager"][1]
+    np.testing.assert_array_equal(res["lazy"][2], res["eager"][2])
+    assert res["lazy"][3] == res["eager"][3]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_in_place_finest_level_paths_agree(torch_cuda, prec):
     """Dense aligned buffers are used in place by the finest level; a
     misaligned view of the same data takes the pitched-copy path, and an
