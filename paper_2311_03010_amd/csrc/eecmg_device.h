@@ -748,12 +748,16 @@ __device__ inline void fin_mr(const JobDesc& d, SolverState* st, const double (&
   if (pub) publish(d, st);
 }
 
-// Body of a finalize kernel: sum the partials, then the scalar update.
+// Body of a finalize kernel: sum the partials, then the scalar update.  With
+// skip_if_done the stop flag is read together with the partials (one memory
+// round trip instead of two) and a level that has already stopped discards
+// the sums.
 template <int NV, typename F>
-__device__ __forceinline__ void finalize_block(const JobDesc& d, const int (&comp)[NV], F fin) {
+__device__ __forceinline__ void finalize_block(const JobDesc& d, const int (&comp)[NV], bool skip_if_done, F fin) {
+  const int done = skip_if_done ? d.st->done : 0;
   double v[NV];
   sum_partials<NV, 256>(d.partials, d.ntiles, d.pstride, comp, v);
-  if (threadIdx.x == 0) fin(d, v);
+  if (threadIdx.x == 0 && !done) fin(d, v);
 }
 
 // ---------------------------------------------------------------------------

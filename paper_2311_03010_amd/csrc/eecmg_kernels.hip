@@ -12,30 +12,27 @@ namespace eecmg {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_fin_cg_init(LaunchList ll, const JobDesc* __restrict__ descs) {
   const JobDesc& d = descs[ll.job[blockIdx.x]];
-  finalize_block(d, kCompCgInit, [](const JobDesc& dd, const double(&v)[2]) { fin_cg_init(dd, dd.st, v); });
+  finalize_block(d, kCompCgInit, false, [](const JobDesc& dd, const double(&v)[2]) { fin_cg_init(dd, dd.st, v); });
 }
 
 __global__ __launch_bounds__(256) void k_fin_cg_a(LaunchList ll, const JobDesc* __restrict__ descs) {
   const JobDesc& d = descs[ll.job[blockIdx.x]];
-  if (__builtin_amdgcn_readfirstlane(d.st->done)) return;
-  finalize_block(d, kCompCgA, [](const JobDesc& dd, const double(&v)[1]) { fin_cg_a(dd, dd.st, v); });
+  finalize_block(d, kCompCgA, true, [](const JobDesc& dd, const double(&v)[1]) { fin_cg_a(dd, dd.st, v); });
 }
 
 __global__ __launch_bounds__(256) void k_fin_cg_b(LaunchList ll, const JobDesc* __restrict__ descs) {
   const JobDesc& d = descs[ll.job[blockIdx.x]];
-  if (__builtin_amdgcn_readfirstlane(d.st->done)) return;
-  finalize_block(d, kCompCgB, [](const JobDesc& dd, const double(&v)[2]) { fin_cg_b(dd, dd.st, v); });
+  finalize_block(d, kCompCgB, true, [](const JobDesc& dd, const double(&v)[2]) { fin_cg_b(dd, dd.st, v); });
 }
 
 __global__ __launch_bounds__(256) void k_fin_mr_init(LaunchList ll, const JobDesc* __restrict__ descs) {
   const JobDesc& d = descs[ll.job[blockIdx.x]];
-  finalize_block(d, kCompMrInit, [](const JobDesc& dd, const double(&v)[1]) { fin_mr_init(dd, dd.st, v); });
+  finalize_block(d, kCompMrInit, false, [](const JobDesc& dd, const double(&v)[1]) { fin_mr_init(dd, dd.st, v); });
 }
 
 __global__ __launch_bounds__(256) void k_fin_mr(LaunchList ll, const JobDesc* __restrict__ descs) {
   const JobDesc& d = descs[ll.job[blockIdx.x]];
-  if (__builtin_amdgcn_readfirstlane(d.st->done)) return;
-  finalize_block(d, kCompMr, [](const JobDesc& dd, const double(&v)[3]) { fin_mr(dd, dd.st, v); });
+  finalize_block(d, kCompMr, true, [](const JobDesc& dd, const double(&v)[3]) { fin_mr(dd, dd.st, v); });
 }
 
 // ---------------------------------------------------------------------------
