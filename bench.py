@@ -15,6 +15,10 @@ reports
                  of Gaussian and disk PSFs, restored one call per image
                  (plain) and as one batched cascade, with the bitwise
                  agreement of the two;
+  edge:          the edge-preservation workload (edge-dense 1024^2 scene,
+                 Gaussian sigma=3, half bandwidth 11) with EECMG(MR) and
+                 EECMG(CG): throughput, PSNR and edge recovery of input and
+                 results;
   served:        requests (sides log-uniform in [64, 4096]) through the
                  create/submit/poll loop: closed-loop capacity, then Poisson
                  arrivals at 0.7 of it, with p50/p99 latency from arrival to
@@ -122,6 +126,37 @@ def cpu_baseline(p, stats):
 
 def _pct(xs, q):
     return float(np.percentile(np.asarray(xs), q))
+
+
+def edge_leg(torch, eecmg, synth, steps, H=1024, n_levels=7):
+    """Edge-preservation workload: edge-dense scene, Gaussian sigma=3 with
+    half bandwidth 11, N(0,1) noise, restored with EECMG(MR) (the paper's
+    edge experiment) and EECMG(CG); throughput and the quality measures of
+    input and results."""
+    from paper_2311_03010_amd import metrics
+
+    p = synth.edge_workload(H=H, n_levels=n_levels)
+    g = torch.from_numpy(p.g_delta.astype(np.float32)).to("cuda:0")
+    out = {"workload": f"{p.name}: edge-dense scene, Gaussian sigma=3 half bandwidth 11, N(0,1) noise, "
+                       f"{n_levels} levels, FP32",
+           "input": {"psnr": round(metrics.psnr(p.u_true, p.g_delta), 3),
+                     "edge_recall": round(metrics.edge_recall(p.u_true, p.g_delta), 4),
+                     "edge_error": round(metrics.edge_error(p.u_true, p.g_delta), 4)}}
+    for sm in ("mr", "cgls"):
+        kw = dict(precision="f32", delta=p.delta, k=p.k, smoother=sm)
+        u, st = eecmg.restore_dev(g, p.psf, n_levels, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            eecmg.restore_dev(g, p.psf, n_levels, out=u, **kw)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        uh = u.cpu().numpy()
+        out["eecmg_" + sm] = {"value": round(H * H / dt / 1e6, 3), "unit": "Mpixel/s", "ms_per_step": round(dt * 1e3, 3),
+                              "iters_per_level": st["iters"], "psnr": round(metrics.psnr(p.u_true, uh), 3),
+                              "edge_recall": round(metrics.edge_recall(p.u_true, uh), 4),
+                              "edge_error": round(metrics.edge_error(p.u_true, uh), 4)}
+    return out
 
 
 def set_leg(torch, eecmg, synth, n_images, steps):
@@ -280,6 +315,7 @@ def main():
     ap.add_argument("--set-steps", type=int, default=2)
     ap.add_argument("--served-requests", type=int, default=2000, help="served requests (0 = skip)")
     ap.add_argument("--served-pool", type=int, default=64)
+    ap.add_argument("--no-edge", action="store_true", help="skip the edge-preservation workload")
     ap.add_argument("--copy-probe", action="store_true", help="only run the HBM counter calibration copy")
     args = ap.parse_args()
     if args.copy_probe:
@@ -381,6 +417,11 @@ def main():
         _log(f"bench: uneven set, {args.set_images} images, plain vs batched")
         uneven = set_leg(torch, eecmg, synth, args.set_images, args.set_steps)
 
+    edge = None
+    if not args.no_edge:
+        _log("bench: edge-preservation workload")
+        edge = edge_leg(torch, eecmg, synth, args.steps)
+
     served = None
     if args.served_requests > 0:
         _log(f"bench: served, {args.served_requests} requests")
@@ -401,7 +442,7 @@ def main():
                        "n_levels": p.n_levels, "precision": prec, "stop_rule": "discrepancy c=1.1",
                        "caps": "economic m_l rule", "form": "plain"},
             "roofline": roofline, "cpu_baseline": cpu, "batched": batched, "uneven_set": uneven,
-            "served": served, "detail": extra}
+            "served": served, "edge": edge, "detail": extra}
     print(json.dumps(line), flush=True)
 
 

@@ -181,6 +181,57 @@ def workload(wid: int, **kw) -> Problem:
     raise ValueError(f"unknown single-image workload {wid}")
 
 
+def edge_scene(H: int, W: int, rng: np.random.Generator, density: float = 3000.0) -> np.ndarray:
+    """Edge-dense piecewise-constant scene: a flat background, many small
+    rectangles and disks (sides 3-48 px, `density` per Mpixel) and thin bars
+    one to three pixels wide across the image, every region at its own
+    intensity in [0, 255]."""
+    u = np.full((H, W), float(rng.uniform(0.0, 255.0)))
+    n = max(8, int(round(density * H * W / 1e6)))
+    for _ in range(n):
+        ci, cj = rng.uniform(0, H), rng.uniform(0, W)
+        a = math.exp(rng.uniform(math.log(3.0), math.log(48.0)))
+        b = math.exp(rng.uniform(math.log(3.0), math.log(48.0)))
+        val = rng.uniform(0.0, 255.0)
+        i0, i1 = int(max(0, ci - a / 2)), int(min(H, ci + a / 2 + 1))
+        j0, j1 = int(max(0, cj - b / 2)), int(min(W, cj + b / 2 + 1))
+        if i1 <= i0 or j1 <= j0:
+            continue
+        if rng.random() < 0.5:
+            u[i0:i1, j0:j1] = val
+        else:
+            yi = np.arange(i0, i1)[:, None] - ci
+            xj = np.arange(j0, j1)[None, :] - cj
+            sub = u[i0:i1, j0:j1]
+            sub[(yi / (a / 2)) ** 2 + (xj / (b / 2)) ** 2 <= 1.0] = val
+    for _ in range(max(2, int(round(40 * math.sqrt(H * W) / 1024)))):
+        width = int(rng.integers(1, 4))
+        val = rng.uniform(0.0, 255.0)
+        if rng.random() < 0.5:
+            i = int(rng.integers(0, max(1, H - width)))
+            u[i:i + width, :] = val
+        else:
+            j = int(rng.integers(0, max(1, W - width)))
+            u[:, j:j + width] = val
+    return u
+
+
+def edge_workload(H: int = 1024, W: int | None = None, n_levels: int = 7, precision: str = "f32") -> Problem:
+    """Edge-preservation workload: the edge-dense scene blurred with the
+    paper's strongest Gaussian case that its edge experiment uses (sigma = 3,
+    half bandwidth 11, normalised to unit sum) plus N(0,1) noise."""
+    W = H if W is None else W
+    seed = SEED_BASE + 6
+    rng = np.random.Generator(np.random.PCG64(seed))
+    u = edge_scene(H, W, rng)
+    psf = gaussian_psf(3.0, 11)
+    g = blur(u, psf)
+    e = rng.standard_normal((H, W))
+    delta = float(np.sqrt(np.mean(e * e)))
+    return Problem(name=f"edges_b3_{H}x{W}", u_true=u, psf=psf, g_delta=g + e, delta=delta, n_levels=n_levels,
+                   precision=precision, meta={"seed": seed, "psf": "gaussian sigma=3 r=11"})
+
+
 def batch_specs(n_images: int = 256, lo: int = 128, hi: int = 2048, wid: int = 4):
     """Sizes and PSFs of the uneven batch: H and W independently log-uniform
     in [lo, hi]; shapes proportional to area (200 per Mpixel, at least 8)."""

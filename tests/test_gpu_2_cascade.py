@@ -145,6 +145,21 @@ def test_workload3_scaled_f32(torch_cuda):
     _check(p, "f32", *_run_both(torch_cuda, p, "f32"))
 
 
+@pytest.mark.parametrize("smoother", ["mr", "cgls"])
+def test_edge_workload_scaled_f32(torch_cuda, smoother):
+    # the edge-preservation recipe (edge-dense scene, Gaussian sigma=3 with
+    # half bandwidth 11) at 256^2 with 5 levels; EECMG(MR) is the paper's
+    # edge experiment.  The edge measures of GPU and oracle results agree.
+    from paper_2311_03010_amd import metrics
+
+    p = synth.edge_workload(H=256, n_levels=5)
+    u, st, u_ref, st_ref = _run_both(torch_cuda, p, "f32", smoother=smoother)
+    _check(p, "f32", u, st, u_ref, st_ref)
+    assert abs(metrics.edge_recall(p.u_true, u) - metrics.edge_recall(p.u_true, u_ref)) <= 1e-3
+    assert abs(metrics.edge_error(p.u_true, u) - metrics.edge_error(p.u_true, u_ref)) <= 1e-3
+    assert metrics.edge_recall(p.u_true, u) > metrics.edge_recall(p.u_true, p.g_delta) + 0.2
+
+
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_pm_steps_and_smooth_scale(torch_cuda, prec):
     p = synth.workload(1, H=96, W=80)
