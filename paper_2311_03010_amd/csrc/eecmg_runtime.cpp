@@ -512,6 +512,10 @@ struct Job {
   bool level_done_seen = false;
   uint32_t uid = 0;           // engine-assigned id, part of the progress tag
   hipEvent_t done_ev = nullptr;
+  // served requests: the input copy runs on the context's copy stream; the
+  // first kernel of the job waits for in_ev, the output copy for comp_ev
+  hipEvent_t in_ev = nullptr, comp_ev = nullptr;
+  bool in_wait = false;
   int status = EECMG_OK;
   LevelRecord rec[kMaxLevels];
   // served-request extras
@@ -578,6 +582,16 @@ class Engine {
   }
 
   void set_stream(hipStream_t s) { stream_ = s; }
+  // Host<->device copies of served requests go to this stream (NULL: the
+  // compute stream), so they overlap other requests' kernels.
+  void set_copy_stream(hipStream_t s) { copy_ = s; }
+  // The job's input was enqueued on stream s: its first kernel waits for it.
+  int mark_input(Job* j, hipStream_t s) {
+    if (!j->in_ev && hipEventCreateWithFlags(&j->in_ev, hipEventDisableTiming) != hipSuccess) return EECMG_EDEVICE;
+    if (hipEventRecord(j->in_ev, s) != hipSuccess) return EECMG_EDEVICE;
+    j->in_wait = true;
+    return EECMG_OK;
+  }
   // First HIP error met by an asynchronous call (sticky), and its reset.
   hipError_t error() const { return err_; }
   void clear_error() { err_ = hipSuccess; }
@@ -722,6 +736,11 @@ class Engine {
     }
     // launches, in dependency order
     if (!restrict_l.empty()) {
+      for (Job* j : restrict_l)
+        if (j->in_wait) {
+          chk(hipStreamWaitEvent(stream_, j->in_ev, 0));
+          j->in_wait = false;
+        }
       // level 0's descriptor: the restriction fields are the same on every
       // level, and a job whose levels are all coarse has no current level
       launch_group(kRestrict, restrict_l, 0, false, 0, -1, -1);
@@ -767,11 +786,18 @@ class Engine {
       if (!j->alias_out) launch_group(kOutCopy, one, j->plan.L - 1, j->plan.f64, 0, -1, -1);
       chk(hipMemcpyAsync(h_rec_ + (size_t)j->slot * kMaxLevels, d_rec_ + (size_t)j->slot * kMaxLevels,
                      sizeof(LevelRecord) * kMaxLevels, hipMemcpyDeviceToHost, stream_));
-      if (j->host_out)
-        chk(hipMemcpyAsync(j->host_out, j->u_out_dev, (size_t)j->plan.H * j->plan.W * j->plan.esz,
-                       hipMemcpyDeviceToHost, stream_));
       if (!j->done_ev) chk(hipEventCreateWithFlags(&j->done_ev, hipEventDisableTiming));
-      chk(hipEventRecord(j->done_ev, stream_));
+      const size_t out_bytes = (size_t)j->plan.H * j->plan.W * j->plan.esz;
+      if (j->host_out && copy_) {
+        if (!j->comp_ev) chk(hipEventCreateWithFlags(&j->comp_ev, hipEventDisableTiming));
+        chk(hipEventRecord(j->comp_ev, stream_));
+        chk(hipStreamWaitEvent(copy_, j->comp_ev, 0));
+        chk(hipMemcpyAsync(j->host_out, j->u_out_dev, out_bytes, hipMemcpyDeviceToHost, copy_));
+        chk(hipEventRecord(j->done_ev, copy_));
+      } else {
+        if (j->host_out) chk(hipMemcpyAsync(j->host_out, j->u_out_dev, out_bytes, hipMemcpyDeviceToHost, stream_));
+        chk(hipEventRecord(j->done_ev, stream_));
+      }
       j->phase = Job::kWaitOut;
       launched = true;
     }
@@ -808,8 +834,11 @@ class Engine {
     if (j->mem) arena_.free(j->mem, j->plan.bytes);
     j->mem = nullptr;
     j->slot = -1;
-    if (j->done_ev) (void)hipEventDestroy(j->done_ev);
-    j->done_ev = nullptr;
+    for (hipEvent_t* e : {&j->done_ev, &j->in_ev, &j->comp_ev}) {
+      if (*e) (void)hipEventDestroy(*e);
+      *e = nullptr;
+    }
+    j->in_wait = false;
   }
 
   int device() const { return device_; }
@@ -1101,6 +1130,7 @@ class Engine {
   int device_;
   hipError_t err_ = hipSuccess;
   hipStream_t stream_ = nullptr;
+  hipStream_t copy_ = nullptr;
   Arena arena_;
   JobDesc* d_desc_ = nullptr;
   JobDesc* h_desc_ = nullptr;
@@ -1635,7 +1665,8 @@ struct eecmg_ctx {
   int device = 0;
   eecmg_ctx_config cfg{};
   std::unique_ptr<eecmg::Engine> eng;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;       // kernels of every admitted request
+  hipStream_t copy_stream = nullptr;  // their input and output copies
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<uint64_t> queue;
@@ -1675,7 +1706,8 @@ static void progress_loop(eecmg_ctx* C) {
         }
         Job* j = r->job.get();
         if (hipMemcpyAsync((void*)j->g_in_dev, j->host_in, (size_t)j->plan.H * j->plan.W * j->plan.esz,
-                           hipMemcpyHostToDevice, C->stream) != hipSuccess)
+                           hipMemcpyHostToDevice, C->copy_stream) != hipSuccess ||
+            E.mark_input(j, C->copy_stream) != EECMG_OK)
           j->cancelled = true;
         r->admitted = true;
         ++C->active;
@@ -1730,9 +1762,11 @@ int eecmg_create(const eecmg_ctx_config* cfg, eecmg_ctx** out) {
   C->cfg = c;
   EECMG_HIP(hipSetDevice(c.device));
   EECMG_HIP(hipStreamCreateWithFlags(&C->stream, hipStreamNonBlocking));
+  EECMG_HIP(hipStreamCreateWithFlags(&C->copy_stream, hipStreamNonBlocking));
   C->eng.reset(new Engine(c.device));
   int rc = C->eng->init(C->stream);
   if (rc) return rc;
+  C->eng->set_copy_stream(C->copy_stream);
   rc = C->eng->arena().reserve(c.hbm_budget_bytes);
   if (rc) return rc;
   C->th = std::thread(progress_loop, C.get());
@@ -1839,6 +1873,7 @@ int eecmg_destroy(eecmg_ctx* C) {
   if (C->th.joinable()) C->th.join();
   (void)hipSetDevice(C->device);
   (void)hipStreamSynchronize(C->stream);
+  (void)hipStreamSynchronize(C->copy_stream);
   for (auto& kv : C->reqs) {
     C->pool.put(kv.second->job->host_in, kv.second->in_cls);
     C->pool.put(kv.second->job->host_out, kv.second->out_cls);
@@ -1848,6 +1883,7 @@ int eecmg_destroy(eecmg_ctx* C) {
   C->eng->shutdown();
   C->pool.release_all();
   (void)hipStreamDestroy(C->stream);
+  (void)hipStreamDestroy(C->copy_stream);
   delete C;
   return EECMG_OK;
 }

@@ -443,8 +443,12 @@ class Context:
         _check(rc)
         return u, st.to_dict()
 
-    def wait(self, req: Request):
-        u = np.empty(req.shape, dtype=req.dtype)
+    def wait(self, req: Request, out=None):
+        """Block until the request finishes; (u, stats).  out: optional
+        preallocated array of the request's shape and dtype."""
+        u = np.empty(req.shape, dtype=req.dtype) if out is None else out
+        if u.shape != tuple(req.shape) or u.dtype != req.dtype or not u.flags.c_contiguous:
+            raise ValueError("out must be a contiguous array of the request's shape and dtype")
         st = Stats()
         _check(lib().eecmg_wait(self._h, req.id, u.ctypes.data, ctypes.byref(st)))
         return u, st.to_dict()
