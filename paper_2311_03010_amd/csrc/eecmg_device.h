@@ -659,7 +659,7 @@ __device__ inline void fin_cg_init(const JobDesc& d, SolverState* st, const doub
   st->par = 0;
   st->beta = 0.0;
   st->alpha = 0.0;
-  st->alpha_prev = 0.0;
+  st->alph[0] = st->alph[1] = 0.0;
   st->done = kStopNone;
   st->pending = 0;
   st->level = d.level;
@@ -687,8 +687,8 @@ __device__ inline void fin_cg_a(const JobDesc& d, SolverState* st, const double 
     if (pub) publish(d, st);
     return;
   }
-  st->alpha_prev = st->alpha;
   st->alpha = st->gamma / eta;
+  st->alph[st->k & 1] = st->alpha;
 }
 
 // After pass B: <r,r> (1), gamma_new = <s,s> (2), beta = gamma_new / gamma.
@@ -1004,13 +1004,30 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
   if (__builtin_amdgcn_readfirstlane(st->done)) return;
   const TileGeo g = tile_geo<P>(d, L.t);
   const int par = uni(st->par);
-  const T alpha = (T)st->alpha;
-  const int um = uni(d.lazy_u) == 0 ? kUOne : ((uni(st->k) & 1) ? kUTwo : kUDefer);
+  const int k = uni(st->k);
+  T alpha;
+  if (uni(d.fold_a) && (ll.flags & kLaunchFoldA)) {
+    // the finalize of pass A, evaluated by every block from the same partials
+    // in the same order (identical alpha everywhere); logical tile 0 records
+    // it, or the stop when <q,q> is 0 or not finite
+    double v[1];
+    sum_partials<1, P::NT>(d.partials, d.ntiles, d.pstride, kCompCgA, v);
+    const bool lead = L.t == 0 && threadIdx.x == 0;
+    if (!finite_d(v[0]) || v[0] == 0.0) {
+      if (lead) fin_cg_a(d, d.st, v);
+      return;
+    }
+    if (lead) fin_cg_a(d, d.st, v);
+    alpha = (T)(st->gamma / v[0]);
+  } else {
+    alpha = (T)st->alph[k & 1];
+  }
+  const int um = uni(d.lazy_u) == 0 ? kUOne : ((k & 1) ? kUTwo : kUDefer);
   double part[2] = {0.0, 0.0};
   if (um == kUDefer)
     cg_b_body<T, P, kUDefer>(d, g, par, alpha, T(0), part);
   else if (um == kUTwo)
-    cg_b_body<T, P, kUTwo>(d, g, par, alpha, (T)st->alpha_prev, part);
+    cg_b_body<T, P, kUTwo>(d, g, par, alpha, (T)st->alph[(k - 1) & 1], part);
   else
     cg_b_body<T, P, kUOne>(d, g, par, alpha, T(0), part);
   block_sum_store<P::NT, 2>(part, d.partials + (size_t)1 * d.pstride + L.t, d.pstride);

@@ -34,7 +34,7 @@ enum : int32_t { kStopNone = 0, kStopDiscrepancy = 1, kStopCap = 2, kStopGuard =
 struct SolverState {
   double gamma, gamma0, alpha, beta;  // CGLS: <s,s>, initial <s,s>, step, direction update
   double rr, rr0, rq, eta;            // <r,r>, initial <r,r>, <r,q> (MR), <q,q>
-  double alpha_prev;                  // CGLS: the previous iteration's step
+  double alph[2];                     // CGLS: step alpha_k of the last iteration k of each parity
   int32_t k;                          // iterations completed on this level
   int32_t done;                       // stop reason, 0 while running
   int32_t par;                        // ping-pong parity of r/p/q buffers
@@ -71,7 +71,7 @@ struct JobDesc {
   int32_t coarse_levels;  // level 0 only: leading levels solved by the coarse kernel
   int32_t zero_u;         // bit l: level l's smoother starts from zero (no transfer into it)
   int32_t lazy_u;         // CGLS pass B updates u every second iteration (see k_cg_b)
-  int32_t pad1;
+  int32_t fold_a;         // CGLS pass B may compute alpha itself (when its launch says so)
   double cdelta, eps2;
   SolverState* st;
   LevelRecord* rec;  // kMaxLevels records of this job
@@ -104,9 +104,13 @@ __host__ __device__ inline uint64_t mirror_word(uint32_t tag, int32_t k, int32_t
 
 // Kernel-argument list of the jobs one launch covers.  Block b belongs to the
 // entry e with start[e] <= b < start[e+1]; job[e] indexes the JobDesc table.
+// Launch options (LaunchList::flags).
+enum : int32_t { kLaunchFoldA = 1 };  // pass B evaluates pass A's finalize (jobs with fold_a)
+
 struct LaunchList {
   int32_t n;
   int32_t total;
+  int32_t flags;
   int32_t job[kMaxLaunchJobs];
   int32_t start[kMaxLaunchJobs + 1];
 };

@@ -51,6 +51,7 @@ struct LevelPlan {
   int h = 0, w = 0, pitch = 0, rad = 0, cap = 0, ntiles = 0, tiles_x = 0;
   int variant = 0;                    // blur-operator kernel family (ConvKind * 100 + R)
   bool lazy = false;                  // CGLS solution update every second iteration
+  bool fold_a = false;                // CGLS pass B evaluates pass A's finalize itself
   std::vector<double> psf;            // (2 rad + 1)^2, FP64
   std::vector<double> taps, taps_t;   // the variant's tap layout for H and H^T
 };
@@ -87,6 +88,17 @@ constexpr long kLazyPixels = 1024L * 1024L;
 static long lazy_min_pixels() {
   const char* e = std::getenv("EECMG_LAZY_MIN_PIXELS");
   return e ? std::atol(e) : kLazyPixels;
+}
+// CGLS levels with the four-wave general blur kernels and at most this many
+// tiles let every block of pass B sum pass A's partials itself (the same
+// fixed order as the finalize kernel, so alpha is bit-identical), which saves
+// a launch per iteration on the small levels where launches dominate.
+// EECMG_FOLD_MAX_TILES moves the limit (0 turns it off).
+constexpr long kFoldMaxTiles = 4096;
+constexpr int kFoldMaxJobs = 1;
+static long fold_max_tiles() {
+  const char* e = std::getenv("EECMG_FOLD_MAX_TILES");
+  return e ? std::atol(e) : kFoldMaxTiles;
 }
 static void choose_variant(LevelPlan& lp, bool f64, bool by_size) {
   const int R = lp.rad, n = 2 * R + 1;
@@ -332,6 +344,9 @@ static int build_plan(int H, int W, const double* psf, int r, int L, const int* 
     const int th = tile_h_for_variant(lp.variant);
     lp.tiles_x = (lp.w + kTW - 1) / kTW;
     lp.ntiles = lp.tiles_x * ((lp.h + th - 1) / th);
+    const int kind = lp.variant / 100;
+    lp.fold_a = l >= P.coarse && P.prm.smoother == EECMG_SMOOTHER_CGLS &&
+                (kind == kConvGeneral || kind == kConvGenShort) && lp.ntiles <= fold_max_tiles();
     P.max_tiles = std::max(P.max_tiles, lp.ntiles);
     P.off_g[l] = take((size_t)lp.h * lp.pitch * P.esz);
     P.off_u[l] = take((size_t)lp.h * lp.pitch * P.esz);
@@ -929,6 +944,7 @@ class Engine {
     d.pm_steps = P.prm.pm_steps;
     d.coarse_levels = l == 0 ? P.coarse : 0;
     d.lazy_u = lazy_level(j, l) ? 1 : 0;
+    d.fold_a = lp.fold_a ? 1 : 0;
     for (int k = 0; k < P.L; ++k)
       if (!needs_transfer(j, k)) d.zero_u |= 1 << k;
     d.cdelta = P.prm.c * P.prm.delta;
@@ -976,10 +992,12 @@ class Engine {
   // Launch `stage` for jobs at the given level (-1: each job's current level),
   // splitting by nothing: caller groups jobs of one precision / variant.
   void launch_group(Stage st, const std::vector<Job*>& jobs, int level, bool f64, int variant, int src, int dst,
-                    const std::vector<int>* kidx = nullptr, const std::vector<int>* levels = nullptr) {
+                    const std::vector<int>* kidx = nullptr, const std::vector<int>* levels = nullptr,
+                    int flags = 0) {
     LaunchList ll;
     ll.n = 0;
     ll.total = 0;
+    ll.flags = flags;
     auto level_of = [&](size_t i) { return levels ? (*levels)[i] : level >= 0 ? level : jobs[i]->cur_level(); };
     for (size_t i = 0; i < jobs.size(); ++i) {
       Job* j = jobs[i];
@@ -1096,8 +1114,13 @@ class Engine {
         const std::vector<int>* ki = &kidx[kv.first];
         if (kv.first.first == EECMG_SMOOTHER_CGLS) {
           launch_group(kCgA, kv.second, -1, f64, rc, -1, -1, ki);
-          launch_fin(kCgFinA, kv.second);
-          launch_group(kCgB, kv.second, -1, f64, rc, -1, -1, ki);
+          // fold pass A's finalize into pass B when the launch is small: each
+          // block then repeats the sum, which pays off only while a separate
+          // launch costs more than that (a launch shared by many jobs does not)
+          bool fold = (int)kv.second.size() <= kFoldMaxJobs;
+          for (Job* j : kv.second) fold = fold && j->plan.lv[j->cur_level()].fold_a;
+          if (!fold) launch_fin(kCgFinA, kv.second);
+          launch_group(kCgB, kv.second, -1, f64, rc, -1, -1, ki, nullptr, fold ? kLaunchFoldA : 0);
           launch_fin(kCgFinB, kv.second);
         } else {
           launch_group(kMrPass, kv.second, -1, f64, rc, -1, -1, ki);

@@ -215,6 +215,32 @@ def test_lazy_solution_update_is_bitwise_identical(torch_cuda, monkeypatch, prec
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("lazy", [False, True])
+def test_folded_finalize_is_bitwise_identical(torch_cuda, monkeypatch, prec, lazy):
+    """On small levels pass B evaluates pass A's finalize in every block (same
+    partials, same summation order) instead of a separate launch.  With the
+    fold on or off the cascade, its statistics and the one-level smoother
+    agree bit for bit, also combined with the every-second-iteration update."""
+    t = torch_cuda
+    p = synth.workload(2, H=256, W=192, n_levels=5, n_shapes=40, precision=prec)
+    g = t.from_numpy(p.g_delta.astype(_dt(prec))).to("cuda:0")
+    psf1 = synth.gaussian_psf(0.8, 1)
+    monkeypatch.setenv("EECMG_LAZY_MIN_PIXELS", "1" if lazy else str(1 << 40))
+    res = {}
+    for mode, lim in (("fold", "4096"), ("separate", "0")):
+        monkeypatch.setenv("EECMG_FOLD_MAX_TILES", lim)
+        u, st = eecmg.restore_dev(g, p.psf, 5, precision=prec, delta=p.delta)
+        u0 = t.zeros_like(g)
+        _, su = eecmg.smoother_dev(g, u0, psf1, 7, precision=prec, delta=p.delta)
+        t.cuda.synchronize()
+        res[mode] = (u.cpu().numpy(), st, u0.cpu().numpy(), su)
+    np.testing.assert_array_equal(res["fold"][0], res["separate"][0])
+    assert res["fold"][1] == res["separate"][1]
+    np.testing.assert_array_equal(res["fold"][2], res["separate"][2])
+    assert res["fold"][3] == res["separate"][3]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_in_place_finest_level_paths_agree(torch_cuda, prec):
     """Dense aligned buffers are used in place by the finest level; a
     misaligned view of the same data takes the pitched-copy path, and an
