@@ -629,18 +629,20 @@ __device__ __forceinline__ void publish(const JobDesc& d, const SolverState* st)
 
 // Stopping tests of the smoother, in the order: non-finite, discrepancy
 // principle ||r|| <= c delta (RMS norm), iteration cap m_l, convergence guard.
+__device__ __forceinline__ int stop_reason(const JobDesc& d, int k, double rr, double guard_val, double guard_ref,
+                                           bool nonfinite) {
+  const double rms = sqrt(rr / ((double)d.h * (double)d.w));
+  if (nonfinite) return kStopNonFinite;
+  if (d.stop_rule && rms <= d.cdelta) return kStopDiscrepancy;
+  if (k >= d.cap) return kStopCap;
+  if (guard_val == 0.0 || guard_val <= d.eps2 * guard_ref) return kStopGuard;
+  return kStopNone;
+}
+
 __device__ __forceinline__ void check_stop(SolverState* st, const JobDesc& d, double rr, double guard_val,
                                            double guard_ref, bool nonfinite) {
   const double rms = sqrt(rr / ((double)d.h * (double)d.w));
-  int reason = kStopNone;
-  if (nonfinite)
-    reason = kStopNonFinite;
-  else if (d.stop_rule && rms <= d.cdelta)
-    reason = kStopDiscrepancy;
-  else if (st->k >= d.cap)
-    reason = kStopCap;
-  else if (guard_val == 0.0 || guard_val <= d.eps2 * guard_ref)
-    reason = kStopGuard;
+  const int reason = stop_reason(d, st->k, rr, guard_val, guard_ref, nonfinite);
   st->rr = rr;
   if (reason != kStopNone) {
     st->done = reason;
@@ -660,10 +662,12 @@ __device__ inline void fin_cg_init(const JobDesc& d, SolverState* st, const doub
   st->beta = 0.0;
   st->alpha = 0.0;
   st->alph[0] = st->alph[1] = 0.0;
+  st->gam[1] = 0.0;
   st->done = kStopNone;
   st->pending = 0;
   st->level = d.level;
   st->gamma = v[1];
+  st->gam[0] = v[1];
   st->gamma0 = v[1];
   st->rr0 = v[0];
   d.rec[d.level].iters = 0;
@@ -698,6 +702,7 @@ __device__ inline void fin_cg_b(const JobDesc& d, SolverState* st, const double 
   st->beta = gnew / st->gamma;
   st->gamma = gnew;
   st->k += 1;
+  st->gam[st->k & 1] = gnew;
   st->par ^= 1;
   st->seq += 1;
   check_stop(st, d, v[0], gnew, st->gamma0, !finite_d(v[0]) || !finite_d(gnew));
@@ -864,9 +869,25 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
   const SolverState* st = d.st;
   if (__builtin_amdgcn_readfirstlane(st->done)) return;
   const TileGeo g = tile_geo<P>(d, L.t);
-  const int par = uni(st->par);
-  const T beta = (T)st->beta;
-  const bool first = uni(st->k) == 0;
+  // with kLaunchFoldB (one job per launch) every block evaluates the
+  // previous pass B's finalize from its partials, in the finalize kernel's
+  // order: the stop decision and beta are identical everywhere; logical tile
+  // 0 records them.  The iteration index comes from the launch.
+  const bool foldb = uni(d.fold_a) && (ll.flags & kLaunchFoldB);
+  const int k = foldb ? ll.k0 : uni(st->k);
+  T beta;
+  if (foldb && k > 0) {
+    double v[2];
+    sum_partials<2, P::NT>(d.partials, d.ntiles, d.pstride, kCompCgB, v);
+    const int reason = stop_reason(d, k, v[0], v[1], st->gamma0, !finite_d(v[0]) || !finite_d(v[1]));
+    if (L.t == 0 && threadIdx.x == 0) fin_cg_b(d, d.st, v);
+    if (reason != kStopNone) return;
+    beta = (T)(v[1] / st->gam[(k - 1) & 1]);
+  } else {
+    beta = (T)st->beta;
+  }
+  const int par = foldb ? (k & 1) : uni(st->par);
+  const bool first = k == 0;
   const auto s = gpc<T>(d.s);
   const auto po = gpc<T>(d.p[par]);
   auto pn = gp<T>(d.p[par ^ 1]);

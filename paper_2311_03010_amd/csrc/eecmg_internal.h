@@ -35,6 +35,7 @@ struct SolverState {
   double gamma, gamma0, alpha, beta;  // CGLS: <s,s>, initial <s,s>, step, direction update
   double rr, rr0, rq, eta;            // <r,r>, initial <r,r>, <r,q> (MR), <q,q>
   double alph[2];                     // CGLS: step alpha_k of the last iteration k of each parity
+  double gam[2];                      // CGLS: gamma_k = <s_k,s_k> of the last iteration k of each parity
   int32_t k;                          // iterations completed on this level
   int32_t done;                       // stop reason, 0 while running
   int32_t par;                        // ping-pong parity of r/p/q buffers
@@ -94,6 +95,17 @@ struct JobDesc {
   void* g_lv[kMaxLevels];
   void* u_lv[kMaxLevels];
   int32_t lh[kMaxLevels], lw[kMaxLevels], lp[kMaxLevels];
+  // bytes of the job's PSF-taps region (it starts at level 0's taps)
+  int32_t taps_bytes;
+  int32_t pad2;
+};
+
+static_assert(sizeof(JobDesc) % 4 == 0, "descriptors are copied as 32-bit words");
+
+// Slots whose descriptors and taps k_upload copies from pinned host memory.
+struct UploadList {
+  int32_t n;
+  int32_t slot[kMaxLaunchJobs];
 };
 
 // Progress word published by the finalize kernels into pinned host memory:
@@ -105,12 +117,16 @@ __host__ __device__ inline uint64_t mirror_word(uint32_t tag, int32_t k, int32_t
 // Kernel-argument list of the jobs one launch covers.  Block b belongs to the
 // entry e with start[e] <= b < start[e+1]; job[e] indexes the JobDesc table.
 // Launch options (LaunchList::flags).
-enum : int32_t { kLaunchFoldA = 1 };  // pass B evaluates pass A's finalize (jobs with fold_a)
+// kLaunchFoldA: pass B evaluates pass A's finalize; kLaunchFoldB: pass A
+// evaluates the previous pass B's finalize (single-job launches, iteration
+// index k0).  Both only for jobs whose level has fold_a set.
+enum : int32_t { kLaunchFoldA = 1, kLaunchFoldB = 2 };
 
 struct LaunchList {
   int32_t n;
   int32_t total;
   int32_t flags;
+  int32_t k0;
   int32_t job[kMaxLaunchJobs];
   int32_t start[kMaxLaunchJobs + 1];
 };
@@ -181,6 +197,12 @@ hipError_t launch_stage(Stage st, bool f64, int variant, const LaunchList& ll, c
                         int dst, hipStream_t stream);
 int rmax_class_for(int r);
 int blocks_for_stage(Stage st, const JobDesc& d);
+
+// Copy the listed slots' descriptors (host table hdesc, kMaxLevels per slot)
+// and PSF taps (htaps, taps_stride bytes per slot), both in device-visible
+// pinned host memory, to ddesc and to each job's taps region.
+hipError_t launch_upload(const UploadList& ul, const JobDesc* hdesc, JobDesc* ddesc, const char* htaps,
+                         size_t taps_stride, hipStream_t s);
 
 // Operator kernels on dense buffers (one image, no job table).
 hipError_t op_conv(const void* x, void* y, int H, int W, const void* taps, int variant, int radius, bool f64,

@@ -1040,6 +1040,40 @@ __global__ __launch_bounds__(256) void k_flush_u(LaunchList ll, const JobDesc* _
   }
 }
 
+// Descriptors and PSF taps of newly admitted jobs, one block per job, read
+// straight from pinned host memory: a step that admits many jobs costs one
+// launch instead of two copies per job.
+__global__ __launch_bounds__(256) void k_upload(UploadList ul, const JobDesc* __restrict__ hdesc,
+                                                JobDesc* __restrict__ ddesc, const char* __restrict__ htaps,
+                                                size_t taps_stride) {
+  const int s = ul.slot[blockIdx.x];
+  const JobDesc* src = hdesc + (size_t)s * kMaxLevels;
+  const int L = src->L;
+  const int tb = src->taps_bytes;
+  uint32_t* tdst = (uint32_t*)const_cast<void*>(src->taps);
+  // every load of a round is issued before any store (host memory is far)
+  auto copy = [](uint32_t* __restrict__ dst, const uint32_t* __restrict__ from, int n) {
+    constexpr int B = 8;
+    for (int base = threadIdx.x; base < n; base += B * 256) {
+      uint32_t v[B];
+#pragma unroll
+      for (int m = 0; m < B; ++m) v[m] = base + m * 256 < n ? from[base + m * 256] : 0u;
+#pragma unroll
+      for (int m = 0; m < B; ++m)
+        if (base + m * 256 < n) dst[base + m * 256] = v[m];
+    }
+  };
+  copy((uint32_t*)(ddesc + (size_t)s * kMaxLevels), (const uint32_t*)src, L * (int)(sizeof(JobDesc) / 4));
+  copy(tdst, (const uint32_t*)(htaps + (size_t)s * taps_stride), tb / 4);
+}
+
+hipError_t launch_upload(const UploadList& ul, const JobDesc* hdesc, JobDesc* ddesc, const char* htaps,
+                         size_t taps_stride, hipStream_t s) {
+  if (ul.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_upload, dim3(ul.n), dim3(256), 0, s, ul, hdesc, ddesc, htaps, taps_stride);
+  return hipGetLastError();
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_out_copy(LaunchList ll, const JobDesc* __restrict__ descs) {
   const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));

@@ -512,6 +512,17 @@ static bool profiled_stage(Stage st) {
 constexpr int kMaxSlots = EECMG_MAX_SLOTS;
 static_assert(kMaxSlots <= kMaxLaunchJobs, "one launch must be able to cover every slot");
 
+// An event owned by every job that waits for it.
+struct HipEvent {
+  hipEvent_t e = nullptr;
+  HipEvent() { (void)hipEventCreateWithFlags(&e, hipEventDisableTiming); }
+  ~HipEvent() {
+    if (e) (void)hipEventDestroy(e);
+  }
+  HipEvent(const HipEvent&) = delete;
+  HipEvent& operator=(const HipEvent&) = delete;
+};
+
 struct Job {
   Plan plan;
   int slot = -1;
@@ -526,7 +537,9 @@ struct Job {
   int confirmed = 0;
   bool level_done_seen = false;
   uint32_t uid = 0;           // engine-assigned id, part of the progress tag
-  hipEvent_t done_ev = nullptr;
+  std::shared_ptr<struct HipEvent> done_ev;  // output complete (shared by jobs finishing in one step)
+  bool needs_upload = false;                  // descriptors and taps still in pinned host memory
+  bool fin_b_pending = false;                 // the last issued pass B has no finalize yet (see kLaunchFoldB)
   // served requests: the input copy runs on the context's copy stream; the
   // first kernel of the job waits for in_ev, the output copy for comp_ev
   hipEvent_t in_ev = nullptr, comp_ev = nullptr;
@@ -562,9 +575,13 @@ class Engine {
     EECMG_HIP(hipMalloc(&d_state_, sizeof(SolverState) * kMaxSlots));
     EECMG_HIP(hipMalloc(&d_rec_, sizeof(LevelRecord) * kMaxSlots * kMaxLevels));
     EECMG_HIP(hipMemset(d_state_, 0, sizeof(SolverState) * kMaxSlots));
-    EECMG_HIP(hipHostMalloc((void**)&h_desc_, sizeof(JobDesc) * kMaxSlots * kMaxLevels, hipHostMallocDefault));
+    // descriptors and taps are staged in fine-grained pinned memory that
+    // k_upload reads directly (no stale device-cached copies)
+    EECMG_HIP(hipHostMalloc((void**)&h_desc_, sizeof(JobDesc) * kMaxSlots * kMaxLevels, hipHostMallocCoherent));
+    EECMG_HIP(hipHostGetDevicePointer((void**)&dv_desc_, (void*)h_desc_, 0));
     EECMG_HIP(hipHostMalloc((void**)&h_rec_, sizeof(LevelRecord) * kMaxSlots * kMaxLevels, hipHostMallocDefault));
-    EECMG_HIP(hipHostMalloc((void**)&h_taps_, kTapsSlotBytes * kMaxSlots, hipHostMallocDefault));
+    EECMG_HIP(hipHostMalloc((void**)&h_taps_, kTapsSlotBytes * kMaxSlots, hipHostMallocCoherent));
+    EECMG_HIP(hipHostGetDevicePointer((void**)&dv_taps_, (void*)h_taps_, 0));
     EECMG_HIP(hipHostMalloc((void**)&h_mirror_, sizeof(uint64_t) * kMaxSlots, hipHostMallocCoherent));
     std::memset((void*)h_mirror_, 0, sizeof(uint64_t) * kMaxSlots);
     EECMG_HIP(hipHostGetDevicePointer((void**)&d_mirror_, (void*)h_mirror_, 0));
@@ -649,13 +666,12 @@ class Engine {
         }
       }
     }
-    chk(hipMemcpyAsync(mem, tb, P.taps_bytes, hipMemcpyHostToDevice, stream_));
     if (P.own_gin) j->g_in_dev = mem + P.off_gin;
     if (P.own_uout) j->u_out_dev = mem + P.off_uout;
     alias_io(j);
     JobDesc* hd = h_desc_ + (size_t)slot * kMaxLevels;
     for (int l = 0; l < P.L; ++l) fill_desc(j, l, hd[l]);
-    chk(hipMemcpyAsync(d_desc_ + (size_t)slot * kMaxLevels, hd, sizeof(JobDesc) * P.L, hipMemcpyHostToDevice, stream_));
+    j->needs_upload = true;  // copied by the next step's k_upload
     return EECMG_OK;
   }
 
@@ -670,6 +686,7 @@ class Engine {
     std::vector<Job*> init_l;
     std::vector<std::pair<Job*, int>> iter_l;  // job, chunk
     std::vector<std::pair<Job*, int>> flush_l;  // job, level left with a possibly deferred update
+    std::vector<std::pair<Job*, int>> finb_l;   // job, level left with its last finalize still to run
     bool launched = false;
     for (int s = 0; s < kMaxSlots; ++s) {
       Job* j = slots_[s];
@@ -717,6 +734,10 @@ class Engine {
             // more pass, because its first pass only forms q = H r
             const int limit = j->plan.lv[j->cur_level()].cap + (j->plan.prm.smoother == EECMG_SMOOTHER_MR ? 1 : 0);
             if (j->cancelled || j->level_done_seen || j->issued >= limit) {
+              if (j->fin_b_pending) {
+                finb_l.push_back({j, j->cur_level()});
+                j->fin_b_pending = false;
+              }
               if (lazy_level(j, j->cur_level())) flush_l.push_back({j, j->cur_level()});
               if (!j->cancelled && j->oi + 1 < (int)j->plan.order.size()) {
                 j->oi += 1;
@@ -740,7 +761,7 @@ class Engine {
             break;
           }
           case Job::kWaitOut:
-            if (hipEventQuery(j->done_ev) == hipSuccess) {
+            if (hipEventQuery(j->done_ev->e) == hipSuccess) {
               finish(j);
               finished.push_back(j);
             }
@@ -749,7 +770,27 @@ class Engine {
         }
       }
     }
-    // launches, in dependency order
+    // launches, in dependency order; first the newly admitted jobs' tables:
+    // one job's by two copies, several jobs' by one upload kernel
+    {
+      UploadList ul;
+      ul.n = 0;
+      for (int s = 0; s < kMaxSlots; ++s)
+        if (slots_[s] && slots_[s]->needs_upload) {
+          slots_[s]->needs_upload = false;
+          ul.slot[ul.n++] = s;
+        }
+      if (ul.n == 1) {
+        const Job* j = slots_[ul.slot[0]];
+        const size_t so = (size_t)j->slot;
+        chk(hipMemcpyAsync(j->mem, h_taps_ + so * kTapsSlotBytes, j->plan.taps_bytes, hipMemcpyHostToDevice,
+                           stream_));
+        chk(hipMemcpyAsync(d_desc_ + so * kMaxLevels, h_desc_ + so * kMaxLevels, sizeof(JobDesc) * j->plan.L,
+                           hipMemcpyHostToDevice, stream_));
+      } else if (ul.n > 1) {
+        chk(launch_upload(ul, dv_desc_, d_desc_, dv_taps_, kTapsSlotBytes, stream_));
+      }
+    }
     if (!restrict_l.empty()) {
       for (Job* j : restrict_l)
         if (j->in_wait) {
@@ -768,6 +809,14 @@ class Engine {
           if ((int)j->plan.f64 == f64) js.push_back(j);
         if (!js.empty()) launch_group(kCoarse, js, 0, f64 != 0, 0, -1, -1);
       }
+      launched = true;
+    }
+    for (auto& x : finb_l) {
+      // the finalize of the level's last pass B (its records, stop reason and
+      // iteration count; a level that already stopped leaves it unchanged)
+      std::vector<Job*> one{x.first};
+      std::vector<int> lv{x.second};
+      launch_group(kCgFinB, one, -1, x.first->plan.f64, 0, -1, -1, nullptr, &lv);
       launched = true;
     }
     if (!flush_l.empty()) {
@@ -796,24 +845,45 @@ class Engine {
       issue_iterations(iter_l);
       launched = true;
     }
-    for (Job* j : out_l) {
-      std::vector<Job*> one{j};
-      if (!j->alias_out) launch_group(kOutCopy, one, j->plan.L - 1, j->plan.f64, 0, -1, -1);
-      chk(hipMemcpyAsync(h_rec_ + (size_t)j->slot * kMaxLevels, d_rec_ + (size_t)j->slot * kMaxLevels,
-                     sizeof(LevelRecord) * kMaxLevels, hipMemcpyDeviceToHost, stream_));
-      if (!j->done_ev) chk(hipEventCreateWithFlags(&j->done_ev, hipEventDisableTiming));
-      const size_t out_bytes = (size_t)j->plan.H * j->plan.W * j->plan.esz;
-      if (j->host_out && copy_) {
-        if (!j->comp_ev) chk(hipEventCreateWithFlags(&j->comp_ev, hipEventDisableTiming));
-        chk(hipEventRecord(j->comp_ev, stream_));
-        chk(hipStreamWaitEvent(copy_, j->comp_ev, 0));
-        chk(hipMemcpyAsync(j->host_out, j->u_out_dev, out_bytes, hipMemcpyDeviceToHost, copy_));
-        chk(hipEventRecord(j->done_ev, copy_));
-      } else {
-        if (j->host_out) chk(hipMemcpyAsync(j->host_out, j->u_out_dev, out_bytes, hipMemcpyDeviceToHost, stream_));
-        chk(hipEventRecord(j->done_ev, stream_));
+    if (!out_l.empty()) {
+      // outputs of every job finishing in this step: one copy launch per
+      // precision, one read-back of the level records, one shared event
+      // (served requests copy their results on the copy stream instead)
+      int lo = kMaxSlots, hi = -1;
+      for (int f64 = 0; f64 < 2; ++f64) {
+        std::vector<Job*> js;
+        std::vector<int> lv;
+        for (Job* j : out_l)
+          if ((int)j->plan.f64 == f64 && !j->alias_out) {
+            js.push_back(j);
+            lv.push_back(j->plan.L - 1);
+          }
+        if (!js.empty()) launch_group(kOutCopy, js, -1, f64 != 0, 0, -1, -1, nullptr, &lv);
       }
-      j->phase = Job::kWaitOut;
+      for (Job* j : out_l) {
+        lo = std::min(lo, j->slot);
+        hi = std::max(hi, j->slot);
+      }
+      chk(hipMemcpyAsync(h_rec_ + (size_t)lo * kMaxLevels, d_rec_ + (size_t)lo * kMaxLevels,
+                         sizeof(LevelRecord) * kMaxLevels * (size_t)(hi - lo + 1), hipMemcpyDeviceToHost, stream_));
+      std::shared_ptr<HipEvent> shared;
+      for (Job* j : out_l) {
+        const size_t out_bytes = (size_t)j->plan.H * j->plan.W * j->plan.esz;
+        if (j->host_out && copy_) {
+          if (!j->comp_ev) chk(hipEventCreateWithFlags(&j->comp_ev, hipEventDisableTiming));
+          chk(hipEventRecord(j->comp_ev, stream_));
+          chk(hipStreamWaitEvent(copy_, j->comp_ev, 0));
+          chk(hipMemcpyAsync(j->host_out, j->u_out_dev, out_bytes, hipMemcpyDeviceToHost, copy_));
+          j->done_ev = std::make_shared<HipEvent>();
+          chk(hipEventRecord(j->done_ev->e, copy_));
+        } else {
+          if (j->host_out) chk(hipMemcpyAsync(j->host_out, j->u_out_dev, out_bytes, hipMemcpyDeviceToHost, stream_));
+          if (!shared) shared = std::make_shared<HipEvent>();
+          j->done_ev = shared;
+        }
+        j->phase = Job::kWaitOut;
+      }
+      if (shared) chk(hipEventRecord(shared->e, stream_));
       launched = true;
     }
     if (launched) {
@@ -831,7 +901,7 @@ class Engine {
     for (long spin = 0;; ++spin) {
       if (snapshot() != before) return;
       for (Job* j : slots_)
-        if (j && j->phase == Job::kWaitOut && hipEventQuery(j->done_ev) == hipSuccess) return;
+        if (j && j->phase == Job::kWaitOut && hipEventQuery(j->done_ev->e) == hipSuccess) return;
       if (!step_pending_ || hipEventQuery(step_ev_[step_cur_]) == hipSuccess) {
         step_pending_ = false;
         return;
@@ -849,7 +919,8 @@ class Engine {
     if (j->mem) arena_.free(j->mem, j->plan.bytes);
     j->mem = nullptr;
     j->slot = -1;
-    for (hipEvent_t* e : {&j->done_ev, &j->in_ev, &j->comp_ev}) {
+    j->done_ev.reset();
+    for (hipEvent_t* e : {&j->in_ev, &j->comp_ev}) {
       if (*e) (void)hipEventDestroy(*e);
       *e = nullptr;
     }
@@ -955,6 +1026,7 @@ class Engine {
     d.pstride = P.max_tiles;
     d.mirror = d_mirror_ + j->slot;
     d.tag = level_tag(j, l);
+    d.taps_bytes = (int32_t)P.taps_bytes;
     if (l >= 1) {
       d.uB = u_at(l - 1);
       d.hB = P.lv[l - 1].h;
@@ -998,6 +1070,7 @@ class Engine {
     ll.n = 0;
     ll.total = 0;
     ll.flags = flags;
+    ll.k0 = kidx && !kidx->empty() ? (*kidx)[0] : 0;
     auto level_of = [&](size_t i) { return levels ? (*levels)[i] : level >= 0 ? level : jobs[i]->cur_level(); };
     for (size_t i = 0; i < jobs.size(); ++i) {
       Job* j = jobs[i];
@@ -1113,15 +1186,34 @@ class Engine {
         const int rc = kv.first.second % 100000;
         const std::vector<int>* ki = &kidx[kv.first];
         if (kv.first.first == EECMG_SMOOTHER_CGLS) {
-          launch_group(kCgA, kv.second, -1, f64, rc, -1, -1, ki);
-          // fold pass A's finalize into pass B when the launch is small: each
+          // pass A: a job whose previous pass B went without a finalize runs
+          // alone and evaluates that finalize itself (kLaunchFoldB)
+          std::vector<Job*> rest;
+          std::vector<int> rest_k;
+          for (size_t i = 0; i < kv.second.size(); ++i) {
+            Job* j = kv.second[i];
+            if (j->fin_b_pending) {
+              std::vector<Job*> one{j};
+              std::vector<int> k1{(*ki)[i]};
+              launch_group(kCgA, one, -1, f64, rc, -1, -1, &k1, nullptr, kLaunchFoldB);
+              j->fin_b_pending = false;
+            } else {
+              rest.push_back(j);
+              rest_k.push_back((*ki)[i]);
+            }
+          }
+          if (!rest.empty()) launch_group(kCgA, rest, -1, f64, rc, -1, -1, &rest_k);
+          // fold the finalizes into the passes when the launch is small: each
           // block then repeats the sum, which pays off only while a separate
           // launch costs more than that (a launch shared by many jobs does not)
           bool fold = (int)kv.second.size() <= kFoldMaxJobs;
           for (Job* j : kv.second) fold = fold && j->plan.lv[j->cur_level()].fold_a;
           if (!fold) launch_fin(kCgFinA, kv.second);
           launch_group(kCgB, kv.second, -1, f64, rc, -1, -1, ki, nullptr, fold ? kLaunchFoldA : 0);
-          launch_fin(kCgFinB, kv.second);
+          if (fold)
+            for (Job* j : kv.second) j->fin_b_pending = true;  // the next pass A, or the level end, runs it
+          else
+            launch_fin(kCgFinB, kv.second);
         } else {
           launch_group(kMrPass, kv.second, -1, f64, rc, -1, -1, ki);
           launch_fin(kMrFin, kv.second);
@@ -1161,6 +1253,8 @@ class Engine {
   LevelRecord* d_rec_ = nullptr;
   LevelRecord* h_rec_ = nullptr;
   char* h_taps_ = nullptr;
+  const JobDesc* dv_desc_ = nullptr;  // device view of h_desc_
+  const char* dv_taps_ = nullptr;     // device view of h_taps_
   volatile uint64_t* h_mirror_ = nullptr;
   uint64_t* d_mirror_ = nullptr;
   hipEvent_t step_ev_[kStepEvents] = {};
