@@ -164,7 +164,7 @@ struct ConvGeneral {
   static_assert(TH_ % 4 == 0, "four waves share the tile rows");
   static constexpr int KV = TH_ / 4;
   static constexpr int NT = 256, TW = kTW, TH = TH_, LW = kTW + 2 * RMAX, LH = TH_ + 2 * RMAX, RC = RMAX;
-  static constexpr bool kRuntimeR = true, kStream = false;
+  static constexpr bool kRuntimeR = true, kStream = false, kVSym = false;
   static constexpr int kWavesPerEU = 1;
   template <typename Emit>
   __device__ static __forceinline__ void conv(const T* __restrict__ tile, const T* __restrict__ taps, int R, int wave,
@@ -239,6 +239,7 @@ struct ConvSep {
   using S = Slide<R>;
   static constexpr int NT = 64, TW = kTW, TH = strip_th(R), LW = kTW + 2 * R, RC = R;
   static constexpr bool kRuntimeR = false, kStream = true;
+  static constexpr bool kVSym = false;  // the column filter need not be symmetric
   // streaming kernels hide memory latency with waves: ask the register
   // allocator for at least this many per SIMD where the state fits (it
   // otherwise trades occupancy for instruction-level parallelism)
@@ -296,6 +297,7 @@ struct ConvSym {
   using S = Slide<R>;
   static constexpr int NT = 64, TW = kTW, TH = strip_th(R), LW = kTW + 2 * R, RC = R;
   static constexpr bool kRuntimeR = false, kStream = true;
+  static constexpr bool kVSym = true;  // symmetric in the vertical direction: strips may walk up
   // streaming kernels hide memory latency with waves: ask the register
   // allocator for at least this many per SIMD where the state fits (it
   // otherwise trades occupancy for instruction-level parallelism)
@@ -346,6 +348,7 @@ struct ConvBox {
   using S = Slide<R>;
   static constexpr int NT = 64, TW = kTW, TH = strip_th(R), LW = kTW + 2 * R, RC = R;
   static constexpr bool kRuntimeR = false, kStream = true;
+  static constexpr bool kVSym = true;  // symmetric in the vertical direction: strips may walk up
   // streaming kernels hide memory latency with waves: ask the register
   // allocator for at least this many per SIMD where the state fits (it
   // otherwise trades occupancy for instruction-level parallelism)
@@ -452,6 +455,16 @@ __device__ __forceinline__ void tile_interior(const T* __restrict__ tile, const 
   }
 }
 
+// Strips of odd tile rows walk bottom-up when the policy allows it (see
+// stream_strip).
+template <typename P>
+__device__ __forceinline__ bool strip_up(const TileGeo& g) {
+  if constexpr (P::kStream && P::kVSym)
+    return ((g.y0 / P::TH) & 1) != 0;
+  else
+    return false;
+}
+
 template <typename P>
 __device__ __forceinline__ int pol_R(const TileGeo& g) {
   return P::kRuntimeR ? g.R : (P::LW - P::TW) / 2;
@@ -493,9 +506,13 @@ constexpr int kPrefetch = 2;
 // Loads at none return 0 (combine(0) must be 0, the zero boundary), and
 // interior/emit receive none as the offset of pixels outside the image, so
 // their stores are dropped; `in` tells the callbacks which pixels count.
+// up: walk the strip bottom-up (policies symmetric in the vertical
+// direction only).  Strips of odd tile rows do, so two vertically adjacent
+// strips reach the rows their halos share at the same time and the second
+// read of those rows finds them in L2.
 template <typename T, typename P, typename InF, typename CombF, typename IntLoadF, typename IntF, typename EmLoadF,
           typename EmF>
-__device__ __forceinline__ void stream_strip(const TileGeo& g, unsigned none, typename P::St& st, InF load_in,
+__device__ __forceinline__ void stream_strip(const TileGeo& g, bool up, unsigned none, typename P::St& st, InF load_in,
                                              CombF combine, IntLoadF load_int, IntF interior, EmLoadF load_em,
                                              EmF emit) {
   constexpr int R = P::RC, NW = 2 * R + 1, GS = strip_group(R), TH = P::TH, LH = TH + 2 * R, NG = LH / GS;
@@ -520,16 +537,20 @@ __device__ __forceinline__ void stream_strip(const TileGeo& g, unsigned none, ty
   VN pn[GS];
   VE pe[GS];
   T cen[NW];
-  // Row offsets are uniform; a row outside the image (or past the strip)
-  // maps every lane to none.
+  // image row of step t, and of the output completed at step t (R steps
+  // behind); rows are uniform, and a row outside the image (or past the
+  // strip) maps every lane to none
+  const int ybase = up ? g.y0 + TH + R - 1 : g.y0 - R, ystep = up ? -1 : 1;
+  auto row_at = [&](int t) { return ybase + ystep * t; };
+  auto out_at = [&](int t) { return ybase + ystep * (t - R); };
   auto issue = [&](int t, VI& a, VI& b, VN& n, VE& e) {
-    const int y = g.y0 - R + t;
+    const int y = row_at(t);
     const bool row_ok = t < LH && y >= 0 && y < g.h;
     const unsigned base = (unsigned)(y * g.pitch);
     a = load_in((row_ok && in1) ? base + (unsigned)c1 : none);
     b = load_in((row_ok && in2) ? base + (unsigned)c2 : none);
     n = load_int((row_ok && t >= R && t < R + TH && inic) ? base + (unsigned)ic : none);
-    const int yo = y - R;
+    const int yo = out_at(t);
     const bool emit_ok = t >= 2 * R && t < LH && yo < g.h;
     e = load_em((emit_ok && inec) ? (unsigned)(yo * g.pitch + ec) : none);
   };
@@ -544,7 +565,7 @@ __device__ __forceinline__ void stream_strip(const TileGeo& g, unsigned none, ty
       const VN n = pn[kg];
       const VE e = pe[kg];
       issue(t + D, pa[(kg + D) % GS], pb[(kg + D) % GS], pn[(kg + D) % GS], pe[(kg + D) % GS]);
-      const int y = g.y0 - R + t;
+      const int y = row_at(t);
       const T v1 = combine(a);
       const T v2 = combine(b);
       T* rb = rowbuf + (t & 1) * RW;
@@ -561,7 +582,7 @@ __device__ __forceinline__ void stream_strip(const TileGeo& g, unsigned none, ty
       cen[k] = row[0];
       const T out = P::step(st, row, k);
       {
-        const int yo = g.y0 + t - 2 * R;
+        const int yo = out_at(t);
         const bool in = t >= 2 * R && yo < g.h && inec;
         emit(in ? (unsigned)(yo * g.pitch + ec) : none, out, in, cen[((k - R) % NW + NW) % NW], e);
       }
@@ -794,7 +815,7 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
     const unsigned n = (unsigned)(g.h * g.pitch);
     const auto U = bview<T>(d.u, n), G = bview<T>(d.g, n), Rn = bview<T>(d.r[0], n);
     stream_strip<T, P>(
-        g, n, st, [&](unsigned o) { return U.ld(o); }, [](T v) { return v; }, NoLoadF{}, NoInterior{},
+        g, strip_up<P>(g), n, st, [&](unsigned o) { return U.ld(o); }, [](T v) { return v; }, NoLoadF{}, NoInterior{},
         [&](unsigned o) { return G.ld(o); },
         [&](unsigned o, T acc, bool in, T, T gv) {
           const T rv = gv - acc;
@@ -841,7 +862,7 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
     const unsigned n = (unsigned)(g.h * g.pitch);
     const auto Rr = bview<T>(d.r[0], n), S = bview<T>(d.s, n);
     stream_strip<T, P>(
-        g, n, st, [&](unsigned o) { return Rr.ld(o); }, [](T v) { return v; }, NoLoadF{}, NoInterior{}, NoLoadF{},
+        g, strip_up<P>(g), n, st, [&](unsigned o) { return Rr.ld(o); }, [](T v) { return v; }, NoLoadF{}, NoInterior{}, NoLoadF{},
         [&](unsigned o, T acc, bool in, T, NoLoad) {
           S.st(o, acc);
           part[0] += in ? (double)acc * (double)acc : 0.0;
@@ -902,7 +923,7 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
     const auto S = bview<T>(d.s, n), Po = bview<T>(d.p[par], first ? 0u : n), Pn = bview<T>(d.p[par ^ 1], n);
     const auto Q = bview<T>(d.q[0], n);
     stream_strip<T, P>(
-        g, n, ps, [&](unsigned o) { return Two<T>{S.ld(o), Po.ld(o)}; }, comb, NoLoadF{},
+        g, strip_up<P>(g), n, ps, [&](unsigned o) { return Two<T>{S.ld(o), Po.ld(o)}; }, comb, NoLoadF{},
         [&](unsigned o, T v, bool, NoLoad) { Pn.st(o, v); }, NoLoadF{},
         [&](unsigned o, T acc, bool in, T, NoLoad) {
           Q.st(o, acc);
@@ -964,7 +985,7 @@ __device__ __forceinline__ void cg_b_body(const JobDesc& d, const TileGeo& g, in
     auto ld_in = [&](unsigned o) { return Two<T>{Ro.ld(o), Q.ld(o)}; };
     if constexpr (UM == kUDefer) {
       stream_strip<T, P>(
-          g, n, ps, ld_in, comb, NoLoadF{},
+          g, strip_up<P>(g), n, ps, ld_in, comb, NoLoadF{},
           [&](unsigned o, T v, bool in, NoLoad) {
             Rn.st(o, v);
             part[0] += in ? (double)v * (double)v : 0.0;
@@ -972,7 +993,7 @@ __device__ __forceinline__ void cg_b_body(const JobDesc& d, const TileGeo& g, in
           NoLoadF{}, emit);
     } else if constexpr (UM == kUTwo) {
       stream_strip<T, P>(
-          g, n, ps, ld_in, comb, [&](unsigned o) { return Three<T>{U.ld(o), Pn.ld(o), Po.ld(o)}; },
+          g, strip_up<P>(g), n, ps, ld_in, comb, [&](unsigned o) { return Three<T>{U.ld(o), Pn.ld(o), Po.ld(o)}; },
           [&](unsigned o, T v, bool in, Three<T> x) {
             Rn.st(o, v);
             U.st(o, fma(alpha, x.b, fma(alpha_prev, x.c, x.a)));
@@ -981,7 +1002,7 @@ __device__ __forceinline__ void cg_b_body(const JobDesc& d, const TileGeo& g, in
           NoLoadF{}, emit);
     } else {
       stream_strip<T, P>(
-          g, n, ps, ld_in, comb, [&](unsigned o) { return Two<T>{U.ld(o), Pn.ld(o)}; },
+          g, strip_up<P>(g), n, ps, ld_in, comb, [&](unsigned o) { return Two<T>{U.ld(o), Pn.ld(o)}; },
           [&](unsigned o, T v, bool in, Two<T> x) {
             Rn.st(o, v);
             U.st(o, fma(alpha, x.b, x.a));
@@ -1085,7 +1106,7 @@ __global__ __launch_bounds__(P::NT) void k_mr_pass(LaunchList ll, const JobDesc*
     };
     if (pending) {
       stream_strip<T, P>(
-          g, n, ps, [&](unsigned o) { return Two<T>{Ro.ld(o), Qo.ld(o)}; },
+          g, strip_up<P>(g), n, ps, [&](unsigned o) { return Two<T>{Ro.ld(o), Qo.ld(o)}; },
           [&](Two<T> x) { return fma(-alpha, x.b, x.a); }, [&](unsigned o) { return Two<T>{U.ld(o), Ro.ld(o)}; },
           [&](unsigned o, T v, bool in, Two<T> x) {
             Rn.st(o, v);
@@ -1095,7 +1116,7 @@ __global__ __launch_bounds__(P::NT) void k_mr_pass(LaunchList ll, const JobDesc*
           NoLoadF{}, emit);
     } else {
       stream_strip<T, P>(
-          g, n, ps, [&](unsigned o) { return Ro.ld(o); }, [](T v) { return v; }, NoLoadF{},
+          g, strip_up<P>(g), n, ps, [&](unsigned o) { return Ro.ld(o); }, [](T v) { return v; }, NoLoadF{},
           [&](unsigned o, T v, bool in, NoLoad) {
             Rn.st(o, v);
             part[1] += in ? (double)v * (double)v : 0.0;
@@ -1155,7 +1176,7 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
     const unsigned n = (unsigned)(H * W);
     const auto X = bview<T>(x, n), Y = bview<T>(y, n);
     stream_strip<T, P>(
-        g, n, st, [&](unsigned o) { return X.ld(o); }, [](T v) { return v; }, NoLoadF{}, NoInterior{}, NoLoadF{},
+        g, strip_up<P>(g), n, st, [&](unsigned o) { return X.ld(o); }, [](T v) { return v; }, NoLoadF{}, NoInterior{}, NoLoadF{},
         [&](unsigned o, T acc, bool, T, NoLoad) { Y.st(o, acc); });
   } else {
     __shared__ T tile[P::LH * P::LW];

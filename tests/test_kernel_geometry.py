@@ -5,7 +5,10 @@ buffer).  Checks, for every radius the library instantiates, that the strip
 height fills whole row groups, that each emitted output receives exactly the
 contributions a = R..-R in that order starting with an assignment, that no
 output or prefetch slot is reused while still pending, that every interior
-row is handled once, and that every LDS access lies inside the row buffer."""
+row is handled once, and that every LDS access lies inside the row buffer.
+Strips may also walk bottom-up: the row mapping then still visits every
+interior row once and completes every output row from the 2R + 1 input rows
+centred on it."""
 import pytest
 
 KTH, KTW, PREFETCH = 32, 64, 2
@@ -84,3 +87,21 @@ def _model(R):
 def test_streaming_scheme(R):
     emitted, TH = _model(R)
     assert emitted == list(range(TH))
+
+
+@pytest.mark.parametrize("R", [0, 1, 3, 6, 12])
+@pytest.mark.parametrize("up", [False, True])
+def test_strip_row_mapping(R, up):
+    """Mirror of stream_strip's row_at / out_at for both walking directions."""
+    TH = strip_th(R)
+    LH = TH + 2 * R
+    y0 = 5 * TH
+    ybase, ystep = (y0 + TH + R - 1, -1) if up else (y0 - R, 1)
+    row_at = lambda t: ybase + ystep * t
+    out_at = lambda t: ybase + ystep * (t - R)
+    assert sorted(row_at(t) for t in range(LH)) == list(range(y0 - R, y0 + TH + R))
+    assert sorted(row_at(t) for t in range(R, R + TH)) == list(range(y0, y0 + TH))
+    assert sorted(out_at(t) for t in range(2 * R, LH)) == list(range(y0, y0 + TH))
+    for t in range(2 * R, LH):
+        # the window of steps t - 2R .. t holds the rows out_at(t) - R .. out_at(t) + R
+        assert sorted(row_at(u) for u in range(t - 2 * R, t + 1)) == list(range(out_at(t) - R, out_at(t) + R + 1))
