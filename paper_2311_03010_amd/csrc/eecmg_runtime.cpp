@@ -41,6 +41,28 @@ static int fail(int code, const std::string& msg) {
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Host copy of a served request's image into or out of its pinned staging
+// buffer; large images are split over a few threads (one thread's memcpy
+// reaches only a fraction of the host's memory bandwidth).
+static void staging_copy(void* dst, const void* src, size_t bytes) {
+  constexpr size_t kChunk = (size_t)8 << 20;
+  constexpr int kMaxThreads = 8;
+  const int n = (int)std::min<size_t>(kMaxThreads, bytes / kChunk);
+  if (n < 2) {
+    std::memcpy(dst, src, bytes);
+    return;
+  }
+  const size_t part = align_up((bytes + n - 1) / n, 4096);
+  std::vector<std::thread> th;
+  for (int i = 1; i < n; ++i) {
+    const size_t o = part * (size_t)i;
+    if (o >= bytes) break;
+    th.emplace_back([=] { std::memcpy((char*)dst + o, (const char*)src + o, std::min(part, bytes - o)); });
+  }
+  std::memcpy(dst, src, std::min(part, bytes));
+  for (auto& t : th) t.join();
+}
+
 constexpr size_t kTapsSlotBytes = 32 << 10;  // pinned staging of one job's PSF pyramid
 
 // ---------------------------------------------------------------------------
@@ -1910,7 +1932,7 @@ int eecmg_submit(eecmg_ctx* C, const void* g_delta, int H, int W, const double* 
     C->pool.put(j->host_out, r->out_cls);
     return fail(EECMG_ENOMEM, "pinned host staging allocation failed");
   }
-  std::memcpy(j->host_in, g_delta, bytes);
+  staging_copy(j->host_in, g_delta, bytes);
   j->t_submit = now_s();
   std::lock_guard<std::mutex> lk(C->mu);
   if ((int)C->queue.size() >= C->cfg.max_queue) {
@@ -1928,19 +1950,29 @@ int eecmg_submit(eecmg_ctx* C, const void* g_delta, int H, int W, const double* 
 }
 
 static int collect(eecmg_ctx* C, uint64_t id, void* u_out, eecmg_stats* stats_out, bool block) {
-  std::unique_lock<std::mutex> lk(C->mu);
-  auto it = C->reqs.find(id);
-  if (it == C->reqs.end()) return fail(EECMG_ENOTFOUND, "unknown request id");
-  if (block) C->cv_done.wait(lk, [&] { return it->second->finished; });
-  Request* r = it->second.get();
-  if (!r->finished) return EECMG_PENDING;
+  // take a finished request out of the table under the lock; copy its result
+  // after releasing it, so the progress thread is never held up by the copy
+  std::unique_ptr<Request> r;
+  {
+    std::unique_lock<std::mutex> lk(C->mu);
+    auto done = [&] {
+      auto f = C->reqs.find(id);
+      return f == C->reqs.end() || f->second->finished;
+    };
+    if (C->reqs.find(id) == C->reqs.end()) return fail(EECMG_ENOTFOUND, "unknown request id");
+    if (block) C->cv_done.wait(lk, done);
+    auto it = C->reqs.find(id);
+    if (it == C->reqs.end()) return fail(EECMG_ENOTFOUND, "unknown request id");
+    if (!it->second->finished) return EECMG_PENDING;
+    r = std::move(it->second);
+    C->reqs.erase(it);
+  }
   Job* j = r->job.get();
   const int st = r->status;
-  if (st == EECMG_OK && u_out) std::memcpy(u_out, j->host_out, (size_t)j->plan.H * j->plan.W * j->plan.esz);
+  if (st == EECMG_OK && u_out) staging_copy(u_out, j->host_out, (size_t)j->plan.H * j->plan.W * j->plan.esz);
   if (stats_out) fill_stats(j, stats_out);
   C->pool.put(j->host_in, r->in_cls);
   C->pool.put(j->host_out, r->out_cls);
-  C->reqs.erase(it);
   if (st != EECMG_OK) return fail(st, st == EECMG_ECANCELED ? "request cancelled" : "request failed");
   return EECMG_OK;
 }
