@@ -258,8 +258,10 @@ int eecmg_op_pm_step_dev(const void* u_dev, void* out_dev, int H, int W, double 
  * H x W).  Stage ids: 1 CGLS init r, 2 CGLS init s, 4 CGLS pass A (q = H p),
  * 6 CGLS pass B (s = H^T r), 8 MR init, 10 MR pass, 12 extrapolation,
  * 13 quadratic interpolation, 14 linear prolongation, 15 smoothing S,
- * 16 denoising D, 18 fused prolongation + S (+ first D step).  Process-wide;
- * not meant for concurrent contexts.
+ * 16 denoising D, 18 fused prolongation + S (+ first D step), 20 coarse
+ * levels in one block per image, 22 CGLS pass B recomputing q = H p (FP32
+ * levels with a streaming blur kernel, where pass A stores no q).
+ * Process-wide; not meant for concurrent contexts.
  * ------------------------------------------------------------------------- */
 int eecmg_profile_enable(int enable, int min_blocks);
 int eecmg_profile_reset(void);

@@ -164,7 +164,7 @@ struct ConvGeneral {
   static_assert(TH_ % 4 == 0, "four waves share the tile rows");
   static constexpr int KV = TH_ / 4;
   static constexpr int NT = 256, TW = kTW, TH = TH_, LW = kTW + 2 * RMAX, LH = TH_ + 2 * RMAX, RC = RMAX;
-  static constexpr bool kRuntimeR = true, kStream = false, kVSym = false;
+  static constexpr bool kRuntimeR = true, kStream = false, kVSym = false, kDconv = false;
   static constexpr int kWavesPerEU = 1;
   template <typename Emit>
   __device__ static __forceinline__ void conv(const T* __restrict__ tile, const T* __restrict__ taps, int R, int wave,
@@ -240,6 +240,7 @@ struct ConvSep {
   static constexpr int NT = 64, TW = kTW, TH = strip_th(R), LW = kTW + 2 * R, RC = R;
   static constexpr bool kRuntimeR = false, kStream = true;
   static constexpr bool kVSym = false;  // the column filter need not be symmetric
+  static constexpr bool kDconv = false;  // two windows of 2 (2R + 1) taps would crowd the registers
   // streaming kernels hide memory latency with waves: ask the register
   // allocator for at least this many per SIMD where the state fits (it
   // otherwise trades occupancy for instruction-level parallelism)
@@ -298,6 +299,7 @@ struct ConvSym {
   static constexpr int NT = 64, TW = kTW, TH = strip_th(R), LW = kTW + 2 * R, RC = R;
   static constexpr bool kRuntimeR = false, kStream = true;
   static constexpr bool kVSym = true;  // symmetric in the vertical direction: strips may walk up
+  static constexpr bool kDconv = false;  // two quadrant windows would crowd the registers
   // streaming kernels hide memory latency with waves: ask the register
   // allocator for at least this many per SIMD where the state fits (it
   // otherwise trades occupancy for instruction-level parallelism)
@@ -349,6 +351,7 @@ struct ConvBox {
   static constexpr int NT = 64, TW = kTW, TH = strip_th(R), LW = kTW + 2 * R, RC = R;
   static constexpr bool kRuntimeR = false, kStream = true;
   static constexpr bool kVSym = true;  // symmetric in the vertical direction: strips may walk up
+  static constexpr bool kDconv = true;   // pass B may recompute q (k_cg_bd): the window state is small
   // streaming kernels hide memory latency with waves: ask the register
   // allocator for at least this many per SIMD where the state fits (it
   // otherwise trades occupancy for instruction-level parallelism)
@@ -779,10 +782,11 @@ __device__ inline void fin_mr(const JobDesc& d, SolverState* st, const double (&
 // round trip instead of two) and a level that has already stopped discards
 // the sums.
 template <int NV, typename F>
-__device__ __forceinline__ void finalize_block(const JobDesc& d, const int (&comp)[NV], bool skip_if_done, F fin) {
+__device__ __forceinline__ void finalize_block(const JobDesc& d, const int (&comp)[NV], bool skip_if_done, int ntiles,
+                                               F fin) {
   const int done = skip_if_done ? d.st->done : 0;
   double v[NV];
-  sum_partials<NV, 256>(d.partials, d.ntiles, d.pstride, comp, v);
+  sum_partials<NV, 256>(d.partials, ntiles, d.pstride, comp, v);
   if (threadIdx.x == 0 && !done) fin(d, v);
 }
 
@@ -899,7 +903,7 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
   T beta;
   if (foldb && k > 0) {
     double v[2];
-    sum_partials<2, P::NT>(d.partials, d.ntiles, d.pstride, kCompCgB, v);
+    sum_partials<2, P::NT>(d.partials, uni(d.dconv) ? uni(d.ntiles_b) : uni(d.ntiles), d.pstride, kCompCgB, v);
     const int reason = stop_reason(d, k, v[0], v[1], st->gamma0, !finite_d(v[0]) || !finite_d(v[1]));
     if (L.t == 0 && threadIdx.x == 0) fin_cg_b(d, d.st, v);
     if (reason != kStopNone) return;
@@ -921,7 +925,7 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
     P::init(ps, (const T*)d.taps);
     const unsigned n = (unsigned)(g.h * g.pitch);
     const auto S = bview<T>(d.s, n), Po = bview<T>(d.p[par], first ? 0u : n), Pn = bview<T>(d.p[par ^ 1], n);
-    const auto Q = bview<T>(d.q[0], n);
+    const auto Q = bview<T>(d.q[0], uni(d.dconv) ? 0u : n);  // pass B recomputes q (dconv): no store
     stream_strip<T, P>(
         g, strip_up<P>(g), n, ps, [&](unsigned o) { return Two<T>{S.ld(o), Po.ld(o)}; }, comb, NoLoadF{},
         [&](unsigned o, T v, bool, NoLoad) { Pn.st(o, v); }, NoLoadF{},
@@ -1038,6 +1042,106 @@ __device__ __forceinline__ void cg_b_body(const JobDesc& d, const TileGeo& g, in
   }
 }
 
+// Pass B on levels whose pass A does not store q (dconv): the strip
+// recomputes q = H p_k from p_k itself and then s = H^T r_new, two sliding
+// windows one after the other.  Lane l holds p_k at columns x0 - 2R + l (and
+// x0 + 64 - 2R + l for l < 2R), so the first window gives q at column
+// x0 - R + l for all 64 lanes; r_new = r - alpha q there (zero outside the
+// image: the operator's boundary condition for H^T), and the second window
+// gives s at the 64 - 2R columns x0 .. x0 + 63 - 2R (lanes R .. 63 - R),
+// which is the strip's output width.  Step t reads p row y0 - 2R + t; the
+// first window completes q row y0 - 3R + t; the second window consumes the
+// r_new row of the previous step (one barrier per step) and completes s row
+// y0 - 4R - 1 + t.  q is bit-identical to pass A's (same policy, same order
+// of rows) except where pass A walked its strip bottom-up.
+template <typename T, typename P, int UM>
+__device__ __forceinline__ void cg_b_dconv(const JobDesc& d, int tile, int par, T alpha, T alpha_prev,
+                                           double (&part)[2]) {
+  constexpr int R = P::RC, NW = 2 * R + 1, GS = strip_group(R), TH = strip_th2(R), TWB = strip_tw2(R);
+  constexpr int LH = TH + 4 * R + 1, NG = LH / GS;
+  static_assert(NG * GS == LH && GS % NW == 0, "strip height must fill whole row groups");
+  constexpr int D = GS < kPrefetch ? GS : kPrefetch;
+  constexpr int RWP = 2 * kTW, RWR = kTW + 2 * R;
+  __shared__ T rowp[2 * RWP];
+  __shared__ T rowr[2 * RWR];
+  const int h = uni(d.h), w = uni(d.w), pitch = uni(d.pitch);
+  const int tiles_x = uni(d.tiles_x_b);
+  const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+  const int y0 = ty * TH, x0 = tx * TWB;
+  const int lane = threadIdx.x & 63;
+  const unsigned n = (unsigned)(h * pitch), none = n;
+  const auto Pk = bview<T>(d.p[par ^ 1], n), Pk1 = bview<T>(d.p[par], n), Ro = bview<T>(d.r[par], n);
+  const auto Rn = bview<T>(d.r[par ^ 1], n), U = bview<T>(d.u, n), S = bview<T>(d.s, n);
+  typename P::St s1, s2;
+  P::init(s1, (const T*)d.taps);
+  P::init(s2, (const T*)d.taps_t);
+  const int cp1 = x0 - 2 * R + lane, cp2 = x0 + kTW - 2 * R + lane;
+  const bool inp1 = cp1 >= 0 && cp1 < w, inp2 = lane < 2 * R && cp2 < w;
+  const int cq = x0 - R + lane;
+  const bool inq = cq >= 0 && cq < w;
+  const bool outl = lane >= R && lane < kTW - R && inq;
+  T pa[GS], pb[GS], rr[GS];
+  Three<T> ex[GS];
+  auto issue = [&](int t, T& a, T& b, T& r, Three<T>& e) {
+    const int yp = y0 - 2 * R + t;
+    const bool pok = t < TH + 4 * R && yp >= 0 && yp < h;
+    a = Pk.ld((pok && inp1) ? (unsigned)(yp * pitch + cp1) : none);
+    b = Pk.ld((pok && inp2) ? (unsigned)(yp * pitch + cp2) : none);
+    const int yq = yp - R;
+    const bool qok = t >= 2 * R && t < TH + 4 * R && yq >= 0 && yq < h;
+    r = Ro.ld((qok && inq) ? (unsigned)(yq * pitch + cq) : none);
+    const int ys = yp - 2 * R - 1;
+    const unsigned os = (t >= 4 * R + 1 && t < LH && ys < h && outl) ? (unsigned)(ys * pitch + cq) : none;
+    if constexpr (UM == kUDefer) {
+      e = Three<T>{T(0), T(0), T(0)};
+    } else if constexpr (UM == kUTwo) {
+      e = Three<T>{U.ld(os), Pk.ld(os), Pk1.ld(os)};
+    } else {
+      e = Three<T>{U.ld(os), Pk.ld(os), T(0)};
+    }
+  };
+#pragma unroll
+  for (int t = 0; t < D; ++t) issue(t, pa[t], pb[t], rr[t], ex[t]);
+#pragma unroll 1
+  for (int gi = 0; gi < NG; ++gi) {
+#pragma unroll
+    for (int kg = 0; kg < GS; ++kg) {
+      const int t = gi * GS + kg, k1 = kg % NW, k2 = (kg + NW - 1) % NW;
+      const T a = pa[kg], b = pb[kg], r = rr[kg];
+      const Three<T> e = ex[kg];
+      issue(t + D, pa[(kg + D) % GS], pb[(kg + D) % GS], rr[(kg + D) % GS], ex[(kg + D) % GS]);
+      T* bp = rowp + (t & 1) * RWP;
+      bp[lane] = a;
+      bp[kTW + lane] = b;
+      __syncthreads();
+      // first window: q at column cq of row yq = y0 - 3R + t
+      const T q = P::step(s1, bp + lane + R, k1);
+      const int yq = y0 - 3 * R + t;
+      const bool qrow = t >= 2 * R && t < TH + 4 * R && yq >= 0 && yq < h;
+      const T rn = (qrow && inq) ? fma(-alpha, q, r) : T(0);
+      {
+        const bool own = outl && yq >= y0 && yq < y0 + TH && qrow;
+        Rn.st(own ? (unsigned)(yq * pitch + cq) : none, rn);
+        part[0] += own ? (double)rn * (double)rn : 0.0;
+      }
+      T* br = rowr + (t & 1) * RWR;
+      br[R + lane] = rn;
+      // second window: the r_new row written in the previous step
+      const T* brp = rowr + ((t + 1) & 1) * RWR;
+      const T sv = P::step(s2, brp + R + lane, k2);
+      {
+        const int ys = y0 - 4 * R - 1 + t;
+        const bool own = outl && t >= 4 * R + 1 && ys < h;
+        const unsigned o = own ? (unsigned)(ys * pitch + cq) : none;
+        S.st(o, sv);
+        part[1] += own ? (double)sv * (double)sv : 0.0;
+        if constexpr (UM == kUTwo) U.st(o, fma(alpha, e.b, fma(alpha_prev, e.c, e.a)));
+        else if constexpr (UM == kUOne) U.st(o, fma(alpha, e.b, e.a));
+      }
+    }
+  }
+}
+
 template <typename T, typename P>
 __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWavesPerEU))) void k_cg_b(LaunchList ll, const JobDesc* __restrict__ descs) {
   const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
@@ -1072,6 +1176,28 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
     cg_b_body<T, P, kUTwo>(d, g, par, alpha, (T)st->alph[(k - 1) & 1], part);
   else
     cg_b_body<T, P, kUOne>(d, g, par, alpha, T(0), part);
+  block_sum_store<P::NT, 2>(part, d.partials + (size_t)1 * d.pstride + L.t, d.pstride);
+}
+
+// Pass B of the levels whose pass A stores no q (see cg_b_dconv): a kernel of
+// its own, so the register budget of the plain pass B is not affected.
+template <typename T, typename P>
+__global__ __launch_bounds__(P::NT) void k_cg_bd(LaunchList ll, const JobDesc* __restrict__ descs) {
+  const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
+  const JobDesc& d = descs[L.d];
+  const SolverState* st = d.st;
+  if (__builtin_amdgcn_readfirstlane(st->done)) return;
+  const int par = uni(st->par);
+  const int k = uni(st->k);
+  const T alpha = (T)st->alph[k & 1];
+  const int um = uni(d.lazy_u) == 0 ? kUOne : ((k & 1) ? kUTwo : kUDefer);
+  double part[2] = {0.0, 0.0};
+  if (um == kUDefer)
+    cg_b_dconv<T, P, kUDefer>(d, L.t, par, alpha, T(0), part);
+  else if (um == kUTwo)
+    cg_b_dconv<T, P, kUTwo>(d, L.t, par, alpha, (T)st->alph[(k - 1) & 1], part);
+  else
+    cg_b_dconv<T, P, kUOne>(d, L.t, par, alpha, T(0), part);
   block_sum_store<P::NT, 2>(part, d.partials + (size_t)1 * d.pstride + L.t, d.pstride);
 }
 
@@ -1200,6 +1326,12 @@ hipError_t launch_policy(Stage st, const LaunchList& ll, const JobDesc* descs, h
     case kCgInit2: hipLaunchKernelGGL((k_cg_init2<T, P>), grid, block, 0, s, ll, descs); break;
     case kCgA: hipLaunchKernelGGL((k_cg_a<T, P>), grid, block, 0, s, ll, descs); break;
     case kCgB: hipLaunchKernelGGL((k_cg_b<T, P>), grid, block, 0, s, ll, descs); break;
+    case kCgBD:
+      if constexpr (P::kDconv) {
+        hipLaunchKernelGGL((k_cg_bd<T, P>), grid, block, 0, s, ll, descs);
+        break;
+      }
+      return hipErrorInvalidValue;
     case kMrPass: hipLaunchKernelGGL((k_mr_pass<T, P>), grid, block, 0, s, ll, descs); break;
     default: return hipErrorInvalidValue;
   }

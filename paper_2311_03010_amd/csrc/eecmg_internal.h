@@ -73,6 +73,9 @@ struct JobDesc {
   int32_t zero_u;         // bit l: level l's smoother starts from zero (no transfer into it)
   int32_t lazy_u;         // CGLS pass B updates u every second iteration (see k_cg_b)
   int32_t fold_a;         // CGLS pass B may compute alpha itself (when its launch says so)
+  // CGLS pass B recomputes q = H p itself (pass A does not store q) on its
+  // own strips of strip_th2 x strip_tw2 outputs
+  int32_t dconv, tiles_x_b, ntiles_b, pad3;
   double cdelta, eps2;
   SolverState* st;
   LevelRecord* rec;  // kMaxLevels records of this job
@@ -155,6 +158,7 @@ enum Stage : int32_t {
   kXfFusedSmall,    // the same with short tiles, for small levels
   kCoarse,          // the leading small levels of each job in one block per job
   kFlushU,          // apply a deferred CGLS solution update when a lazy_u level stops
+  kCgBD,            // CGLS pass B that recomputes q = H p (levels with dconv)
   kNumStages
 };
 
@@ -188,6 +192,12 @@ __host__ __device__ constexpr int strip_group(int R) {
 __host__ __device__ constexpr int strip_th(int R) {
   return strip_group(R) * ((kTH + 2 * R + strip_group(R) - 1) / strip_group(R)) - 2 * R;
 }
+// Strips of the double-convolution pass B: TH2 output rows of kTW - 2R
+// columns, walked in TH2 + 4R + 1 steps (whole row groups).
+__host__ __device__ constexpr int strip_th2(int R) {
+  return strip_group(R) * ((kTH + 4 * R + 1 + strip_group(R) - 1) / strip_group(R)) - 4 * R - 1;
+}
+__host__ __device__ constexpr int strip_tw2(int R) { return kTW - 2 * R; }
 __host__ __device__ constexpr int tile_h_for_variant(int variant) {
   return variant / 100 == kConvGeneral ? kTH : variant / 100 == kConvGenShort ? kTHShort : strip_th(variant % 100);
 }

@@ -12,27 +12,31 @@ namespace eecmg {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_fin_cg_init(LaunchList ll, const JobDesc* __restrict__ descs) {
   const JobDesc& d = descs[ll.job[blockIdx.x]];
-  finalize_block(d, kCompCgInit, false, [](const JobDesc& dd, const double(&v)[2]) { fin_cg_init(dd, dd.st, v); });
+  finalize_block(d, kCompCgInit, false, d.ntiles,
+                 [](const JobDesc& dd, const double(&v)[2]) { fin_cg_init(dd, dd.st, v); });
 }
 
 __global__ __launch_bounds__(256) void k_fin_cg_a(LaunchList ll, const JobDesc* __restrict__ descs) {
   const JobDesc& d = descs[ll.job[blockIdx.x]];
-  finalize_block(d, kCompCgA, true, [](const JobDesc& dd, const double(&v)[1]) { fin_cg_a(dd, dd.st, v); });
+  finalize_block(d, kCompCgA, true, d.ntiles, [](const JobDesc& dd, const double(&v)[1]) { fin_cg_a(dd, dd.st, v); });
 }
 
 __global__ __launch_bounds__(256) void k_fin_cg_b(LaunchList ll, const JobDesc* __restrict__ descs) {
   const JobDesc& d = descs[ll.job[blockIdx.x]];
-  finalize_block(d, kCompCgB, true, [](const JobDesc& dd, const double(&v)[2]) { fin_cg_b(dd, dd.st, v); });
+  // pass B's partials come from its own strips when it recomputes q
+  finalize_block(d, kCompCgB, true, d.dconv ? d.ntiles_b : d.ntiles,
+                 [](const JobDesc& dd, const double(&v)[2]) { fin_cg_b(dd, dd.st, v); });
 }
 
 __global__ __launch_bounds__(256) void k_fin_mr_init(LaunchList ll, const JobDesc* __restrict__ descs) {
   const JobDesc& d = descs[ll.job[blockIdx.x]];
-  finalize_block(d, kCompMrInit, false, [](const JobDesc& dd, const double(&v)[1]) { fin_mr_init(dd, dd.st, v); });
+  finalize_block(d, kCompMrInit, false, d.ntiles,
+                 [](const JobDesc& dd, const double(&v)[1]) { fin_mr_init(dd, dd.st, v); });
 }
 
 __global__ __launch_bounds__(256) void k_fin_mr(LaunchList ll, const JobDesc* __restrict__ descs) {
   const JobDesc& d = descs[ll.job[blockIdx.x]];
-  finalize_block(d, kCompMr, true, [](const JobDesc& dd, const double(&v)[3]) { fin_mr(dd, dd.st, v); });
+  finalize_block(d, kCompMr, true, d.ntiles, [](const JobDesc& dd, const double(&v)[3]) { fin_mr(dd, dd.st, v); });
 }
 
 // ---------------------------------------------------------------------------
@@ -1129,9 +1133,10 @@ int blocks_for_stage(Stage st, const JobDesc& d) {
     case kCgInit1:
     case kCgInit2:
     case kCgA:
-    case kCgB:
     case kMrInit:
     case kMrPass: return d.ntiles;
+    case kCgB: return d.ntiles;
+    case kCgBD: return d.ntiles_b;
     case kCgFinInit:
     case kCgFinA:
     case kCgFinB:

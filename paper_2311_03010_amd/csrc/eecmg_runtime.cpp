@@ -74,6 +74,8 @@ struct LevelPlan {
   int variant = 0;                    // blur-operator kernel family (ConvKind * 100 + R)
   bool lazy = false;                  // CGLS solution update every second iteration
   bool fold_a = false;                // CGLS pass B evaluates pass A's finalize itself
+  bool dconv = false;                 // CGLS pass B recomputes q = H p (pass A stores no q)
+  int tiles_x_b = 0, ntiles_b = 0;    // pass B's own strips when dconv
   std::vector<double> psf;            // (2 rad + 1)^2, FP64
   std::vector<double> taps, taps_t;   // the variant's tap layout for H and H^T
 };
@@ -118,6 +120,16 @@ static long lazy_min_pixels() {
 // EECMG_FOLD_MAX_TILES moves the limit (0 turns it off).
 constexpr long kFoldMaxTiles = 4096;
 constexpr int kFoldMaxJobs = 1;
+// FP32 CGLS levels with the uniform-disk streaming kernel can let pass B
+// recompute q = H p from p instead of pass A storing q: 8 bytes per pixel and
+// iteration less, but two chained windows per strip make pass B slower by
+// about what pass A saves on this hardware, so it is off unless
+// EECMG_DCONV=1.  FP64, and the separable and symmetric kernels, always keep
+// the stored q (two of their windows would crowd the registers).
+static bool dconv_enabled() {
+  const char* e = std::getenv("EECMG_DCONV");
+  return e && e[0] == '1';
+}
 static long fold_max_tiles() {
   const char* e = std::getenv("EECMG_FOLD_MAX_TILES");
   return e ? std::atol(e) : kFoldMaxTiles;
@@ -369,6 +381,14 @@ static int build_plan(int H, int W, const double* psf, int r, int L, const int* 
     const int kind = lp.variant / 100;
     lp.fold_a = l >= P.coarse && P.prm.smoother == EECMG_SMOOTHER_CGLS &&
                 (kind == kConvGeneral || kind == kConvGenShort) && lp.ntiles <= fold_max_tiles();
+    lp.dconv = l >= P.coarse && P.prm.smoother == EECMG_SMOOTHER_CGLS && !P.f64 && kind == kConvBoxDisk &&
+               dconv_enabled();
+    if (lp.dconv) {
+      const int R = lp.variant % 100;
+      lp.tiles_x_b = (lp.w + strip_tw2(R) - 1) / strip_tw2(R);
+      lp.ntiles_b = lp.tiles_x_b * ((lp.h + strip_th2(R) - 1) / strip_th2(R));
+      P.max_tiles = std::max(P.max_tiles, lp.ntiles_b);
+    }
     P.max_tiles = std::max(P.max_tiles, lp.ntiles);
     P.off_g[l] = take((size_t)lp.h * lp.pitch * P.esz);
     P.off_u[l] = take((size_t)lp.h * lp.pitch * P.esz);
@@ -525,7 +545,7 @@ static Profiler& profiler() {
 static bool profiled_stage(Stage st) {
   return st == kCgInit1 || st == kCgInit2 || st == kCgA || st == kCgB || st == kMrInit || st == kMrPass ||
          st == kXfExtrap || st == kXfQuad || st == kXfLinear || st == kXfSmooth || st == kXfPm || st == kXfFused ||
-         st == kXfFusedSmall || st == kCoarse;
+         st == kXfFusedSmall || st == kCoarse || st == kCgBD;
 }
 
 // ---------------------------------------------------------------------------
@@ -1038,6 +1058,9 @@ class Engine {
     d.coarse_levels = l == 0 ? P.coarse : 0;
     d.lazy_u = lazy_level(j, l) ? 1 : 0;
     d.fold_a = lp.fold_a ? 1 : 0;
+    d.dconv = lp.dconv ? 1 : 0;
+    d.tiles_x_b = lp.tiles_x_b;
+    d.ntiles_b = lp.ntiles_b;
     for (int k = 0; k < P.L; ++k)
       if (!needs_transfer(j, k)) d.zero_u |= 1 << k;
     d.cdelta = P.prm.c * P.prm.delta;
@@ -1231,7 +1254,8 @@ class Engine {
           bool fold = (int)kv.second.size() <= kFoldMaxJobs;
           for (Job* j : kv.second) fold = fold && j->plan.lv[j->cur_level()].fold_a;
           if (!fold) launch_fin(kCgFinA, kv.second);
-          launch_group(kCgB, kv.second, -1, f64, rc, -1, -1, ki, nullptr, fold ? kLaunchFoldA : 0);
+          const Stage sb = kv.second.front()->plan.lv[kv.second.front()->cur_level()].dconv ? kCgBD : kCgB;
+          launch_group(sb, kv.second, -1, f64, rc, -1, -1, ki, nullptr, fold ? kLaunchFoldA : 0);
           if (fold)
             for (Job* j : kv.second) j->fin_b_pending = true;  // the next pass A, or the level end, runs it
           else

@@ -377,7 +377,7 @@ def transfer_dev(ub, HC, WC, prolongation="quad", smooth_h=1.0, pm_steps=1, k=10
 # ------------------------------------------------------------ kernel timing
 STAGES = {"cg_init_r": 1, "cg_init_s": 2, "cg_pass_a": 4, "cg_pass_b": 6, "mr_init": 8, "mr_pass": 10,
           "extrapolate": 12, "prolong_quad": 13, "prolong_linear": 14, "local_smooth": 15, "pm_step": 16,
-          "transfer_fused": 18, "coarse": 20}
+          "transfer_fused": 18, "coarse": 20, "cg_pass_b_dconv": 22}
 
 
 def profile_enable(enable=True, min_blocks=0):

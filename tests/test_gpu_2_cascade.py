@@ -240,6 +240,35 @@ def test_folded_finalize_is_bitwise_identical(torch_cuda, monkeypatch, prec, laz
     assert res["fold"][3] == res["separate"][3]
 
 
+@pytest.mark.parametrize("H,W,caps", [(300, 263, None), (517, 389, [2, 3, 5, 7]), (130, 709, [3, 4, 6, 9])])
+def test_recomputed_q_pass_matches_stored_q(torch_cuda, monkeypatch, H, W, caps):
+    """FP32 levels with the uniform-disk kernel can run the pass B that
+    recomputes q = H p on its own (64 - 2R)-wide strips instead of reading the
+    q that pass A stored (EECMG_DCONV=1).  Both schedules agree to FP32
+    rounding (q is summed in another row order where pass A walks a strip
+    bottom-up), with identical iteration counts; sizes leave ragged strips on
+    both axes."""
+    t = torch_cuda
+    p = synth.workload(3, H=H, W=W, n_levels=4, n_shapes=30, n_textures=3)
+    g = t.from_numpy(p.g_delta.astype(np.float32)).to("cuda:0")
+    kw = dict(precision="f32", delta=p.delta)
+    if caps is not None:
+        kw["stop_rule"] = False
+    res = {}
+    for mode, env in (("dconv", "1"), ("stored", "0")):
+        monkeypatch.setenv("EECMG_DCONV", env)
+        u, st = eecmg.restore_dev(g, p.psf, 4, caps=caps, **kw)
+        u0 = t.zeros_like(g)
+        _, su = eecmg.smoother_dev(g, u0, p.psf, 6, precision="f32", delta=p.delta, stop_rule=False)
+        t.cuda.synchronize()
+        res[mode] = (u.cpu().numpy().astype(np.float64), st, u0.cpu().numpy().astype(np.float64), su)
+    a, b = res["dconv"], res["stored"]
+    assert a[1]["iters"] == b[1]["iters"] and a[1]["reason"] == b[1]["reason"]
+    assert _rel(a[0], b[0]) <= 1e-5
+    assert a[3]["iters"] == b[3]["iters"]
+    assert _rel(a[2], b[2]) <= 1e-5
+
+
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_in_place_finest_level_paths_agree(torch_cuda, prec):
     """Dense aligned buffers are used in place by the finest level; a
