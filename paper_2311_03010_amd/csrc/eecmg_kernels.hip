@@ -432,6 +432,51 @@ __device__ __forceinline__ XArgs make_xargs(const JobDesc& d, int src, int dst) 
   return x;
 }
 
+// Pi on the engine's levels, one 2 x 2 block of grid B per thread: the four
+// outputs (2a + i, 2b + j) share the corrections d(a..a+1, b..b+1), so each
+// is computed once instead of up to four times; every output is the same
+// expression as pi_value (bit-identical).
+template <typename T>
+__device__ __forceinline__ void pi_tile2(const XArgs& x, int t) {
+  const int HA = (x.hd + 1) / 2, WA = (x.wd + 1) / 2;
+  const int tiles_x = (WA + kXW - 1) / kXW;
+  const int ty = t / tiles_x, tx = t - ty * tiles_x;
+  const int b = tx * kXW + (threadIdx.x & 63);
+  if (b >= WA) return;
+  const T* uA = (const T*)x.s0;
+  const T* uB = (const T*)x.s1;
+  T* out = (T*)x.dst;
+  const PiD<T> D{uA, uB, x.h0, x.w0, x.p0, x.p1};
+  const int q = 2 * b;
+  const bool q1 = q + 1 < x.wd;
+  for (int k = 0; k < kXH / 4; ++k) {
+    const int a = ty * kXH + (threadIdx.x >> 6) * (kXH / 4) + k;
+    if (a >= HA) break;
+    const int p = 2 * a;
+    const bool p1 = p + 1 < x.hd;
+    // d beyond the virtual nodes is never needed: those outputs do not exist
+    const double d00 = D(a, b), d01 = q1 ? D(a, b + 1) : 0.0;
+    const double d10 = p1 ? D(a + 1, b) : 0.0, d11 = (p1 && q1) ? D(a + 1, b + 1) : 0.0;
+    const T* ub = uB + (size_t)p * x.p1 + q;
+    T* o = out + (size_t)p * x.pd + q;
+    o[0] = to_t<T>((double)ub[0] + d00 * 0.25);
+    if (q1) o[1] = to_t<T>((double)ub[1] + (d00 + d01) * 0.125);
+    if (p1) {
+      o[x.pd] = to_t<T>((double)ub[x.p1] + (d00 + d10) * 0.125);
+      if (q1) o[x.pd + 1] = to_t<T>((double)ub[x.p1 + 1] + (d00 + d10 + d01 + d11) * 0.0625);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_pi2_f32(LaunchList ll, const JobDesc* __restrict__ descs, int dst) {
+  const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
+  pi_tile2<float>(make_xargs<kXfExtrap>(descs[L.d], -1, dst), L.t);
+}
+__global__ __launch_bounds__(256) void k_pi2_f64(LaunchList ll, const JobDesc* __restrict__ descs, int dst) {
+  const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
+  pi_tile2<double>(make_xargs<kXfExtrap>(descs[L.d], -1, dst), L.t);
+}
+
 // Engine form: the job's descriptor supplies the grids and buffers.
 template <typename T, int OP>
 __global__ __launch_bounds__(256) void k_xfer(LaunchList ll, const JobDesc* __restrict__ descs, int src, int dst) {
@@ -1142,7 +1187,7 @@ int blocks_for_stage(Stage st, const JobDesc& d) {
     case kCgFinB:
     case kMrFinInit:
     case kMrFin: return 1;
-    case kXfExtrap: return tiles2(d.hB, d.wB, kXH, kXW);
+    case kXfExtrap: return tiles2((d.hB + 1) / 2, (d.wB + 1) / 2, kXH, kXW);  // 2 x 2 outputs per thread
     case kXfFused: return tiles2(d.h, d.w, kFY, kFX);
     case kXfFusedSmall: return tiles2(d.h, d.w, kFYSmall, kFX);
     case kFlushU: return tiles2(d.h, d.w, kXH, kXW);
@@ -1188,7 +1233,10 @@ static hipError_t launch_typed(Stage st, int variant, const LaunchList& ll, cons
     case kOutCopy: hipLaunchKernelGGL(k_out_copy<T>, grid, block, 0, s, ll, descs); return hipGetLastError();
     case kFlushU: hipLaunchKernelGGL(k_flush_u<T>, grid, block, 0, s, ll, descs); return hipGetLastError();
     case kXfExtrap:
-      hipLaunchKernelGGL((k_xfer<T, kXfExtrap>), grid, block, 0, s, ll, descs, src, dst);
+      if constexpr (sizeof(T) == 4)
+        hipLaunchKernelGGL(k_pi2_f32, grid, block, 0, s, ll, descs, dst);
+      else
+        hipLaunchKernelGGL(k_pi2_f64, grid, block, 0, s, ll, descs, dst);
       return hipGetLastError();
     case kXfQuad:
       hipLaunchKernelGGL((k_xfer<T, kXfQuad>), grid, block, 0, s, ll, descs, src, dst);
