@@ -324,8 +324,8 @@ def main():
         copy_probe()
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU design is described but not built", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); "
+              "sharding across GPUs is designed but not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
