@@ -602,45 +602,59 @@ __device__ __forceinline__ void stream_strip(const TileGeo& g, bool up, unsigned
 __device__ __forceinline__ bool finite_d(double x) { return isfinite(x); }
 
 // Fixed-order sum of selected components of the tile partials of one job,
-// returned to every thread of the NT-thread block.  Thread i sums tiles
-// i, i + NT, i + 2 NT, ... in that order, eight independent (coalesced)
-// loads at a time, then the thread sums are combined by a fixed tree.
+// returned to every thread of the NT-thread block.  The order is that of 256
+// threads whatever NT is (a 64-thread block plays four of them per thread),
+// so a finalize gives the same bits in every kernel that runs it: virtual
+// thread i adds tiles i, i + 256, i + 512, ... in that order to +0; each group
+// of 64 virtual threads is reduced by wave_sum and the four group sums are
+// added in order.  Eight loads per thread are in flight at a time.  (Partials
+// are sums that start at +0, so none is -0 and the +0 that pads a batch adds
+// nothing: the batching does not change a bit.)
 template <int NV, int NT>
 __device__ __forceinline__ void sum_partials(const double* __restrict__ part, int ntiles, int stride,
                                              const int (&comp)[NV], double (&out)[NV]) {
-  constexpr int NWV = NT / 64, B = 8;
-  double acc[NV];
+  constexpr int NTO = 256, V = NTO / NT, NWO = NTO / 64, B = 8 / V;
+  static_assert(NT % 64 == 0 && NTO % NT == 0 && 8 % V == 0, "block size must divide the canonical 256");
+  double acc[NV][V];
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     const double* __restrict__ c = part + (size_t)comp[i] * stride;
-    double a = 0.0;
-    for (int t = threadIdx.x; t < ntiles; t += B * NT) {
-      double v[B];
+    double a[V];
 #pragma unroll
-      for (int m = 0; m < B; ++m) v[m] = t + m * NT < ntiles ? c[t + m * NT] : 0.0;
+    for (int j = 0; j < V; ++j) a[j] = 0.0;
+    for (int t0 = (int)threadIdx.x; t0 < ntiles; t0 += B * NTO) {
+      double v[V][B];
 #pragma unroll
-      for (int m = 0; m < B; ++m) a += v[m];
+      for (int j = 0; j < V; ++j)
+#pragma unroll
+        for (int m = 0; m < B; ++m) {
+          const int t = t0 + j * NT + m * NTO;
+          v[j][m] = t < ntiles ? c[t] : 0.0;
+        }
+#pragma unroll
+      for (int j = 0; j < V; ++j)
+#pragma unroll
+        for (int m = 0; m < B; ++m) a[j] += v[j][m];
     }
-    acc[i] = wave_sum(a);
+#pragma unroll
+    for (int j = 0; j < V; ++j) acc[i][j] = wave_sum(a[j]);
   }
-  if constexpr (NWV == 1) {
+  // virtual thread threadIdx.x + j NT lies in group (threadIdx.x >> 6) + j NT / 64
+  __shared__ double red[NWO][NV];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) out[i] = acc[i];
-  } else {
-    __shared__ double red[NWV][NV];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) {
+    for (int i = 0; i < NV; ++i)
 #pragma unroll
-      for (int i = 0; i < NV; ++i) red[wave][i] = acc[i];
-    }
-    __syncthreads();
+      for (int j = 0; j < V; ++j) red[wave + j * (NT / 64)][i] = acc[i][j];
+  }
+  __syncthreads();
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      double v = red[0][i];
+  for (int i = 0; i < NV; ++i) {
+    double v = red[0][i];
 #pragma unroll
-      for (int w = 1; w < NWV; ++w) v += red[w][i];
-      out[i] = v;
-    }
+    for (int w = 1; w < NWO; ++w) v += red[w][i];
+    out[i] = v;
   }
 }
 

@@ -113,12 +113,15 @@ static long lazy_min_pixels() {
   const char* e = std::getenv("EECMG_LAZY_MIN_PIXELS");
   return e ? std::atol(e) : kLazyPixels;
 }
-// CGLS levels with the four-wave general blur kernels and at most this many
-// tiles let every block of pass B sum pass A's partials itself (the same
-// fixed order as the finalize kernel, so alpha is bit-identical), which saves
-// a launch per iteration on the small levels where launches dominate.
-// EECMG_FOLD_MAX_TILES moves the limit (0 turns it off).
+// CGLS levels with at most this many tiles let every block of pass B sum
+// pass A's partials itself, and every block of pass A the previous pass B's
+// (the same fixed order as the finalize kernel, so alpha and beta are
+// bit-identical), which saves two launches per iteration where launches
+// weigh most.  The one-wave streaming kernels read the partials with a
+// quarter of the threads, so their limit is lower.  EECMG_FOLD_MAX_TILES and
+// EECMG_FOLD_MAX_TILES_STREAM move the limits (0 turns folding off).
 constexpr long kFoldMaxTiles = 4096;
+constexpr long kFoldMaxTilesStream = 512;
 constexpr int kFoldMaxJobs = 1;
 // FP32 CGLS levels with the uniform-disk streaming kernel can let pass B
 // recompute q = H p from p instead of pass A storing q: 8 bytes per pixel and
@@ -133,6 +136,10 @@ static bool dconv_enabled() {
 static long fold_max_tiles() {
   const char* e = std::getenv("EECMG_FOLD_MAX_TILES");
   return e ? std::atol(e) : kFoldMaxTiles;
+}
+static long fold_max_tiles_stream() {
+  const char* e = std::getenv("EECMG_FOLD_MAX_TILES_STREAM");
+  return e ? std::atol(e) : kFoldMaxTilesStream;
 }
 static void choose_variant(LevelPlan& lp, bool f64, bool by_size) {
   const int R = lp.rad, n = 2 * R + 1;
@@ -379,10 +386,12 @@ static int build_plan(int H, int W, const double* psf, int r, int L, const int* 
     lp.tiles_x = (lp.w + kTW - 1) / kTW;
     lp.ntiles = lp.tiles_x * ((lp.h + th - 1) / th);
     const int kind = lp.variant / 100;
-    lp.fold_a = l >= P.coarse && P.prm.smoother == EECMG_SMOOTHER_CGLS &&
-                (kind == kConvGeneral || kind == kConvGenShort) && lp.ntiles <= fold_max_tiles();
+    const bool general = kind == kConvGeneral || kind == kConvGenShort;
     lp.dconv = l >= P.coarse && P.prm.smoother == EECMG_SMOOTHER_CGLS && !P.f64 && kind == kConvBoxDisk &&
                dconv_enabled();
+    // (the recomputed-q pass B takes alpha from a finalize launch)
+    lp.fold_a = l >= P.coarse && P.prm.smoother == EECMG_SMOOTHER_CGLS && !lp.dconv &&
+                lp.ntiles <= (general ? fold_max_tiles() : fold_max_tiles_stream());
     if (lp.dconv) {
       const int R = lp.variant % 100;
       lp.tiles_x_b = (lp.w + strip_tw2(R) - 1) / strip_tw2(R);

@@ -217,27 +217,36 @@ def test_lazy_solution_update_is_bitwise_identical(torch_cuda, monkeypatch, prec
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 @pytest.mark.parametrize("lazy", [False, True])
 def test_folded_finalize_is_bitwise_identical(torch_cuda, monkeypatch, prec, lazy):
-    """On small levels pass B evaluates pass A's finalize in every block (same
-    partials, same summation order) instead of a separate launch.  With the
-    fold on or off the cascade, its statistics and the one-level smoother
-    agree bit for bit, also combined with the every-second-iteration update."""
+    """On small levels pass B evaluates pass A's finalize in every block, and
+    pass A the previous pass B's (same partials, same summation order: the
+    one-wave streaming kernels play the finalize kernel's 256 threads)
+    instead of separate launches.  With the fold on or off the cascade (a
+    separable streaming finest level over general levels), its statistics and
+    the one-level smoother with a general, a uniform-disk and a symmetric
+    streaming PSF agree bit for bit, also combined with the
+    every-second-iteration update."""
     t = torch_cuda
     p = synth.workload(2, H=256, W=192, n_levels=5, n_shapes=40, precision=prec)
     g = t.from_numpy(p.g_delta.astype(_dt(prec))).to("cuda:0")
-    psf1 = synth.gaussian_psf(0.8, 1)
+    psfs = [synth.gaussian_psf(0.8, 1), synth.disk_psf(5), synth.gaussian_psf(1.5, 5)]
     monkeypatch.setenv("EECMG_LAZY_MIN_PIXELS", "1" if lazy else str(1 << 40))
     res = {}
     for mode, lim in (("fold", "4096"), ("separate", "0")):
         monkeypatch.setenv("EECMG_FOLD_MAX_TILES", lim)
+        monkeypatch.setenv("EECMG_FOLD_MAX_TILES_STREAM", lim)
         u, st = eecmg.restore_dev(g, p.psf, 5, precision=prec, delta=p.delta)
-        u0 = t.zeros_like(g)
-        _, su = eecmg.smoother_dev(g, u0, psf1, 7, precision=prec, delta=p.delta)
+        sm = []
+        for psf in psfs:
+            u0 = t.zeros_like(g)
+            _, su = eecmg.smoother_dev(g, u0, psf, 7, precision=prec, delta=p.delta)
+            sm.append((u0, su))
         t.cuda.synchronize()
-        res[mode] = (u.cpu().numpy(), st, u0.cpu().numpy(), su)
+        res[mode] = (u.cpu().numpy(), st, [(x.cpu().numpy(), y) for x, y in sm])
     np.testing.assert_array_equal(res["fold"][0], res["separate"][0])
     assert res["fold"][1] == res["separate"][1]
-    np.testing.assert_array_equal(res["fold"][2], res["separate"][2])
-    assert res["fold"][3] == res["separate"][3]
+    for (xa, ya), (xb, yb) in zip(res["fold"][2], res["separate"][2]):
+        np.testing.assert_array_equal(xa, xb)
+        assert ya == yb
 
 
 @pytest.mark.parametrize("H,W,caps", [(300, 263, None), (517, 389, [2, 3, 5, 7]), (130, 709, [3, 4, 6, 9])])
