@@ -345,9 +345,9 @@ def main():
         eecmg.restore_dev(g, p.psf, p.n_levels, out=out, **kw)
     torch.cuda.synchronize()
 
-    # finest-level launches only: every tile is at most 64 rows tall, and the
-    # next level has a quarter of the pixels
-    fine_tiles = ((W + 63) // 64) * ((H + 63) // 64)
+    # finest-level launches only: every smoother tile is at most 96 rows tall
+    # (tall strips included), and the next level has a quarter of the pixels
+    fine_tiles = ((W + 63) // 64) * ((H + 95) // 96)
     eecmg.profile_reset()
     eecmg.profile_enable(True, min_blocks=fine_tiles)
     _log(f"bench: timing {args.steps} steps")
@@ -398,7 +398,8 @@ def main():
         roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                     "copy_gbs": round(cbw, 1), "frac_vs_copy": round(ach / cbw, 4),
-                    "kernel": ("k_cg_bd" if dconv else "k_cg_b") + "<float, ConvBox<float, 6>> (finest level, 4096^2)",
+                    "kernel": ("k_cg_bd<float, ConvBox<float, 6>>" if dconv else "k_cg_b<float, ConvBox<float, 6, true>>")
+                    + " (finest level, 4096^2" + ("" if dconv else ", tall strips") + ")",
                     "avg_launch_us": round(rb["avg_us"], 2), "alg_bytes_per_launch": int(20 * H * W)}
     extra = {"kernels": kern, "iters_per_level": stats["iters"], "stop_reason": stats["reason"]}
 

@@ -189,8 +189,11 @@ constexpr int kTHShort = EECMG_SHORT_TH;
 __host__ __device__ constexpr int strip_group(int R) {
   return (2 * R + 1) * ((4 + 2 * R) / (2 * R + 1));
 }
-__host__ __device__ constexpr int strip_th(int R) {
-  return strip_group(R) * ((kTH + 2 * R + strip_group(R) - 1) / strip_group(R)) - 2 * R;
+// Tall strips (at least 2 kTH rows) serve large FP32 levels: half the halo
+// rows per output and half the strips in flight per XCD.
+constexpr int kTHTall = 2 * kTH;
+__host__ __device__ constexpr int strip_th(int R, bool tall = false) {
+  return strip_group(R) * (((tall ? kTHTall : kTH) + 2 * R + strip_group(R) - 1) / strip_group(R)) - 2 * R;
 }
 // Strips of the double-convolution pass B: TH2 output rows of kTW - 2R
 // columns, walked in TH2 + 4R + 1 steps (whole row groups).
@@ -198,8 +201,16 @@ __host__ __device__ constexpr int strip_th2(int R) {
   return strip_group(R) * ((kTH + 4 * R + 1 + strip_group(R) - 1) / strip_group(R)) - 4 * R - 1;
 }
 __host__ __device__ constexpr int strip_tw2(int R) { return kTW - 2 * R; }
+// A variant id is kind * 100 + R, plus kTallVariant for a streaming kind on
+// tall strips.
+constexpr int kTallVariant = 10000;
+__host__ __device__ constexpr int variant_kind(int variant) { return (variant % kTallVariant) / 100; }
+__host__ __device__ constexpr int variant_r(int variant) { return variant % 100; }
+__host__ __device__ constexpr bool variant_tall(int variant) { return variant >= kTallVariant; }
 __host__ __device__ constexpr int tile_h_for_variant(int variant) {
-  return variant / 100 == kConvGeneral ? kTH : variant / 100 == kConvGenShort ? kTHShort : strip_th(variant % 100);
+  return variant_kind(variant) == kConvGeneral    ? kTH
+         : variant_kind(variant) == kConvGenShort ? kTHShort
+                                                  : strip_th(variant_r(variant), variant_tall(variant));
 }
 
 // Host-side launchers (defined in eecmg_kernels.hip).

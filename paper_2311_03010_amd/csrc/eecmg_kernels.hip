@@ -1156,8 +1156,9 @@ __global__ __launch_bounds__(256) void k_op_restrict(const T* __restrict__ gf, i
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
-hipError_t sm_f32_sep(Stage st, int R, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
-hipError_t sm_f32_sym(Stage st, bool disk, int R, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
+hipError_t sm_f32_sep(Stage st, int R, bool tall, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
+hipError_t sm_f32_sym(Stage st, bool disk, int R, bool tall, const LaunchList& ll, const JobDesc* descs,
+                      hipStream_t s);
 hipError_t sm_f64_sep(Stage st, int R, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
 hipError_t sm_f64_sym(Stage st, bool disk, int R, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
 hipError_t sm_gen(Stage st, bool f64, int rclass, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
@@ -1167,7 +1168,7 @@ hipError_t opc_f32_sym(bool disk, const void* x, void* y, int H, int W, const vo
 hipError_t opc_f64_sep(const void* x, void* y, int H, int W, const void* taps, int R, hipStream_t s);
 hipError_t opc_f64_sym(bool disk, const void* x, void* y, int H, int W, const void* taps, int R, hipStream_t s);
 hipError_t opc_gen(bool f64, const void* x, void* y, int H, int W, const void* taps, int R, hipStream_t s);
-hipError_t sm_box(Stage st, bool f64, int R, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
+hipError_t sm_box(Stage st, bool f64, int R, bool tall, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
 hipError_t opc_box(bool f64, const void* x, void* y, int H, int W, const void* taps, int R, hipStream_t s);
 
 int rmax_class_for(int r) { return r <= 3 ? 3 : (r <= 6 ? 6 : 12); }
@@ -1201,15 +1202,18 @@ int blocks_for_stage(Stage st, const JobDesc& d) {
 
 static hipError_t launch_smoother(Stage st, bool f64, int variant, const LaunchList& ll, const JobDesc* descs,
                                   hipStream_t s) {
-  const int kind = variant / 100, R = variant % 100;
+  const int kind = variant_kind(variant), R = variant_r(variant);
+  const bool tall = variant_tall(variant);
+  if (tall && (f64 || kind == kConvGeneral || kind == kConvGenShort)) return hipErrorInvalidValue;
   switch (kind) {
     case kConvGeneral: return sm_gen(st, f64, R, ll, descs, s);
     case kConvGenShort: return sm_gen_short(st, f64, R, ll, descs, s);
-    case kConvSep: return f64 ? sm_f64_sep(st, R, ll, descs, s) : sm_f32_sep(st, R, ll, descs, s);
+    case kConvSep: return f64 ? sm_f64_sep(st, R, ll, descs, s) : sm_f32_sep(st, R, tall, ll, descs, s);
     case kConvSymSquare:
-      return f64 ? sm_f64_sym(st, false, R, ll, descs, s) : sm_f32_sym(st, false, R, ll, descs, s);
-    case kConvSymDisk: return f64 ? sm_f64_sym(st, true, R, ll, descs, s) : sm_f32_sym(st, true, R, ll, descs, s);
-    case kConvBoxDisk: return sm_box(st, f64, R, ll, descs, s);
+      return f64 ? sm_f64_sym(st, false, R, ll, descs, s) : sm_f32_sym(st, false, R, tall, ll, descs, s);
+    case kConvSymDisk:
+      return f64 ? sm_f64_sym(st, true, R, ll, descs, s) : sm_f32_sym(st, true, R, tall, ll, descs, s);
+    case kConvBoxDisk: return sm_box(st, f64, R, tall, ll, descs, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -133,6 +133,18 @@ static bool dconv_enabled() {
   const char* e = std::getenv("EECMG_DCONV");
   return e && e[0] == '1';
 }
+// Levels whose tall-strip tiles number at least this many (two waves per
+// SIMD of the 1024 on the chip) use tall strips; EECMG_TALL_MIN_TILES moves
+// the limit and EECMG_TALL_STRIPS=0 keeps every level on short strips.
+constexpr long kTallMinTiles = 2048;
+static bool tall_strips_enabled() {
+  const char* e = std::getenv("EECMG_TALL_STRIPS");
+  return !(e && e[0] == '0');
+}
+static long tall_min_tiles() {
+  const char* e = std::getenv("EECMG_TALL_MIN_TILES");
+  return e ? std::atol(e) : kTallMinTiles;
+}
 static long fold_max_tiles() {
   const char* e = std::getenv("EECMG_FOLD_MAX_TILES");
   return e ? std::atol(e) : kFoldMaxTiles;
@@ -382,18 +394,25 @@ static int build_plan(int H, int W, const double* psf, int r, int L, const int* 
     lp.pitch = (int)align_up((size_t)lp.w, pitch_elems);
     if ((size_t)lp.h * lp.pitch * P.esz >= ((size_t)1 << 32))
       return fail(EECMG_EINVAL, "a level array would exceed 4 GiB (32-bit offsets)");
-    const int th = tile_h_for_variant(lp.variant);
     lp.tiles_x = (lp.w + kTW - 1) / kTW;
-    lp.ntiles = lp.tiles_x * ((lp.h + th - 1) / th);
-    const int kind = lp.variant / 100;
+    const int kind = variant_kind(lp.variant);
     const bool general = kind == kConvGeneral || kind == kConvGenShort;
+    // FP32 streaming kernels walk tall strips on levels that still give the
+    // chip enough of them (the choice depends on the level's shape only, so
+    // an image gets the same kernels alone and in a batch)
+    if (!general && !P.f64 && tall_strips_enabled() &&
+        (long)lp.tiles_x * ((lp.h + strip_th(variant_r(lp.variant), true) - 1) / strip_th(variant_r(lp.variant), true)) >=
+            tall_min_tiles())
+      lp.variant += kTallVariant;
+    const int th = tile_h_for_variant(lp.variant);
+    lp.ntiles = lp.tiles_x * ((lp.h + th - 1) / th);
     lp.dconv = l >= P.coarse && P.prm.smoother == EECMG_SMOOTHER_CGLS && !P.f64 && kind == kConvBoxDisk &&
-               dconv_enabled();
+               !variant_tall(lp.variant) && dconv_enabled();
     // (the recomputed-q pass B takes alpha from a finalize launch)
     lp.fold_a = l >= P.coarse && P.prm.smoother == EECMG_SMOOTHER_CGLS && !lp.dconv &&
                 lp.ntiles <= (general ? fold_max_tiles() : fold_max_tiles_stream());
     if (lp.dconv) {
-      const int R = lp.variant % 100;
+      const int R = variant_r(lp.variant);
       lp.tiles_x_b = (lp.w + strip_tw2(R) - 1) / strip_tw2(R);
       lp.ntiles_b = lp.tiles_x_b * ((lp.h + strip_th2(R) - 1) / strip_th2(R));
       P.max_tiles = std::max(P.max_tiles, lp.ntiles_b);

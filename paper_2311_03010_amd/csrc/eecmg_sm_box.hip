@@ -1,15 +1,25 @@
 // Smoother kernels with the uniform-disk blur policy (psf(a,b) = w on
-// a^2 + b^2 <= R^2): FP32 for R = 1..8, FP64 for R = 1..6.
+// a^2 + b^2 <= R^2): FP32 for R = 1..8 (also on tall strips), FP64 for R = 1..6.
 #include "eecmg_device.h"
 
 namespace eecmg {
 
 #define EECMG_BOX_CASE(T, R) \
   case R: return launch_policy<T, ConvBox<T, R>>(st, ll, descs, s);
+#define EECMG_BOX_TALL(R) \
+  case R: return launch_policy<float, ConvBox<float, R, true>>(st, ll, descs, s);
 #define EECMG_BOX_OP(T, R) \
   case R: return launch_op_conv<T, ConvBox<T, R>>(x, y, H, W, taps, R, s);
 
-hipError_t sm_box(Stage st, bool f64, int R, const LaunchList& ll, const JobDesc* descs, hipStream_t s) {
+hipError_t sm_box(Stage st, bool f64, int R, bool tall, const LaunchList& ll, const JobDesc* descs, hipStream_t s) {
+  if (tall) {
+    if (f64) return hipErrorInvalidValue;
+    switch (R) {
+      EECMG_BOX_TALL(1) EECMG_BOX_TALL(2) EECMG_BOX_TALL(3) EECMG_BOX_TALL(4)
+      EECMG_BOX_TALL(5) EECMG_BOX_TALL(6) EECMG_BOX_TALL(7) EECMG_BOX_TALL(8)
+      default: return hipErrorInvalidValue;
+    }
+  }
   if (f64) {
     switch (R) {
       EECMG_BOX_CASE(double, 1) EECMG_BOX_CASE(double, 2) EECMG_BOX_CASE(double, 3)

@@ -1,15 +1,32 @@
 // FP32 smoother kernels with the doubly-symmetric blur policy: square support
-// R = 1..6, disk support R = 1..8.
+// R = 1..6, disk support R = 1..8, on short and on tall strips.
 #include "eecmg_device.h"
 
 namespace eecmg {
 
 #define EECMG_SYM_CASE(R, D) \
   case R: return launch_policy<float, ConvSym<float, R, D>>(st, ll, descs, s);
+#define EECMG_SYM_TALL(R, D) \
+  case R: return launch_policy<float, ConvSym<float, R, D, true>>(st, ll, descs, s);
 #define EECMG_SYM_OP(R, D) \
   case R: return launch_op_conv<float, ConvSym<float, R, D>>(x, y, H, W, taps, R, s);
 
-hipError_t sm_f32_sym(Stage st, bool disk, int R, const LaunchList& ll, const JobDesc* descs, hipStream_t s) {
+hipError_t sm_f32_sym(Stage st, bool disk, int R, bool tall, const LaunchList& ll, const JobDesc* descs,
+                      hipStream_t s) {
+  if (tall && disk) {
+    switch (R) {
+      EECMG_SYM_TALL(1, true) EECMG_SYM_TALL(2, true) EECMG_SYM_TALL(3, true) EECMG_SYM_TALL(4, true)
+      EECMG_SYM_TALL(5, true) EECMG_SYM_TALL(6, true) EECMG_SYM_TALL(7, true) EECMG_SYM_TALL(8, true)
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (tall) {
+    switch (R) {
+      EECMG_SYM_TALL(1, false) EECMG_SYM_TALL(2, false) EECMG_SYM_TALL(3, false) EECMG_SYM_TALL(4, false)
+      EECMG_SYM_TALL(5, false) EECMG_SYM_TALL(6, false)
+      default: return hipErrorInvalidValue;
+    }
+  }
   if (disk) {
     switch (R) {
       EECMG_SYM_CASE(1, true) EECMG_SYM_CASE(2, true) EECMG_SYM_CASE(3, true) EECMG_SYM_CASE(4, true)

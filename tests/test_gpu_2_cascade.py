@@ -71,6 +71,38 @@ def _symdisk(r):
     return w / w.sum()
 
 
+@pytest.mark.parametrize("psfname", ["disk6", "gauss5", "square4"])
+def test_tall_strip_smoother_parity(torch_cuda, monkeypatch, psfname):
+    """A 2200 x 4096 FP32 level is large enough for the streaming kernels'
+    tall strips (uniform-disk, separable and square symmetric PSFs): CGLS
+    from zero matches the oracle, and the short-strip kernels
+    (EECMG_TALL_STRIPS=0) to FP32 rounding (the partial sums are grouped by
+    other tiles)."""
+    H, W = 2200, 4096
+    rng = np.random.Generator(np.random.PCG64(H + len(psfname)))
+    psf = {"disk6": synth.disk_psf(6), "gauss5": synth.gaussian_psf(1.5, 5),
+           "square4": 0.5 * synth.gaussian_psf(1.5, 4) + 0.5 * synth.disk_psf(4)}[psfname]
+    u_true = synth.scene(H, W, 200, rng)
+    g = (synth.blur(u_true, psf) + rng.standard_normal((H, W))).astype(np.float32).astype(np.float64)
+    cap = 6
+    t = torch_cuda
+    gd = t.from_numpy(g.astype(np.float32)).to("cuda:0")
+    res = {}
+    for mode, env in (("tall", "1"), ("short", "0")):
+        monkeypatch.setenv("EECMG_TALL_STRIPS", env)
+        ud = t.zeros_like(gd)
+        u, st = eecmg.smoother_dev(gd, ud, psf, cap, precision="f32", stop_rule=False)
+        t.cuda.synchronize()
+        res[mode] = (u.cpu().numpy().astype(np.float64), st)
+    u_ref, it, hist, why = oracle.cgls(g, psf, u0=np.zeros_like(g), cap=cap, eps=GUARD["f32"])
+    for mode in ("tall", "short"):
+        u, st = res[mode]
+        print(f"  {mode}: iters gpu={st['iters']} oracle={it} rel={_rel(u, u_ref):.2e}", flush=True)
+        assert st["iters"] == it and st["reason"] == why
+        assert _rel(u, u_ref) <= 2e-5
+    assert _rel(res["tall"][0], res["short"][0]) <= 1e-5
+
+
 @pytest.mark.parametrize("smoother", ["cgls", "mr"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("H,W,psfname", [(100, 77, "disk3"), (101, 90, "symdisk3"), (130, 257, "gauss2"),
@@ -143,6 +175,15 @@ def test_workload3_scaled_f32(torch_cuda):
     # the 4096^2 disk r=6 + texture recipe at 512^2 with 6 levels
     p = synth.workload(3, H=512, n_levels=6, n_shapes=120, n_textures=12)
     _check(p, "f32", *_run_both(torch_cuda, p, "f32"))
+
+
+@pytest.mark.parametrize("wid", [2, 3])
+def test_full_size_workload_matches_oracle(torch_cuda, wid):
+    """The 1024^2 and 4096^2 workloads at full size, in the configuration the
+    benchmark times (the 4096^2 finest level on tall strips): identical
+    iteration counts and stop reasons, FP32 bar against the FP64 oracle."""
+    p = synth.workload(wid)
+    _check(p, p.precision, *_run_both(torch_cuda, p, p.precision))
 
 
 @pytest.mark.parametrize("smoother", ["mr", "cgls"])

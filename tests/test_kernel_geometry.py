@@ -20,21 +20,23 @@ def strip_group(R):
     return NW * ((4 + 2 * R) // NW)
 
 
-def strip_th(R):
-    """Mirror of strip_th(): smallest height >= 32 with (height + 2R) a
-    multiple of the group size."""
+def strip_th(R, tall=False):
+    """Mirror of strip_th(): smallest height >= 32 (tall strips: >= 64) with
+    (height + 2R) a multiple of the group size."""
     GS = strip_group(R)
-    return GS * ((KTH + 2 * R + GS - 1) // GS) - 2 * R
+    base = 2 * KTH if tall else KTH
+    return GS * ((base + 2 * R + GS - 1) // GS) - 2 * R
 
 
-def _model(R):
+def _model(R, tall=False):
     NW = 2 * R + 1
-    TH = strip_th(R)
+    TH = strip_th(R, tall)
     LH = TH + 2 * R
     LW = KTW + 2 * R
     GS = strip_group(R)
+    base = 2 * KTH if tall else KTH
     assert GS % NW == 0 and GS >= 4
-    assert TH >= KTH and TH < KTH + GS and LH % GS == 0
+    assert TH >= base and TH < base + GS and LH % GS == 0
     NG = LH // GS
     D = min(GS, PREFETCH)
     slot_owner = [None] * NW
@@ -83,17 +85,19 @@ def _model(R):
     return emitted, TH
 
 
+@pytest.mark.parametrize("tall", [False, True])
 @pytest.mark.parametrize("R", list(range(0, 13)))
-def test_streaming_scheme(R):
-    emitted, TH = _model(R)
+def test_streaming_scheme(R, tall):
+    emitted, TH = _model(R, tall)
     assert emitted == list(range(TH))
 
 
+@pytest.mark.parametrize("tall", [False, True])
 @pytest.mark.parametrize("R", [0, 1, 3, 6, 12])
 @pytest.mark.parametrize("up", [False, True])
-def test_strip_row_mapping(R, up):
+def test_strip_row_mapping(R, up, tall):
     """Mirror of stream_strip's row_at / out_at for both walking directions."""
-    TH = strip_th(R)
+    TH = strip_th(R, tall)
     LH = TH + 2 * R
     y0 = 5 * TH
     ybase, ystep = (y0 + TH + R - 1, -1) if up else (y0 - R, 1)
