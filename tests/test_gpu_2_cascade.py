@@ -364,6 +364,28 @@ def test_batch_equals_alone_bitwise(torch_cuda, prec):
         assert sa == sb
 
 
+def test_tall_strip_image_in_a_batch_equals_alone_bitwise(torch_cuda):
+    """A 2200 x 4096 FP32 image's finest level runs on tall strips; the
+    choice depends on the level's shape only, so the image restored in a
+    batch with small images (which share the coarser levels' launches) gives
+    the same bits as alone."""
+    t = torch_cuda
+    probs = [synth.workload(3, H=2200, W=4096, n_levels=6, n_shapes=200, n_textures=20),
+             synth.workload(3, H=300, W=520, n_levels=4, n_shapes=20, n_textures=2),
+             synth.workload(2, H=256, W=256, n_levels=5, n_shapes=30)]
+    gs = [t.from_numpy(q.g_delta.astype(np.float32)).to("cuda:0") for q in probs]
+    alone = []
+    for q, g in zip(probs, gs):
+        u, st = eecmg.restore_dev(g, q.psf, q.n_levels, precision="f32", delta=q.delta)
+        alone.append((u.clone(), st))
+    outs, sts = eecmg.restore_batch_dev(gs, [q.psf for q in probs], [q.n_levels for q in probs], precision="f32",
+                                        params=[{"delta": q.delta} for q in probs])
+    t.cuda.synchronize()
+    for (ua, sa), ub, sb in zip(alone, outs, sts):
+        np.testing.assert_array_equal(ua.cpu().numpy(), ub.cpu().numpy())
+        assert sa == sb
+
+
 def test_served_mix_equals_alone_bitwise(torch_cuda):
     t = torch_cuda
     probs = [synth.workload(1, H=64, W=64), synth.workload(1, H=97, W=50),
