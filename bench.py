@@ -345,11 +345,9 @@ def main():
         eecmg.restore_dev(g, p.psf, p.n_levels, out=out, **kw)
     torch.cuda.synchronize()
 
-    # finest-level launches only: every smoother tile is at most 96 rows tall
-    # (tall strips included), and the next level has a quarter of the pixels
-    fine_tiles = ((W + 63) // 64) * ((H + 95) // 96)
+    # finest-level launches only (the job's level holds all H x W pixels)
     eecmg.profile_reset()
-    eecmg.profile_enable(True, min_blocks=fine_tiles)
+    eecmg.profile_enable(True, min_pixels=H * W)
     _log(f"bench: timing {args.steps} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()

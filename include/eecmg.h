@@ -251,8 +251,9 @@ int eecmg_op_pm_step_dev(const void* u_dev, void* out_dev, int H, int W, double 
 
 /* ---------------------------------------------------------------------------
  * Kernel timing (diagnostics).  While enabled, every launch of a smoother or
- * transfer stage whose grid has at least min_blocks blocks is bracketed by
- * HIP events on its launch stream; eecmg_profile_read waits for the recorded
+ * transfer stage whose grid has at least min_blocks blocks, and whose jobs'
+ * levels hold at least the pixels set by eecmg_profile_min_pixels (default 0;
+ * EINVAL if negative or NaN), is bracketed by HIP events on its launch stream; eecmg_profile_read waits for the recorded
  * events and returns, for one stage id, the number of launches, their summed
  * duration, and the pixels they covered (sum over the jobs of the level's
  * H x W).  Stage ids: 1 CGLS init r, 2 CGLS init s, 4 CGLS pass A (q = H p),
@@ -264,6 +265,7 @@ int eecmg_op_pm_step_dev(const void* u_dev, void* out_dev, int H, int W, double 
  * Process-wide; not meant for concurrent contexts.
  * ------------------------------------------------------------------------- */
 int eecmg_profile_enable(int enable, int min_blocks);
+int eecmg_profile_min_pixels(double min_pixels);
 int eecmg_profile_reset(void);
 int eecmg_profile_read(int stage, int* launches, double* total_ms, double* total_pixels);
 

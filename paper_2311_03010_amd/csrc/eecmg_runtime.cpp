@@ -510,6 +510,7 @@ struct Profiler {
   std::mutex mu;
   std::atomic<bool> on{false};
   int min_blocks = 0;
+  double min_pixels = 0.0;
   struct Tag {
     uint32_t uid;
     int level, kidx;
@@ -1163,14 +1164,16 @@ class Engine {
     ll.start[ll.n] = ll.total;
     if (ll.total <= 0) return;
     Profiler& pr = profiler();
-    if (pr.on.load(std::memory_order_relaxed) && profiled_stage(st) && ll.total >= pr.min_blocks) {
-      double px = 0.0;
+    double px = 0.0;
+    const bool prof = pr.on.load(std::memory_order_relaxed) && profiled_stage(st) && ll.total >= pr.min_blocks;
+    if (prof)
       for (size_t i = 0; i < jobs.size(); ++i) {
         const Job* j = jobs[i];
         const int l = level_of(i);
         px += st == kXfExtrap ? (double)j->plan.lv[l - 1].h * j->plan.lv[l - 1].w
                               : (double)j->plan.lv[l].h * j->plan.lv[l].w;
       }
+    if (prof && px >= pr.min_pixels) {
       std::lock_guard<std::mutex> g(pr.mu);
       hipEvent_t a = pr.ev(), b = pr.ev();
       chk(hipEventRecord(a, stream_));
@@ -1466,6 +1469,14 @@ int eecmg_profile_enable(int enable, int min_blocks) {
   std::lock_guard<std::mutex> g(p.mu);
   p.min_blocks = min_blocks < 0 ? 0 : min_blocks;
   p.on.store(enable != 0);
+  return EECMG_OK;
+}
+
+int eecmg_profile_min_pixels(double min_pixels) {
+  if (!(min_pixels >= 0.0)) return fail(EECMG_EINVAL, "min_pixels must be >= 0");
+  Profiler& p = profiler();
+  std::lock_guard<std::mutex> g(p.mu);
+  p.min_pixels = min_pixels;
   return EECMG_OK;
 }
 

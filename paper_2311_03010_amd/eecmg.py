@@ -96,6 +96,7 @@ def lib():
         "eecmg_op_pm_step_dev": [vp, vp, i, i, d, d, i, vp],
         "eecmg_op_transfer_dev": [vp, i, i, vp, i, d, i, d, d, i, vp],
         "eecmg_profile_enable": [i, i],
+        "eecmg_profile_min_pixels": [d],
         "eecmg_profile_reset": [],
         "eecmg_profile_read": [i, ip, dp, dp],
     }
@@ -380,7 +381,10 @@ STAGES = {"cg_init_r": 1, "cg_init_s": 2, "cg_pass_a": 4, "cg_pass_b": 6, "mr_in
           "transfer_fused": 18, "coarse": 20, "cg_pass_b_dconv": 22}
 
 
-def profile_enable(enable=True, min_blocks=0):
+def profile_enable(enable=True, min_blocks=0, min_pixels=0.0):
+    """Time launches of at least min_blocks blocks whose levels hold at least
+    min_pixels pixels (summed over the jobs of the launch)."""
+    _check(lib().eecmg_profile_min_pixels(float(min_pixels)))
     _check(lib().eecmg_profile_enable(1 if enable else 0, int(min_blocks)))
 
 

@@ -64,3 +64,7 @@ def test_host_only_entry_points_without_gpu():
             np.testing.assert_allclose(eecmg.coarse_psf(psf, mode), oracle.coarse_psf(psf, mode), rtol=1e-15)
     with pytest.raises(eecmg.EecmgError):
         eecmg.coarse_psf(synth.disk_psf(6), 7)
+    # the profiler's pixel filter rejects a negative or NaN bound and accepts 0
+    assert eecmg.lib().eecmg_profile_min_pixels(-1.0) == eecmg.EINVAL
+    assert eecmg.lib().eecmg_profile_min_pixels(float("nan")) == eecmg.EINVAL
+    assert eecmg.lib().eecmg_profile_min_pixels(0.0) == eecmg.OK
