@@ -187,6 +187,20 @@ def test_full_size_workload_matches_oracle(torch_cuda, wid):
 
 
 @pytest.mark.parametrize("smoother", ["mr", "cgls"])
+def test_full_size_edge_workload_matches_oracle(torch_cuda, smoother):
+    """The edge-preservation workload at the size the benchmark runs it
+    (1024^2, 7 levels), EECMG(MR) and EECMG(CG): oracle bars, and the same
+    edge measures."""
+    from paper_2311_03010_amd import metrics
+
+    p = synth.edge_workload()
+    u, st, u_ref, st_ref = _run_both(torch_cuda, p, "f32", smoother=smoother)
+    _check(p, "f32", u, st, u_ref, st_ref)
+    assert abs(metrics.edge_recall(p.u_true, u) - metrics.edge_recall(p.u_true, u_ref)) <= 1e-3
+    assert abs(metrics.edge_error(p.u_true, u) - metrics.edge_error(p.u_true, u_ref)) <= 1e-3
+
+
+@pytest.mark.parametrize("smoother", ["mr", "cgls"])
 def test_edge_workload_scaled_f32(torch_cuda, smoother):
     # the edge-preservation recipe (edge-dense scene, Gaussian sigma=3 with
     # half bandwidth 11) at 256^2 with 5 levels; EECMG(MR) is the paper's
