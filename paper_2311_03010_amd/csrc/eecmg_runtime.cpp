@@ -1001,7 +1001,12 @@ class Engine {
   int device() const { return device_; }
 
  private:
+  // Unconfirmed iterations a job may have queued.  At least 2: with folded
+  // finalizes, iteration k's progress word is published by iteration k + 1's
+  // pass A, so a single iteration in flight would wait for itself.  Deeper
+  // run-ahead only adds empty launches after a level stops (measured slower).
   static constexpr int kMaxAhead = 2;
+  static_assert(kMaxAhead >= 2, "folded finalizes confirm an iteration only from the next one");
 
   static constexpr int kStepEvents = 4;
 
