@@ -18,7 +18,9 @@ Parity status per function (pins live in ``tests/test_oracle_*.py``):
   local_smooth           pinned (affine reproduction, brute-force lstsq)
   pm_step                pinned (mass conservation, maximum principle,
                          heat-step limit)
-  restore                pinned on identity-PSF / zero-noise recovery and
+  restore                pinned on its composition (rebuilt from the pinned
+                         operators in the order of Algorithms 1 and 2, bit for
+                         bit), identity-PSF / zero-noise recovery and
                          symmetry; the paper's PSNR tables use an image that
                          is not available: parity unpinned for those values.
 """

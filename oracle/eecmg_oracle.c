@@ -105,8 +105,8 @@ int or_level_sizes(int H, int W, int L, int* hs, int* ws) {
 /* Economic iteration counts m_l (Section 2, after Algorithm 2):
  *   l >  L0: m_l = ceil(m0 (L - L0)^2 beta^(L-l))
  *   l <= L0: m_l = ceil(sqrt(m_*) (L - (2 - eps0) l) h_l^(-2))
- * with L0 = L/2, m0 = 1, beta = 4, m_* = 1, eps0 = 1/2, h_l = (1/2)^(l-1), and
- * [t] the smallest positive integer not less than t (so at least 1).
+ * with L0 = L/2, m0 = 1, beta = 4, m_* = 1, eps0 = 1/2, h_l = (1/2)^(l-1);
+ * the bracket [t] is read as ceil(t), and a cap is never below 1.
  * Reading: l > L0 is compared as reals (L0 may be a half-integer). */
 int or_iteration_caps(int L, int* m) {
   if (L < 1) return OR_EINVAL;
