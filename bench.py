@@ -159,7 +159,7 @@ def edge_leg(torch, eecmg, synth, steps, H=1024, n_levels=7):
     return out
 
 
-def set_leg(torch, eecmg, synth, n_images, steps):
+def set_leg(torch, eecmg, synth, n_images, steps, form="both"):
     """The uneven batch: n_images images with sides log-uniform in
     [128, 2048] and a mix of Gaussian and disk PSFs, each restored with its
     own level count.  Plain = one restore call per image in turn; batched =
@@ -191,9 +191,9 @@ def set_leg(torch, eecmg, synth, n_images, steps):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
-    tp = timed(plain)
-    tb = timed(batched)
-    equal = all(torch.equal(a, b) for a, b in zip(po, bo))
+    tp = timed(plain) if form != "batched" else float("nan")
+    tb = timed(batched) if form != "plain" else float("nan")
+    equal = form == "both" and all(torch.equal(a, b) for a, b in zip(po, bo))
     return {"workload": f"uneven batch of {n_images} images, sides log-uniform in [128, 2048], "
                         "Gaussian sigma U[1,4] / disk r U{2..6} PSFs, FP32",
             "images": n_images, "mpixels": round(px / 1e6, 3), "steps": steps,
@@ -315,13 +315,23 @@ def main():
     ap.add_argument("--set-images", type=int, default=256,
                     help="images in the uneven plain-vs-batched set (0 = skip)")
     ap.add_argument("--set-steps", type=int, default=2)
+    ap.add_argument("--set-form", default="both", choices=["both", "plain", "batched"],
+                    help="which forms of the uneven set to run (profiling one form)")
     ap.add_argument("--served-requests", type=int, default=2000, help="served requests (0 = skip)")
     ap.add_argument("--served-pool", type=int, default=64)
     ap.add_argument("--no-edge", action="store_true", help="skip the edge-preservation workload")
     ap.add_argument("--copy-probe", action="store_true", help="only run the HBM counter calibration copy")
+    ap.add_argument("--only-set", action="store_true", help="only run the uneven set (for profiling it)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.only_set:
+        import torch
+
+        from paper_2311_03010_amd import eecmg, synth
+
+        print(json.dumps(set_leg(torch, eecmg, synth, args.set_images, args.set_steps, args.set_form)), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -424,7 +434,7 @@ def main():
     uneven = None
     if args.set_images > 0:
         _log(f"bench: uneven set, {args.set_images} images, plain vs batched")
-        uneven = set_leg(torch, eecmg, synth, args.set_images, args.set_steps)
+        uneven = set_leg(torch, eecmg, synth, args.set_images, args.set_steps, args.set_form)
 
     edge = None
     if not args.no_edge:

@@ -20,12 +20,20 @@ COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
-def build_library(verbose: bool = False) -> str:
+def build_library(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source (incremental=True: only those whose object is
+    older than the source or any header) and link libeecmg.so."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
+    headers = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    headers.append(os.path.join(ROOT, "include", "eecmg.h"))
+    newest_header = max(os.path.getmtime(h) for h in headers)
 
     def compile_one(src):
         obj = os.path.join(objdir, src + ".o")
+        if incremental and os.path.exists(obj) and os.path.getmtime(obj) >= max(
+                newest_header, os.path.getmtime(os.path.join(CSRC, src))):
+            return obj
         cmd = [HIPCC, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
             cmd = [HIPCC, *COMMON, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
@@ -50,4 +58,4 @@ def build_library(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build_library(verbose=True))
+    print(build_library(verbose=True, incremental="--incremental" in sys.argv))

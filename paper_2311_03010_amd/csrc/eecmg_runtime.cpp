@@ -717,6 +717,10 @@ class Engine {
     j->slot = slot;
     j->mem = mem;
     j->uid = (next_uid_++) & 0xFFFFFF;
+    // the slot's previous occupant has no kernels left (its completion event
+    // was seen): clear its progress word so that a stale word with the same
+    // tag can never be taken for this job's
+    __atomic_store_n(&h_mirror_[slot], (uint64_t)0, __ATOMIC_RELEASE);
     slots_[slot] = j;
     ++n_active_;
     j->phase = Job::kNew;
@@ -749,8 +753,16 @@ class Engine {
   // Issue one round of work for every active job.  Returns true if anything
   // was launched.
   bool step(std::vector<Job*>& finished) {
+    const bool idle_before = !step_pending_;  // everything enqueued so far had completed
+    const uint64_t progress_before = progress_sum();
     poll_mirror();
     finished.clear();
+    if (fail_step_ > 0 && ++steps_ == fail_step_ && err_ == hipSuccess) {
+      // test hook (EECMG_TEST_FAIL_STEP): a HIP error reported by this step,
+      // without any kernel being affected
+      err_ = hipErrorUnknown;
+      return false;
+    }
     // action lists
     std::vector<Job*> restrict_l, out_l, coarse_l;
     std::vector<std::pair<Job*, int>> xfer_l;  // job, level
@@ -824,7 +836,7 @@ class Engine {
             // hide the host's reaction time, few enough that a data-dependent
             // stop leaves almost no empty launches behind
             const int ahead = j->issued - j->confirmed;
-            const int chunk = std::min(limit - j->issued, kMaxAhead - ahead);
+            const int chunk = std::min(limit - j->issued, max_ahead_ - ahead);
             if (chunk > 0) {
               iter_l.push_back({j, chunk});
               j->issued += chunk;
@@ -832,7 +844,7 @@ class Engine {
             break;
           }
           case Job::kWaitOut:
-            if (hipEventQuery(j->done_ev->e) == hipSuccess) {
+            if (event_done(j->done_ev->e)) {
               finish(j);
               finished.push_back(j);
             }
@@ -962,6 +974,7 @@ class Engine {
       chk(hipEventRecord(step_ev_[step_cur_], stream_));
       step_pending_ = true;
     }
+    note_progress(launched || !finished.empty() || progress_sum() != progress_before || !idle_before);
     return launched;
   }
 
@@ -972,11 +985,12 @@ class Engine {
     for (long spin = 0;; ++spin) {
       if (snapshot() != before) return;
       for (Job* j : slots_)
-        if (j && j->phase == Job::kWaitOut && hipEventQuery(j->done_ev->e) == hipSuccess) return;
-      if (!step_pending_ || hipEventQuery(step_ev_[step_cur_]) == hipSuccess) {
+        if (j && j->phase == Job::kWaitOut && event_done(j->done_ev->e)) return;
+      if (!step_pending_ || event_done(step_ev_[step_cur_])) {
         step_pending_ = false;
         return;
       }
+      if (err_ != hipSuccess) return;
       if (spin > 2000) std::this_thread::yield();
     }
   }
@@ -1005,8 +1019,87 @@ class Engine {
   // finalizes, iteration k's progress word is published by iteration k + 1's
   // pass A, so a single iteration in flight would wait for itself.  Deeper
   // run-ahead only adds empty launches after a level stops (measured slower).
+  // EECMG_MAX_AHEAD moves it (1..8); 1 stalls on levels with folded
+  // finalizes, which the stall guard then reports (its test uses that).
   static constexpr int kMaxAhead = 2;
   static_assert(kMaxAhead >= 2, "folded finalizes confirm an iteration only from the next one");
+
+ public:
+  // Re-read the environment knobs of the scheduler (once per driver call).
+  void read_knobs() {
+    const char* e = std::getenv("EECMG_MAX_AHEAD");
+    max_ahead_ = e ? std::min(8, std::max(1, std::atoi(e))) : kMaxAhead;
+    e = std::getenv("EECMG_STALL_STEPS");
+    stall_steps_ = e ? std::max(0L, std::atol(e)) : kStallSteps;
+    e = std::getenv("EECMG_STALL_MS");
+    stall_ms_ = e ? std::max(0.0, std::atof(e)) : kStallMs;
+    e = std::getenv("EECMG_TEST_FAIL_STEP");
+    fail_step_ = e ? std::atol(e) : 0;
+    steps_ = 0;
+  }
+  // The engine can make no further progress: a HIP error was reported, or the
+  // stall guard tripped.  Returns the status and message for the callers.
+  bool failed() const { return err_ != hipSuccess || stalled_; }
+  std::string failure() const {
+    if (err_ != hipSuccess) return std::string("HIP error in the cascade: ") + hipGetErrorString(err_);
+    return "scheduler stall: no kernel to launch, no progress and the device idle for " +
+           std::to_string(idle_steps_) + " steps";
+  }
+  // After failed(): wait for the device to finish (or fail) everything
+  // enqueued, mark every admitted job that has not finished with `status`,
+  // free their slots and memory and append them to `out`, and clear the error
+  // state so that the engine can be used again.
+  void abort_all(int status, std::vector<Job*>& out) {
+    (void)hipStreamSynchronize(stream_);
+    if (copy_) (void)hipStreamSynchronize(copy_);
+    (void)hipGetLastError();
+    for (Job* j : slots_) {
+      if (!j || j->phase == Job::kFinished) continue;  // finished ones are the caller's to release
+      j->status = status;
+      j->phase = Job::kFinished;
+      j->t_done = now_s();
+      release(j);
+      out.push_back(j);
+    }
+    for (int i = 0; i < kMaxSlots; ++i) __atomic_store_n(&h_mirror_[i], (uint64_t)0, __ATOMIC_RELEASE);
+    err_ = hipSuccess;
+    stalled_ = false;
+    step_pending_ = false;
+    idle_steps_ = 0;
+  }
+
+ private:
+  // A job cannot advance when nothing was launched, no job finished, no
+  // progress word changed and the device had completed all enqueued work
+  // before the step.  In a correct schedule that resolves at once (the
+  // progress words of completed work are visible), so it persisting for
+  // stall_steps_ consecutive steps and stall_ms_ milliseconds is a stall.
+  static constexpr long kStallSteps = 1000;
+  static constexpr double kStallMs = 1000.0;
+  void note_progress(bool progress) {
+    // a job waiting for its output copy waits for an event that completes
+    for (const Job* j : slots_)
+      if (j && j->phase == Job::kWaitOut) progress = true;
+    if (progress || n_active_ == 0) {
+      idle_steps_ = 0;
+      return;
+    }
+    if (idle_steps_++ == 0) idle_since_ = now_s();
+    if (idle_steps_ >= stall_steps_ && (now_s() - idle_since_) * 1e3 >= stall_ms_) stalled_ = true;
+  }
+  uint64_t progress_sum() const {
+    uint64_t h = 0;
+    for (int i = 0; i < kMaxSlots; ++i) h = h * 1000003u + __atomic_load_n(&h_mirror_[i], __ATOMIC_ACQUIRE);
+    return h;
+  }
+  // hipEventQuery: complete, not yet, or an error (recorded as the engine's
+  // error, which the drivers then report).
+  bool event_done(hipEvent_t e) {
+    const hipError_t r = hipEventQuery(e);
+    if (r == hipSuccess) return true;
+    if (r != hipErrorNotReady) chk(r);
+    return false;
+  }
 
   static constexpr int kStepEvents = 4;
 
@@ -1309,7 +1402,9 @@ class Engine {
     {
       Profiler& pr = profiler();
       std::lock_guard<std::mutex> g(pr.mu);
-      for (int l = 0; l < j->plan.L; ++l) pr.final_iters[((uint64_t)j->uid << 8) | (uint64_t)l] = j->rec[l].iters;
+      // (only while profiling: a long-running context would grow the map)
+      if (pr.on.load(std::memory_order_relaxed) || !pr.pending.empty())
+        for (int l = 0; l < j->plan.L; ++l) pr.final_iters[((uint64_t)j->uid << 8) | (uint64_t)l] = j->rec[l].iters;
     }
     int st = EECMG_OK;
     for (int l = 0; l < j->plan.L; ++l)
@@ -1342,6 +1437,10 @@ class Engine {
   hipEvent_t step_ev_[kStepEvents] = {};
   int step_cur_ = 0;
   bool step_pending_ = false;
+  int max_ahead_ = kMaxAhead;
+  long stall_steps_ = kStallSteps, idle_steps_ = 0, fail_step_ = 0, steps_ = 0;
+  double stall_ms_ = kStallMs, idle_since_ = 0.0;
+  bool stalled_ = false;
   uint32_t next_uid_ = 1;
   std::vector<Job*> slots_;
   int n_active_ = 0;
@@ -1364,14 +1463,22 @@ static void fill_stats(const Job* j, eecmg_stats* s) {
 }
 
 // Run a set of jobs to completion on an engine (admitting as room frees).
+// On a HIP error or a scheduler stall every admitted job is aborted (the
+// device drained first, slots and memory freed) before EDEVICE is returned,
+// so the engine holds no job of this call afterwards.
 static int run_jobs(Engine& E, std::vector<Job*>& jobs) {
   size_t next = 0, done = 0;
   std::vector<Job*> fin;
+  E.read_knobs();
   while (done < jobs.size()) {
     while (next < jobs.size()) {
       const int rc = E.admit(jobs[next]);
       if (rc == EECMG_EAGAIN) break;
-      if (rc != EECMG_OK) return rc;
+      if (rc != EECMG_OK) {
+        std::vector<Job*> ab;
+        E.abort_all(rc, ab);
+        return rc;
+      }
       ++next;
     }
     if (E.active() == 0 && next < jobs.size())
@@ -1381,11 +1488,12 @@ static int run_jobs(Engine& E, std::vector<Job*>& jobs) {
       E.release(j);
       ++done;
     }
-    if (!launched && fin.empty()) E.wait_some();
-    if (E.error() != hipSuccess) {
-      const hipError_t e = E.error();
-      E.clear_error();
-      return fail(EECMG_EDEVICE, std::string("HIP error in the cascade: ") + hipGetErrorString(e));
+    if (!launched && fin.empty() && !E.failed()) E.wait_some();
+    if (E.failed()) {
+      const std::string msg = E.failure();
+      std::vector<Job*> ab;
+      E.abort_all(EECMG_EDEVICE, ab);
+      return fail(EECMG_EDEVICE, msg);
     }
   }
   return EECMG_OK;
@@ -1568,9 +1676,16 @@ int eecmg_restore(const void* g_delta, int H, int W, const double* psf, int psf_
     return fail(EECMG_EDEVICE, std::string("hipMemcpy H2D: ") + hipGetErrorString(he));
   }
   std::vector<Job*> fin;
+  E.read_knobs();
   while (job.phase != Job::kFinished) {
     const bool launched = E.step(fin);
-    if (!launched && fin.empty()) E.wait_some();
+    if (!launched && fin.empty() && !E.failed()) E.wait_some();
+    if (E.failed()) {
+      const std::string msg = E.failure();
+      std::vector<Job*> ab;
+      E.abort_all(EECMG_EDEVICE, ab);
+      return fail(EECMG_EDEVICE, msg);
+    }
   }
   he = hipMemcpy(u_out, job.u_out_dev, bytes, hipMemcpyDeviceToHost);
   E.release(&job);
@@ -1926,7 +2041,14 @@ static void progress_loop(eecmg_ctx* C) {
         continue;
       }
     }
-    const bool launched = E.step(fin);
+    bool launched = E.step(fin);
+    if (!launched && fin.empty() && !E.failed()) E.wait_some();
+    if (E.failed()) {
+      // a HIP error or a stall: every admitted request fails with EDEVICE
+      // (the device is drained first); queued requests stay queued
+      launched = false;
+      E.abort_all(EECMG_EDEVICE, fin);
+    }
     if (!fin.empty()) {
       std::lock_guard<std::mutex> lk(C->mu);
       for (Job* j : fin) {
@@ -1940,7 +2062,6 @@ static void progress_loop(eecmg_ctx* C) {
       }
       C->cv_done.notify_all();
     }
-    if (!launched && fin.empty()) E.wait_some();
   }
 }
 
@@ -1976,6 +2097,7 @@ int eecmg_create(const eecmg_ctx_config* cfg, eecmg_ctx** out) {
   C->eng->set_copy_stream(C->copy_stream);
   rc = C->eng->arena().reserve(c.hbm_budget_bytes);
   if (rc) return rc;
+  C->eng->read_knobs();  // the context's scheduler knobs are fixed at creation
   C->th = std::thread(progress_loop, C.get());
   *out = C.release();
   return EECMG_OK;
