@@ -25,10 +25,23 @@ reports
                  the poll that returns the result;
   roofline:      the finest-level CGLS pass B kernel (dominant), algorithmic
                  HBM bytes per launch / its mean duration from HIP events on
-                 the library's launch stream during the timed region (launches
-                 that found their level already stopped are excluded);
+                 the library's launch stream, over a timed region of its own
+                 (launches that found their level already stopped are
+                 excluded); roofline.cascade: the whole restore's algorithmic
+                 bytes / ms_per_step, and per level the algorithmic bytes /
+                 the summed kernel time of that level (HIP events around every
+                 launch, in one more timed region);
+  workloads:     the 64^2 FP64 and 1024^2 FP32 workloads: throughput and the
+                 error against the FP64 oracle;
+  one_level:     the 1024^2 workload restored by the one-level smoother with
+                 the stopping rule (CGLS and MR) next to the cascade: PSNR and
+                 time;
   cpu_baseline:  the FP64 CPU oracle timed on one complete restore of the
-                 same input on the host's cores.
+                 same input on all of the host's cores; cpu_oracle: the oracle
+                 on one core and on all cores for the three single-image
+                 workloads, with the host's CPU model and core count.
+`value` comes from a timed region with kernel timing off; the profiled
+regions come after it.
 """
 from __future__ import annotations
 
@@ -108,20 +121,202 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(p, stats):
-    """The FP64 CPU oracle (OpenMP over the pixel loops of its stencils) timed
-    on one complete restore of the same input, same parameters."""
+def host_cpu():
+    """CPU model and core counts of the host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "nproc": os.cpu_count(), "usable": usable}
+
+
+def oracle_restore(p, threads=None):
+    """One complete FP64 oracle restore of the workload's input (rounded to
+    the GPU run's storage precision first), same parameters; (u, stats, s)."""
     import oracle
 
+    if threads is not None:
+        oracle.set_num_threads(threads)
     g = p.g_delta.astype(np.float32).astype(np.float64) if p.precision != "f64" else p.g_delta
     t0 = time.perf_counter()
-    _, st = oracle.restore(g, p.psf, p.n_levels, delta=p.delta, k=p.k,
+    u, st = oracle.restore(g, p.psf, p.n_levels, delta=p.delta, k=p.k,
                            guard_eps=1e-6 if p.precision != "f64" else 1e-14)
-    dt = time.perf_counter() - t0
+    return u, st, time.perf_counter() - t0
+
+
+def accuracy(p, u_gpu, u_ref, st_gpu, st_ref):
+    import oracle
+
+    u = np.asarray(u_gpu, np.float64)
+    return {"rel_l2_vs_oracle": float(np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)),
+            "dpsnr_db": round(abs(oracle.psnr(p.u_true, u) - oracle.psnr(p.u_true, u_ref)), 6),
+            "psnr_db": round(oracle.psnr(p.u_true, u), 4), "iters_equal": st_gpu["iters"] == st_ref["iters"]}
+
+
+def cpu_baseline(p, stats, u_gpu):
+    """The FP64 CPU oracle (OpenMP over the pixel loops of its stencils) timed
+    on one complete restore of the same input on all host cores."""
+    import oracle
+
+    oracle.set_num_threads(host_cpu()["usable"])
+    u, st, dt = oracle_restore(p)
+    acc = accuracy(p, u_gpu, u, stats, st)
     return {"value": round(p.shape[0] * p.shape[1] / dt / 1e6, 4), "unit": "Mpixel/s", "cores": oracle.num_threads(),
             "kind": "oracle",
             "sample": f"one complete restore of the same {p.shape[0]}x{p.shape[1]} input ({dt:.1f} s); "
-                      f"oracle iterations per level {st['iters']} (GPU {stats['iters']})"}
+                      f"oracle iterations per level {st['iters']} (GPU {stats['iters']})"}, acc
+
+
+def cpu_oracle_table(synth, ids, one_core):
+    """The oracle on one core and on all usable cores, per workload (full
+    restores; one run each)."""
+    import oracle
+
+    cpu = host_cpu()
+    out = {"host": cpu, "workloads": {}}
+    for wid in ids:
+        p = synth.workload(wid)
+        row = {}
+        for label, th in (("all_cores", cpu["usable"]), ("one_core", 1)):
+            if label == "one_core" and not one_core:
+                continue
+            _, _, dt = oracle_restore(p, threads=th)
+            row[label] = {"threads": th, "seconds": round(dt, 3),
+                          "mpixel_s": round(p.shape[0] * p.shape[1] / dt / 1e6, 4)}
+        out["workloads"][p.name] = row
+    oracle.set_num_threads(cpu["usable"])
+    return out
+
+
+# Algorithmic HBM bytes per pixel (FP32; FP64 doubles them): a CGLS iteration
+# reads and writes u, r, p, s once (32); its start r = g - H u0, s = H^T r
+# reads g, u0, r and writes r, s (20); an MR iteration reads r, q, u and
+# writes them (24), its start 12; the transfer into a level reads the two
+# coarser solutions and writes the extrapolated one (Pi: 2.25 per fine
+# pixel), then reads that and writes the level's start (prolongation, S, D:
+# 5); the restriction reads the even rows of the input (2) and writes every
+# coarser right-hand side.
+def level_bytes(sizes, iters, esz, smoother="cgls", cascade="eecmg"):
+    f = esz / 4.0
+    it_b, init_b = (32.0, 20.0) if smoother == "cgls" else (24.0, 12.0)
+    out = []
+    for l, ((h, w), k) in enumerate(zip(sizes, iters)):
+        px = h * w
+        b = (it_b * k + init_b) * px
+        if (cascade == "eecmg" and l >= 2) or (cascade != "eecmg" and l >= 1):
+            b += (7.25 if cascade == "eecmg" else 5.0) * px
+        out.append(b * f)
+    fine = sizes[-1][0] * sizes[-1][1]
+    restrict_b = (2.0 * fine + 4.0 * sum(h * w for h, w in sizes[:-1])) * f
+    return out, restrict_b
+
+
+def cascade_roofline(eecmg, restore_once, p, stats, steps, ms_step, copy_gbs):
+    """Per-level and whole-restore fractions of the HBM roofline."""
+    sizes = [tuple(s) for s in stats["sizes"]]
+    esz = 8 if p.precision == "f64" else 4
+    lb, rb = level_bytes(sizes, stats["iters"], esz)
+    coarse = 0
+    while coarse < len(sizes) and sizes[coarse][0] * sizes[coarse][1] <= 64 * 64:
+        coarse += 1
+    eecmg.profile_reset()
+    eecmg.profile_enable(True, min_pixels=0)
+    for _ in range(steps):
+        restore_once()
+    eecmg.profile_enable(False)
+    rows = []
+    kern_ms = 0.0
+    for l in range(len(sizes)):
+        if 0 < l < coarse:
+            continue
+        n, ms = eecmg.profile_read_level(l)
+        ms /= steps
+        kern_ms += ms
+        lv = list(range(coarse)) if (l == 0 and coarse > 0) else [l]
+        b = sum(lb[i] for i in lv)
+        ws = 6 * sizes[l][0] * sizes[l][1] * esz
+        rows.append({"levels": f"{sizes[lv[0]][0]}x{sizes[lv[0]][1]}" + (f"..{sizes[lv[-1]][0]}x{sizes[lv[-1]][1]}"
+                                                                          if len(lv) > 1 else ""),
+                     "iters": [stats["iters"][i] for i in lv], "launches_per_step": round(n / steps, 1),
+                     "alg_mb": round(b / 1e6, 3), "us": round(ms * 1e3, 1),
+                     "achieved_gbs": round(b / (ms * 1e-3) / 1e9, 1) if ms > 0 else None,
+                     "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ms > 0 else None,
+                     "fits_mall": ws <= (256 << 20)})
+    other = {}
+    for st in ("restrict", "out_copy"):
+        n, ms, _ = eecmg.profile_read(st)
+        other[st] = round(ms / steps * 1e3, 1)
+        kern_ms += ms / steps
+    total_b = sum(lb) + rb
+    ach = total_b / (ms_step * 1e-3) / 1e9
+    return {"alg_bytes_per_step": int(total_b), "ms_per_step": round(ms_step, 4), "achieved": round(ach, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+            "frac_vs_copy": round(ach / copy_gbs, 4) if copy_gbs else None,
+            "kernel_ms_per_step": round(kern_ms, 4), "gap_ms_per_step": round(ms_step - kern_ms, 4),
+            "restrict_us": other["restrict"], "out_copy_us": other["out_copy"], "per_level": rows,
+            "bytes": "CGLS 32 B/px per iteration + 20 at its start; transfer 7.25 per fine px (Pi 2.25, "
+                     "prolongation+S+D 5); restriction 2 per fine px + the coarser right-hand sides (FP32)"}
+
+
+def plain_leg(torch, eecmg, synth, wid, steps, warmup, with_oracle=True):
+    """Throughput of one workload restored plain, and its error against the
+    oracle (same input rounded to the storage precision)."""
+    p = synth.workload(wid)
+    prec = p.precision
+    g = torch.from_numpy(p.g_delta.astype(np.float64 if prec == "f64" else np.float32)).to("cuda:0")
+    out = torch.empty_like(g)
+    kw = dict(precision=prec, delta=p.delta, k=p.k)
+    for _ in range(warmup):
+        eecmg.restore_dev(g, p.psf, p.n_levels, out=out, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, st = eecmg.restore_dev(g, p.psf, p.n_levels, out=out, **kw)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    res = {"workload": p.name, "H": p.shape[0], "W": p.shape[1], "precision": prec, "n_levels": p.n_levels,
+           "value": round(p.shape[0] * p.shape[1] / dt / 1e6, 3), "unit": "Mpixel/s", "ms_per_step": round(dt * 1e3, 4),
+           "iters_per_level": st["iters"]}
+    if with_oracle:
+        u_ref, st_ref, _ = oracle_restore(p)
+        res["accuracy"] = accuracy(p, out.cpu().numpy(), u_ref, st, st_ref)
+    return res
+
+
+def one_level_leg(torch, eecmg, synth, steps):
+    """The 1024^2 workload (Gaussian sigma=3) restored by the one-level
+    smoother with the discrepancy stopping rule (the one-level baseline of the
+    paper's Table 1, here with the stopping rule instead of 4 fixed
+    iterations) next to the 7-level cascade: PSNR and time, CGLS and MR."""
+    import oracle
+
+    p = synth.workload(2)
+    g = torch.from_numpy(p.g_delta.astype(np.float32)).to("cuda:0")
+    out = torch.empty_like(g)
+    res = {"workload": f"{p.name}, FP32, discrepancy stopping rule c=1.1",
+           "input_psnr": round(oracle.psnr(p.u_true, p.g_delta), 4)}
+    for sm in ("cgls", "mr"):
+        for name, L, caps in (("one_level", 1, [1000]), ("cascade", p.n_levels, None)):
+            kw = dict(precision="f32", delta=p.delta, k=p.k, smoother=sm)
+            eecmg.restore_dev(g, p.psf, L, caps=caps, out=out, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                _, st = eecmg.restore_dev(g, p.psf, L, caps=caps, out=out, **kw)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            res[f"{name}_{sm}"] = {"ms": round(dt * 1e3, 4), "iters_per_level": st["iters"],
+                                   "psnr": round(oracle.psnr(p.u_true, out.cpu().numpy().astype(np.float64)), 4)}
+    return res
 
 
 def _pct(xs, q):
@@ -310,6 +505,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-table", action="store_true",
+                    help="skip the one-core / all-core oracle timings of the three workloads")
     ap.add_argument("--workload", type=int, default=3, choices=[1, 2, 3])
     ap.add_argument("--batch", type=int, default=4, help="images in the batched leg (0 = skip)")
     ap.add_argument("--set-images", type=int, default=256,
@@ -320,8 +517,12 @@ def main():
     ap.add_argument("--served-requests", type=int, default=2000, help="served requests (0 = skip)")
     ap.add_argument("--served-pool", type=int, default=64)
     ap.add_argument("--no-edge", action="store_true", help="skip the edge-preservation workload")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other workloads and the one-level leg")
     ap.add_argument("--copy-probe", action="store_true", help="only run the HBM counter calibration copy")
     ap.add_argument("--only-set", action="store_true", help="only run the uneven set (for profiling it)")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="no profiled regions (for runs under an external profiler)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
@@ -350,65 +551,77 @@ def main():
     out = torch.empty_like(g)
     kw = dict(precision=prec, delta=p.delta, k=p.k)
 
+    def restore_once():
+        return eecmg.restore_dev(g, p.psf, p.n_levels, out=out, **kw)
+
     _log("bench: warmup")
     for _ in range(args.warmup):
-        eecmg.restore_dev(g, p.psf, p.n_levels, out=out, **kw)
+        restore_once()
     torch.cuda.synchronize()
 
-    # finest-level launches only (the job's level holds all H x W pixels)
-    eecmg.profile_reset()
-    eecmg.profile_enable(True, min_pixels=H * W)
+    # the throughput: kernel timing off
     _log(f"bench: timing {args.steps} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = None
     for _ in range(args.steps):
-        _, stats = eecmg.restore_dev(g, p.psf, p.n_levels, out=out, **kw)
+        _, stats = restore_once()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    eecmg.profile_enable(False)
     ms_step = dt / args.steps * 1e3
     value = H * W * args.steps / dt / 1e6
+    u_gpu = out.cpu().numpy()
 
-    # dominant kernel: finest-level CGLS pass B (r -= alpha q, s = H^T r, u += alpha p).
-    # Algorithmic HBM bytes per pixel and iteration are 32 (u, r, p, s each
-    # read and written once): 12 in pass A (read s, p; write p) and 20 in
-    # pass B (read r, u; write r, u, s).  The two passes actually move 16 and,
-    # on average, 26 bytes: q is stored by A and read by B; B reads p again;
-    # on levels of >= 1024^2 pixels B updates u every second iteration
-    # (alternately 20 bytes without u and p, 32 with u and two directions).
-    # FP32 levels with a streaming blur kernel run the pass B that recomputes
-    # q = H p (pass A then stores no q): pass A moves 12 bytes, pass B 16 and
-    # 28 alternately (22 on average: it reads p for q instead of q).
-    try:
-        dconv = eecmg.profile_read("cg_pass_b_dconv")[0] > 0
-    except eecmg.EecmgError:  # a library without that stage
-        dconv = False
-    kern = {}
-    for name, src, bpp, moved in (("cg_pass_a", "cg_pass_a", 12, 12 if dconv else 16),
-                                  ("cg_pass_b", "cg_pass_b_dconv" if dconv else "cg_pass_b", 20, 22 if dconv else 26)):
-        n, ms, px = eecmg.profile_read(src)
-        if n:
-            avg_ms = ms / n
-            px_launch = px / n
-            kern[name] = {"launches": n, "avg_us": avg_ms * 1e3, "alg_bytes_per_px": bpp,
-                          "kernel": src, "gbs": bpp * px_launch / (avg_ms * 1e-3) / 1e9, "moved_bytes_per_px": moved,
-                          "moved_gbs": moved * px_launch / (avg_ms * 1e-3) / 1e9}
-    for name in ("cg_init_r", "cg_init_s", "transfer_fused"):
-        n, ms, px = eecmg.profile_read(name)
-        if n:
-            kern[name] = {"launches": n, "avg_us": ms / n * 1e3}
-    rb = kern.get("cg_pass_b")
     roofline = None
-    if rb:
-        ach = rb["gbs"]
+    kern = {}
+    if not args.no_profile:
+        # dominant kernel: finest-level CGLS pass B (r -= alpha q, s = H^T r,
+        # u += alpha p), timed with HIP events on the library's launch stream
+        # around each finest-level launch (the job's level holds all H x W
+        # pixels) in a timed region of its own.  Algorithmic HBM bytes per
+        # pixel and iteration are 32 (u, r, p, s each read and written once):
+        # 12 in pass A (read s, p; write p) and 20 in pass B (read r, u; write
+        # r, u, s).  The two passes actually move 16 and, on average, 26 bytes:
+        # q is stored by A and read by B; B reads p again; on levels of >=
+        # 1024^2 pixels B updates u every second iteration (alternately 20
+        # bytes without u and p, 32 with u and two directions).
+        _log("bench: profiled region (finest level)")
+        eecmg.profile_reset()
+        eecmg.profile_enable(True, min_pixels=H * W)
+        tp0 = time.perf_counter()
+        for _ in range(args.steps):
+            restore_once()
+        torch.cuda.synchronize()
+        ms_prof = (time.perf_counter() - tp0) / args.steps * 1e3
+        eecmg.profile_enable(False)
+        for name, bpp, moved in (("cg_pass_a", 12, 16), ("cg_pass_b", 20, 26)):
+            n, ms, px = eecmg.profile_read(name)
+            if n:
+                avg_ms = ms / n
+                px_launch = px / n
+                kern[name] = {"launches": n, "avg_us": avg_ms * 1e3, "alg_bytes_per_px": bpp,
+                              "gbs": bpp * px_launch / (avg_ms * 1e-3) / 1e9, "moved_bytes_per_px": moved,
+                              "moved_gbs": moved * px_launch / (avg_ms * 1e-3) / 1e9}
+        for name in ("cg_init_r", "cg_init_s", "transfer_fused", "extrapolate", "cg_fin_a", "cg_fin_b"):
+            n, ms, px = eecmg.profile_read(name)
+            if n:
+                kern[name] = {"launches": n, "avg_us": ms / n * 1e3}
+        rb = kern.get("cg_pass_b")
         cbw = copy_bandwidth(torch)
-        roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                    "copy_gbs": round(cbw, 1), "frac_vs_copy": round(ach / cbw, 4),
-                    "kernel": ("k_cg_bd<float, ConvBox<float, 6>>" if dconv else "k_cg_b<float, ConvBox<float, 6, true>>")
-                    + " (finest level, 4096^2" + ("" if dconv else ", tall strips") + ")",
-                    "avg_launch_us": round(rb["avg_us"], 2), "alg_bytes_per_launch": int(20 * H * W)}
+        if rb:
+            ach = rb["gbs"]
+            roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                        "copy_gbs": round(cbw, 1), "frac_vs_copy": round(ach / cbw, 4),
+                        "kernel": "k_cg_b<float, ConvBox<float, 6, true>> (finest level, 4096^2, tall strips)",
+                        "avg_launch_us": round(rb["avg_us"], 2), "alg_bytes_per_launch": int(20 * H * W),
+                        "ms_per_step_profiled": round(ms_prof, 4)}
+        _log("bench: profiled region (every level)")
+        casc = cascade_roofline(eecmg, restore_once, p, stats, args.steps, ms_step, cbw)
+        if roofline is None:
+            roofline = {"bound": "hbm", "achieved": casc["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": casc["frac"], "traffic": None, "kernel": "whole cascade"}
+        roofline["cascade"] = casc
     extra = {"kernels": kern, "iters_per_level": stats["iters"], "stop_reason": stats["reason"]}
 
     batched = None
@@ -427,9 +640,11 @@ def main():
             eecmg.restore_batch_dev(gs, [p.psf] * len(gs), [p.n_levels] * len(gs), outs=outs, **bkw)
         torch.cuda.synchronize()
         bdt = time.perf_counter() - t0
+        same = all(torch.equal(o, out) for o in outs)
         batched = {"images": len(gs), "value": round(len(gs) * H * W * args.steps / bdt / 1e6, 3),
                    "unit": "Mpixel/s", "ms_per_step": round(bdt / args.steps * 1e3, 3),
-                   "speedup_vs_plain": round(len(gs) * H * W * args.steps / bdt / 1e6 / value, 3)}
+                   "speedup_vs_plain": round(len(gs) * H * W * args.steps / bdt / 1e6 / value, 3),
+                   "bitwise_equal_to_plain": bool(same)}
 
     uneven = None
     if args.set_images > 0:
@@ -441,27 +656,42 @@ def main():
         _log("bench: edge-preservation workload")
         edge = edge_leg(torch, eecmg, synth, args.steps)
 
+    workloads = None
+    one_level = None
+    if not args.no_extra:
+        _log("bench: the other single-image workloads and the one-level leg")
+        workloads = [plain_leg(torch, eecmg, synth, wid, max(args.steps, 20), args.warmup)
+                     for wid in (1, 2, 3) if wid != args.workload]
+        one_level = one_level_leg(torch, eecmg, synth, args.steps)
+
     served = None
     if args.served_requests > 0:
         _log(f"bench: served, {args.served_requests} requests")
         served = served_leg(torch, eecmg, synth, args.served_requests, args.served_pool)
 
     cpu = None
+    cpu_table = None
+    acc = None
     if not args.no_cpu_baseline:
-        _log("bench: cpu baseline (oracle sample)")
-        cpu = cpu_baseline(p, stats)
+        _log("bench: cpu baseline (oracle, all cores)")
+        cpu, acc = cpu_baseline(p, stats, u_gpu)
+        if not args.no_oracle_table:
+            _log("bench: oracle on one core and on all cores")
+            cpu_table = cpu_oracle_table(synth, (1, 2, 3), one_core=True)
 
     metric = ("restored Mpixel/s plain vs batched at 4096\u00b2; p50/p99 latency; % HBM roofline"
               if args.workload == 3 else "restored Mpixel/s")
     line = {"metric": metric,
             "value": round(value, 3), "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-            "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f32" if prec != "f64" else "f64", "data": "synthetic",
-            "config": {"workload": p.name, "H": H, "W": W, "psf": "disk r=6" if args.workload == 3 else "gaussian",
+            "config": {"workload": p.name, "H": H, "W": W,
+                       "psf": {1: "gaussian sigma=2 r=4", 2: "gaussian sigma=3 r=7", 3: "disk r=6"}[args.workload],
                        "n_levels": p.n_levels, "precision": prec, "stop_rule": "discrepancy c=1.1",
                        "caps": "economic m_l rule", "form": "plain"},
-            "roofline": roofline, "cpu_baseline": cpu, "batched": batched, "uneven_set": uneven,
-            "served": served, "edge": edge, "detail": extra}
+            "roofline": roofline, "cpu_baseline": cpu, "accuracy_vs_oracle": acc, "batched": batched,
+            "uneven_set": uneven, "served": served, "edge": edge, "workloads": workloads, "one_level": one_level,
+            "cpu_oracle": cpu_table, "detail": extra}
     print(json.dumps(line), flush=True)
 
 

@@ -81,6 +81,7 @@ def _load():
         "or_pm_step": (None, [dp, i, i, d, d, dp]),
         "or_restore": (i, [dp, i, i, dp, i, i, ip, d, i, d, d, d, i, d, i, d, i, i, dp, ip, dp, ip, ip]),
         "or_num_threads": (i, []),
+        "or_set_num_threads": (None, [i]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -112,6 +113,11 @@ def _psf(psf):
 
 def num_threads() -> int:
     return int(_load().or_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the pixel loops (the results do not depend on it)."""
+    _load().or_set_num_threads(int(n))
 
 
 def dot(x, y) -> float:

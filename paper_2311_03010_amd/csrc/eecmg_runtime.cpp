@@ -521,6 +521,7 @@ struct Profiler {
     hipEvent_t a, b;
     double pixels;
     std::vector<Tag> tags;  // smoother passes: which iteration each job runs
+    int level;              // level index shared by every job of the launch, or -1
   };
   std::vector<Rec> pending;
   std::map<uint64_t, int> final_iters;  // (uid, level) -> iterations run
@@ -528,6 +529,9 @@ struct Profiler {
   int launches[kNumStages] = {};
   double ms[kNumStages] = {};
   double pixels[kNumStages] = {};
+  // every launch (also those that found their level stopped) by level and stage
+  int lv_launches[kMaxLevels][kNumStages] = {};
+  double lv_ms[kMaxLevels][kNumStages] = {};
 
   hipEvent_t ev() {
     if (!pool.empty()) {
@@ -554,10 +558,16 @@ struct Profiler {
   void harvest() {
     for (auto& r : pending) {
       float t = 0.f;
-      if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess && real(r)) {
-        launches[r.stage] += 1;
-        ms[r.stage] += t;
-        pixels[r.stage] += r.pixels;
+      if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+        if (real(r)) {
+          launches[r.stage] += 1;
+          ms[r.stage] += t;
+          pixels[r.stage] += r.pixels;
+        }
+        if (r.level >= 0 && r.level < kMaxLevels) {
+          lv_launches[r.level][r.stage] += 1;
+          lv_ms[r.level][r.stage] += t;
+        }
       }
       pool.push_back(r.a);
       pool.push_back(r.b);
@@ -571,11 +581,7 @@ static Profiler& profiler() {
   return *p;
 }
 
-static bool profiled_stage(Stage st) {
-  return st == kCgInit1 || st == kCgInit2 || st == kCgA || st == kCgB || st == kMrInit || st == kMrPass ||
-         st == kXfExtrap || st == kXfQuad || st == kXfLinear || st == kXfSmooth || st == kXfPm || st == kXfFused ||
-         st == kXfFusedSmall || st == kCoarse || st == kCgBD;
-}
+static bool profiled_stage(Stage st) { return st >= 0 && st < kNumStages; }
 
 // ---------------------------------------------------------------------------
 // Jobs and the engine
@@ -1277,7 +1283,11 @@ class Engine {
       chk(hipEventRecord(a, stream_));
       chk(launch_stage(st, f64, variant, ll, d_desc_, src, dst, stream_));
       chk(hipEventRecord(b, stream_));
-      Profiler::Rec rec{(int)st, a, b, px, {}};
+      // the level the launch works on (restriction and output copy: none)
+      int lvl = (st == kRestrict || st == kOutCopy || jobs.empty()) ? -1 : level_of(0);
+      for (size_t i = 1; i < jobs.size() && lvl >= 0; ++i)
+        if (level_of(i) != lvl) lvl = -1;
+      Profiler::Rec rec{(int)st, a, b, px, {}, lvl};
       if (kidx)
         for (size_t i = 0; i < jobs.size(); ++i)
           rec.tags.push_back({jobs[i]->uid, jobs[i]->cur_level(), (*kidx)[i], st == kMrPass});
@@ -1602,7 +1612,30 @@ int eecmg_profile_reset(void) {
     p.ms[i] = 0.0;
     p.pixels[i] = 0.0;
   }
+  for (int l = 0; l < kMaxLevels; ++l)
+    for (int i = 0; i < kNumStages; ++i) {
+      p.lv_launches[l][i] = 0;
+      p.lv_ms[l][i] = 0.0;
+    }
   p.final_iters.clear();
+  return EECMG_OK;
+}
+
+int eecmg_profile_read_level(int stage, int level, int* launches, double* total_ms) {
+  if (stage < -1 || stage >= kNumStages) return fail(EECMG_EINVAL, "unknown stage id");
+  if (level < 0 || level >= kMaxLevels) return fail(EECMG_EINVAL, "level out of range");
+  Profiler& p = profiler();
+  std::lock_guard<std::mutex> g(p.mu);
+  p.harvest();
+  int n = 0;
+  double ms = 0.0;
+  for (int i = 0; i < kNumStages; ++i)
+    if (stage == -1 || stage == i) {
+      n += p.lv_launches[level][i];
+      ms += p.lv_ms[level][i];
+    }
+  if (launches) *launches = n;
+  if (total_ms) *total_ms = ms;
   return EECMG_OK;
 }
 

@@ -99,6 +99,7 @@ def lib():
         "eecmg_profile_min_pixels": [d],
         "eecmg_profile_reset": [],
         "eecmg_profile_read": [i, ip, dp, dp],
+        "eecmg_profile_read_level": [i, i, ip, dp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -376,9 +377,11 @@ def transfer_dev(ub, HC, WC, prolongation="quad", smooth_h=1.0, pm_steps=1, k=10
 
 
 # ------------------------------------------------------------ kernel timing
-STAGES = {"cg_init_r": 1, "cg_init_s": 2, "cg_pass_a": 4, "cg_pass_b": 6, "mr_init": 8, "mr_pass": 10,
+STAGES = {"restrict": 0, "cg_init_r": 1, "cg_init_s": 2, "cg_fin_init": 3, "cg_pass_a": 4, "cg_fin_a": 5,
+          "cg_pass_b": 6, "cg_fin_b": 7, "mr_init": 8, "mr_fin_init": 9, "mr_pass": 10, "mr_fin": 11,
           "extrapolate": 12, "prolong_quad": 13, "prolong_linear": 14, "local_smooth": 15, "pm_step": 16,
-          "transfer_fused": 18, "coarse": 20, "cg_pass_b_dconv": 22}
+          "out_copy": 17, "transfer_fused": 18, "transfer_fused_small": 19, "coarse": 20, "flush_u": 21,
+          "cg_pass_b_dconv": 22}
 
 
 def profile_enable(enable=True, min_blocks=0, min_pixels=0.0):
@@ -398,6 +401,15 @@ def profile_read(stage):
     sid = STAGES[stage] if isinstance(stage, str) else int(stage)
     _check(lib().eecmg_profile_read(sid, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(px)))
     return n.value, ms.value, px.value
+
+
+def profile_read_level(level, stage=None):
+    """(launches, total_ms) of the launches working on level index `level`
+    (0 = coarsest) since the last reset: one stage, or all (stage None)."""
+    n, ms = ctypes.c_int(), ctypes.c_double()
+    sid = -1 if stage is None else (STAGES[stage] if isinstance(stage, str) else int(stage))
+    _check(lib().eecmg_profile_read_level(sid, int(level), ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
 
 
 # ------------------------------------------------------------ request loop
