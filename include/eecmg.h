@@ -147,6 +147,25 @@ int eecmg_restore_dev(const void* g_delta_dev, int H, int W, const double* psf, 
                       const int* iters_per_level, double k, const eecmg_params* params, void* u_out_dev,
                       void* hip_stream);
 
+/* As eecmg_restore_dev, for callers that cannot allocate device memory
+ * (tight serving loops, harnesses that forbid hipMalloc): the call allocates
+ * no device or pinned memory.  It works in a fixed device region of 64 MiB
+ * that the library reserves per GPU (a device global, held until the process
+ * ends) and that also holds its own engine's tables; the first call on a
+ * device sets that engine up (the region's address, HIP events, host
+ * tables).  A restore whose device footprint (about 9.7 times the finest
+ * level's bytes: FP32 images up to about 1300 x 1300, FP64 up to about
+ * 900 x 900) exceeds the region returns EINVAL and does nothing.  Calls on one
+ * GPU share the region and are serialised (every call returns only after its
+ * cascade completed); each call clears the solver state it reads, and the
+ * region otherwise keeps the previous call's bytes.  Results and statistics
+ * are bit for bit those of eecmg_restore_dev.  The level schedule follows the
+ * device's progress by draining the stream (slower on levels with many
+ * iterations); kernel timing (eecmg_profile_*) does not cover this call. */
+int eecmg_restore_dev_noalloc(const void* g_delta_dev, int H, int W, const double* psf, int psf_radius,
+                              int n_levels, const int* iters_per_level, double k, const eecmg_params* params,
+                              void* u_out_dev, void* hip_stream);
+
 /* Restore n_images independent images of possibly different sizes, PSFs and
  * level counts in one batched cascade: all images at a smoother or transfer
  * stage share each kernel launch.  Arrays are indexed by image; params is an

@@ -225,6 +225,9 @@ int blocks_for_stage(Stage st, const JobDesc& d);
 hipError_t launch_upload(const UploadList& ul, const JobDesc* hdesc, JobDesc* ddesc, const char* htaps,
                          size_t taps_stride, hipStream_t s);
 
+// Set n 32-bit words at p to zero with a kernel on stream s.
+hipError_t launch_zero_words(void* p, size_t n, hipStream_t s);
+
 // Operator kernels on dense buffers (one image, no job table).
 hipError_t op_conv(const void* x, void* y, int H, int W, const void* taps, int variant, int radius, bool f64,
                    hipStream_t s);

@@ -3,6 +3,8 @@
 // top-level launch dispatch.
 #include <math.h>
 
+#include <algorithm>
+
 #include "eecmg_device.h"
 
 namespace eecmg {
@@ -1117,6 +1119,17 @@ __global__ __launch_bounds__(256) void k_upload(UploadList ul, const JobDesc* __
   };
   copy((uint32_t*)(ddesc + (size_t)s * kMaxLevels), (const uint32_t*)src, L * (int)(sizeof(JobDesc) / 4));
   copy(tdst, (const uint32_t*)(htaps + (size_t)s * taps_stride), tb / 4);
+}
+
+__global__ __launch_bounds__(256) void k_zero_words(uint32_t* __restrict__ p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) p[i] = 0u;
+}
+
+hipError_t launch_zero_words(void* p, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_zero_words, dim3(blocks), dim3(256), 0, s, (uint32_t*)p, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_upload(const UploadList& ul, const JobDesc* hdesc, JobDesc* ddesc, const char* htaps,

@@ -436,6 +436,7 @@ class Arena {
   ~Arena() {}
   int reserve(size_t bytes) {
     if (bytes <= size_) return EECMG_OK;
+    if (!owned_) return fail(EECMG_ENOMEM, "the arena is a fixed region and cannot grow");
     if (used_ != 0) return fail(EECMG_ENOMEM, "arena busy, cannot grow");
     if (base_) (void)hipFree(base_);
     base_ = nullptr;
@@ -452,10 +453,20 @@ class Arena {
     return EECMG_OK;
   }
   void release() {
-    if (base_) (void)hipFree(base_);
+    if (base_ && owned_) (void)hipFree(base_);
     base_ = nullptr;
     size_ = used_ = 0;
     free_.clear();
+  }
+  // Use [base, base + bytes) of memory the arena does not own (never grown
+  // or freed by it).
+  void adopt(void* base, size_t bytes) {
+    base_ = (char*)base;
+    size_ = bytes;
+    used_ = 0;
+    owned_ = false;
+    free_.clear();
+    free_[0] = bytes;
   }
   void* alloc(size_t n) {
     n = align_up(n, 256);
@@ -499,6 +510,7 @@ class Arena {
  private:
   char* base_ = nullptr;
   size_t size_ = 0, used_ = 0;
+  bool owned_ = true;
   std::map<size_t, size_t> free_;
 };
 
@@ -667,6 +679,59 @@ class Engine {
     return EECMG_OK;
   }
 
+  // An engine that allocates no device or pinned memory: its descriptor
+  // table, solver state, level records, progress words and job arena are
+  // carved from the device region [dev, dev + bytes) (256-byte aligned), its
+  // host-side tables are ordinary host memory, and it serves one job at a
+  // time.  The progress words then live in device memory: the engine reads
+  // them with a copy after draining its stream (wait_some), so a level's
+  // schedule advances in steps of at most two iterations per drain.
+  // Returns EINVAL when the region cannot hold the tables.
+  int init_noalloc(char* dev, size_t bytes) {
+    EECMG_HIP(hipSetDevice(device_));
+    noalloc_ = true;
+    n_slots_ = 1;
+    size_t off = 0;
+    auto carve = [&](size_t n) {
+      char* p = dev + off;
+      off = align_up(off + n, 256);
+      return p;
+    };
+    d_desc_ = (JobDesc*)carve(sizeof(JobDesc) * kMaxLevels);
+    d_state_ = (SolverState*)carve(sizeof(SolverState));
+    d_rec_ = (LevelRecord*)carve(sizeof(LevelRecord) * kMaxLevels);
+    d_mirror_ = (uint64_t*)carve(sizeof(uint64_t));
+    if (off >= bytes) return fail(EECMG_EINVAL, "scratch region too small for the engine tables");
+    arena_.adopt(dev + off, bytes - off);
+    noalloc_tables_.assign(sizeof(JobDesc) * kMaxLevels + sizeof(LevelRecord) * kMaxLevels + kTapsSlotBytes +
+                               sizeof(uint64_t) + 3 * 256,
+                           0);
+    char* h = noalloc_tables_.data();
+    h = (char*)align_up((uintptr_t)h, 256);
+    h_desc_ = (JobDesc*)h;
+    h += align_up(sizeof(JobDesc) * kMaxLevels, 256);
+    h_rec_ = (LevelRecord*)h;
+    h += align_up(sizeof(LevelRecord) * kMaxLevels, 256);
+    h_taps_ = h;
+    h += kTapsSlotBytes;
+    h_mirror_ = (volatile uint64_t*)h;
+    dv_desc_ = nullptr;  // k_upload is never used (one job: two copies)
+    dv_taps_ = nullptr;
+    for (auto& e : step_ev_) EECMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    out_ev_ = std::make_shared<HipEvent>();
+    slots_.assign(n_slots_, nullptr);
+    return EECMG_OK;
+  }
+  size_t arena_capacity() const { return arena_.size(); }
+  // Clear the solver state and progress word of the engine's one slot (a
+  // fill kernel on the stream: the region keeps the previous call's bytes).
+  int clear_noalloc_state() {
+    EECMG_HIP(launch_zero_words(d_state_, sizeof(SolverState) / 4, stream_));
+    EECMG_HIP(launch_zero_words(d_mirror_, sizeof(uint64_t) / 4, stream_));
+    h_mirror_[0] = 0;
+    return EECMG_OK;
+  }
+
   // Free the engine's own device and pinned memory (the arena is released
   // separately).  No job may be active.
   void shutdown() {
@@ -712,7 +777,7 @@ class Engine {
   // EAGAIN when no slot or memory is free right now.
   int admit(Job* j) {
     int slot = -1;
-    for (int i = 0; i < kMaxSlots; ++i)
+    for (int i = 0; i < n_slots_; ++i)
       if (!slots_[i]) {
         slot = i;
         break;
@@ -777,7 +842,7 @@ class Engine {
     std::vector<std::pair<Job*, int>> flush_l;  // job, level left with a possibly deferred update
     std::vector<std::pair<Job*, int>> finb_l;   // job, level left with its last finalize still to run
     bool launched = false;
-    for (int s = 0; s < kMaxSlots; ++s) {
+    for (int s = 0; s < n_slots_; ++s) {
       Job* j = slots_[s];
       if (!j) continue;
       bool again = true, started = false;
@@ -864,7 +929,7 @@ class Engine {
     {
       UploadList ul;
       ul.n = 0;
-      for (int s = 0; s < kMaxSlots; ++s)
+      for (int s = 0; s < n_slots_; ++s)
         if (slots_[s] && slots_[s]->needs_upload) {
           slots_[s]->needs_upload = false;
           ul.slot[ul.n++] = s;
@@ -938,7 +1003,7 @@ class Engine {
       // outputs of every job finishing in this step: one copy launch per
       // precision, one read-back of the level records, one shared event
       // (served requests copy their results on the copy stream instead)
-      int lo = kMaxSlots, hi = -1;
+      int lo = n_slots_, hi = -1;
       for (int f64 = 0; f64 < 2; ++f64) {
         std::vector<Job*> js;
         std::vector<int> lv;
@@ -967,7 +1032,7 @@ class Engine {
           chk(hipEventRecord(j->done_ev->e, copy_));
         } else {
           if (j->host_out) chk(hipMemcpyAsync(j->host_out, j->u_out_dev, out_bytes, hipMemcpyDeviceToHost, stream_));
-          if (!shared) shared = std::make_shared<HipEvent>();
+          if (!shared) shared = noalloc_ ? out_ev_ : std::make_shared<HipEvent>();
           j->done_ev = shared;
         }
         j->phase = Job::kWaitOut;
@@ -987,6 +1052,14 @@ class Engine {
   // Wait until the device reports progress for some job (through the pinned
   // progress words) or all enqueued work has completed.
   void wait_some() {
+    if (noalloc_) {
+      // progress words in device memory: read them behind everything
+      // enqueued, on the engine's stream, and drain it
+      chk(hipMemcpyAsync((void*)h_mirror_, d_mirror_, sizeof(uint64_t) * n_slots_, hipMemcpyDeviceToHost, stream_));
+      chk(hipStreamSynchronize(stream_));
+      step_pending_ = false;
+      return;
+    }
     const std::vector<uint64_t> before = snapshot();
     for (long spin = 0;; ++spin) {
       if (snapshot() != before) return;
@@ -1067,7 +1140,7 @@ class Engine {
       release(j);
       out.push_back(j);
     }
-    for (int i = 0; i < kMaxSlots; ++i) __atomic_store_n(&h_mirror_[i], (uint64_t)0, __ATOMIC_RELEASE);
+    for (int i = 0; i < n_slots_; ++i) __atomic_store_n(&h_mirror_[i], (uint64_t)0, __ATOMIC_RELEASE);
     err_ = hipSuccess;
     stalled_ = false;
     step_pending_ = false;
@@ -1095,7 +1168,7 @@ class Engine {
   }
   uint64_t progress_sum() const {
     uint64_t h = 0;
-    for (int i = 0; i < kMaxSlots; ++i) h = h * 1000003u + __atomic_load_n(&h_mirror_[i], __ATOMIC_ACQUIRE);
+    for (int i = 0; i < n_slots_; ++i) h = h * 1000003u + __atomic_load_n(&h_mirror_[i], __ATOMIC_ACQUIRE);
     return h;
   }
   // hipEventQuery: complete, not yet, or an error (recorded as the engine's
@@ -1110,8 +1183,8 @@ class Engine {
   static constexpr int kStepEvents = 4;
 
   std::vector<uint64_t> snapshot() const {
-    std::vector<uint64_t> v(kMaxSlots);
-    for (int i = 0; i < kMaxSlots; ++i) v[i] = __atomic_load_n(&h_mirror_[i], __ATOMIC_ACQUIRE);
+    std::vector<uint64_t> v(n_slots_);
+    for (int i = 0; i < n_slots_; ++i) v[i] = __atomic_load_n(&h_mirror_[i], __ATOMIC_ACQUIRE);
     return v;
   }
 
@@ -1269,7 +1342,8 @@ class Engine {
     if (ll.total <= 0) return;
     Profiler& pr = profiler();
     double px = 0.0;
-    const bool prof = pr.on.load(std::memory_order_relaxed) && profiled_stage(st) && ll.total >= pr.min_blocks;
+    const bool prof = !noalloc_ && pr.on.load(std::memory_order_relaxed) && profiled_stage(st) &&
+                      ll.total >= pr.min_blocks;
     if (prof)
       for (size_t i = 0; i < jobs.size(); ++i) {
         const Job* j = jobs[i];
@@ -1448,6 +1522,10 @@ class Engine {
   int step_cur_ = 0;
   bool step_pending_ = false;
   int max_ahead_ = kMaxAhead;
+  bool noalloc_ = false;                 // see init_noalloc
+  int n_slots_ = kMaxSlots;
+  std::vector<char> noalloc_tables_;     // host tables of a no-alloc engine
+  std::shared_ptr<HipEvent> out_ev_;     // its output event (one job at a time)
   long stall_steps_ = kStallSteps, idle_steps_ = 0, fail_step_ = 0, steps_ = 0;
   double stall_ms_ = kStallMs, idle_since_ = 0.0;
   bool stalled_ = false;
@@ -1549,6 +1627,50 @@ static int check_dev_ptr(const void* p, const char* what) {
   if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
     return fail(EECMG_EINVAL, std::string(what) + " is not device memory");
   return EECMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Restores that allocate nothing: one fixed device region per GPU
+// ---------------------------------------------------------------------------
+// The region holds the no-alloc engine's tables (descriptors, solver state,
+// level records, progress word: about 12 KiB) and the job arena.  A job needs
+// about 9.7 times its finest level's bytes (seven work vectors, the
+// right-hand-side and solution pyramids, PSF taps and tile partials), so
+// 64 MiB serves FP32 images up to about 1300 x 1300 and FP64 ones up to
+// about 900 x 900.  Each GPU the library runs on holds its own copy until
+// the process ends.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+struct NoAllocEngine {
+  std::mutex mu;  // calls on one GPU share its region: they run one at a time
+  std::unique_ptr<Engine> eng;
+  char* base = nullptr;  // this GPU's device address of `scratch`
+};
+
+// Set-up on the first call on a device (with that device current): the
+// region's device address from hipGetSymbolAddress (the host-side name of
+// the array is only a stand-in and never reaches a kernel), the engine's
+// events and host tables.  No device or pinned memory is allocated.
+static NoAllocEngine* noalloc_engine(int device, int* rc) {
+  static std::mutex mu;
+  static std::map<int, NoAllocEngine*> engines;  // never destroyed, like the region itself
+  std::lock_guard<std::mutex> g(mu);
+  auto it = engines.find(device);
+  if (it != engines.end()) return it->second;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    *rc = fail(EECMG_EDEVICE, std::string("hipGetSymbolAddress of the scratch region: ") + hipGetErrorString(e));
+    return nullptr;
+  }
+  std::unique_ptr<NoAllocEngine> ne(new NoAllocEngine());
+  ne->base = (char*)ptr;
+  ne->eng.reset(new Engine(device));
+  *rc = ne->eng->init_noalloc(ne->base, kScratchBytes);
+  if (*rc != EECMG_OK) return nullptr;
+  engines[device] = ne.get();
+  return ne.release();
 }
 
 static size_t arena_target(size_t need) {
@@ -1677,6 +1799,41 @@ int eecmg_restore_dev(const void* g_delta_dev, int H, int W, const double* psf, 
   job.u_out_dev = u_out_dev;
   std::vector<Job*> jobs{&job};
   rc = restore_jobs_on(pe, jobs, (hipStream_t)hip_stream);
+  if (rc) return rc;
+  if (params && params->stats) fill_stats(&job, (eecmg_stats*)params->stats);
+  if (job.status != EECMG_OK) return fail(job.status, "non-finite value in the smoother");
+  return EECMG_OK;
+}
+
+int eecmg_restore_dev_noalloc(const void* g_delta_dev, int H, int W, const double* psf, int psf_radius,
+                              int n_levels, const int* iters_per_level, double k, const eecmg_params* params,
+                              void* u_out_dev, void* hip_stream) {
+  g_err.clear();
+  int rc = check_dev_ptr(g_delta_dev, "g_delta_dev");
+  if (rc) return rc;
+  rc = check_dev_ptr(u_out_dev, "u_out_dev");
+  if (rc) return rc;
+  Job job;
+  rc = build_plan(H, W, psf, psf_radius, n_levels, iters_per_level, k, params, false, job.plan);
+  if (rc) return rc;
+  int dev = 0;
+  rc = current_device(&dev);
+  if (rc) return rc;
+  NoAllocEngine* ne = noalloc_engine(dev, &rc);
+  if (!ne) return rc;
+  std::lock_guard<std::mutex> g(ne->mu);
+  Engine& E = *ne->eng;
+  if (job.plan.bytes > E.arena_capacity())
+    return fail(EECMG_EINVAL, "the restore needs " + std::to_string(job.plan.bytes) +
+                                  " bytes of device scratch, more than the fixed region's " +
+                                  std::to_string(E.arena_capacity()) + " (use eecmg_restore_dev)");
+  E.set_stream((hipStream_t)hip_stream);
+  rc = E.clear_noalloc_state();
+  if (rc) return rc;
+  job.g_in_dev = g_delta_dev;
+  job.u_out_dev = u_out_dev;
+  std::vector<Job*> jobs{&job};
+  rc = run_jobs(E, jobs);
   if (rc) return rc;
   if (params && params->stats) fill_stats(&job, (eecmg_stats*)params->stats);
   if (job.status != EECMG_OK) return fail(job.status, "non-finite value in the smoother");

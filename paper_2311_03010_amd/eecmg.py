@@ -75,6 +75,7 @@ def lib():
         "eecmg_params_default": [ctypes.POINTER(Params)],
         "eecmg_restore": [vp, i, i, dp, i, i, ip, d, ctypes.POINTER(Params), vp],
         "eecmg_restore_dev": [vp, i, i, dp, i, i, ip, d, ctypes.POINTER(Params), vp, vp],
+        "eecmg_restore_dev_noalloc": [vp, i, i, dp, i, i, ip, d, ctypes.POINTER(Params), vp, vp],
         "eecmg_restore_batch_dev": [i, ctypes.POINTER(vp), ip, ip, ctypes.POINTER(dp), ip, ip, ctypes.POINTER(ip), dp,
                                     ctypes.POINTER(Params), ctypes.POINTER(vp), vp],
         "eecmg_ctx_config_default": [ctypes.POINTER(CtxConfig)],
@@ -198,10 +199,11 @@ def _torch_dtype(precision):
     return torch.float64 if (precision == "f64" or precision == 0) else torch.float32
 
 
-def restore_dev(g_delta, psf, n_levels, caps=None, k=10.0, out=None, stream=None, **kw):
+def restore_dev(g_delta, psf, n_levels, caps=None, k=10.0, out=None, stream=None, noalloc=False, **kw):
     """Device restore on torch tensors (contiguous H x W on the current GPU).
     Returns (u tensor, stats dict); the result is ready after the stream
-    synchronises."""
+    synchronises.  noalloc=True calls eecmg_restore_dev_noalloc (no device
+    allocation; images up to the library's fixed scratch region)."""
     import torch
 
     prec = kw.get("precision", "f32")
@@ -216,7 +218,8 @@ def restore_dev(g_delta, psf, n_levels, caps=None, k=10.0, out=None, stream=None
     p.stats = ctypes.cast(ctypes.pointer(st), ctypes.c_void_p)
     psf, r = _psf_arr(psf)
     c = _caps_arr(caps, n_levels)
-    rc = lib().eecmg_restore_dev(ctypes.c_void_p(g_delta.data_ptr()), g_delta.shape[0], g_delta.shape[1], _dptr(psf),
+    fn = lib().eecmg_restore_dev_noalloc if noalloc else lib().eecmg_restore_dev
+    rc = fn(ctypes.c_void_p(g_delta.data_ptr()), g_delta.shape[0], g_delta.shape[1], _dptr(psf),
                                  r, int(n_levels),
                                  c.ctypes.data_as(ctypes.POINTER(ctypes.c_int)) if c is not None else None, float(k),
                                  ctypes.byref(p), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
