@@ -908,16 +908,28 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
   const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
   const JobDesc& d = descs[L.d];
   const SolverState* st = d.st;
-  if (__builtin_amdgcn_readfirstlane(st->done)) return;
+  // with kLaunchFoldB every block of an entry that owes a finalize (kf >= 0)
+  // evaluates it from its job's partials, in the finalize kernel's order: the
+  // previous pass B's, or at iteration 0 the initialisation's.  The stop
+  // decision and beta are then identical everywhere; logical tile 0 records
+  // them.  The iteration index comes from the launch list.
+  const int kf = (uni(d.fold_a) && (ll.flags & kLaunchFoldB)) ? uni(ll.kf[L.e]) : -1;
+  const bool foldb = kf >= 0;
+  // iteration 0 with the initialisation's finalize starts the level here: the
+  // solver state still holds the previous level's stop, so it is not consulted
+  const bool finit = kf == 0;
+  if (!finit && __builtin_amdgcn_readfirstlane(st->done)) return;
   const TileGeo g = tile_geo<P>(d, L.t);
-  // with kLaunchFoldB (one job per launch) every block evaluates the
-  // previous pass B's finalize from its partials, in the finalize kernel's
-  // order: the stop decision and beta are identical everywhere; logical tile
-  // 0 records them.  The iteration index comes from the launch.
-  const bool foldb = uni(d.fold_a) && (ll.flags & kLaunchFoldB);
-  const int k = foldb ? ll.k0 : uni(st->k);
+  const int k = foldb ? kf : uni(st->k);
   T beta;
-  if (foldb && k > 0) {
+  if (finit) {
+    double v[2];
+    sum_partials<2, P::NT>(d.partials, uni(d.ntiles), d.pstride, kCompCgInit, v);
+    const int reason = stop_reason(d, 0, v[0], v[1], v[1], !finite_d(v[0]) || !finite_d(v[1]));
+    if (L.t == 0 && threadIdx.x == 0) fin_cg_init(d, d.st, v);
+    if (reason != kStopNone) return;
+    beta = T(0);
+  } else if (foldb && k > 0) {
     double v[2];
     sum_partials<2, P::NT>(d.partials, uni(d.dconv) ? uni(d.ntiles_b) : uni(d.ntiles), d.pstride, kCompCgB, v);
     const int reason = stop_reason(d, k, v[0], v[1], st->gamma0, !finite_d(v[0]) || !finite_d(v[1]));

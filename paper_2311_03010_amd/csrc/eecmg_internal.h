@@ -120,19 +120,22 @@ __host__ __device__ inline uint64_t mirror_word(uint32_t tag, int32_t k, int32_t
 // Kernel-argument list of the jobs one launch covers.  Block b belongs to the
 // entry e with start[e] <= b < start[e+1]; job[e] indexes the JobDesc table.
 // Launch options (LaunchList::flags).
-// kLaunchFoldA: pass B evaluates pass A's finalize; kLaunchFoldB: pass A
-// evaluates the previous pass B's finalize (single-job launches, iteration
-// index k0).  Both only for jobs whose level has fold_a set.
+// kLaunchFoldA: pass B evaluates pass A's finalize; kLaunchFoldB: pass A of
+// entry e evaluates the finalize still owed before iteration kf[e] (the
+// previous pass B's, or at iteration 0 the initialisation's); kf[e] < 0: none
+// is owed.  Both only for jobs whose level has fold_a set.
 enum : int32_t { kLaunchFoldA = 1, kLaunchFoldB = 2 };
 
 struct LaunchList {
   int32_t n;
   int32_t total;
   int32_t flags;
-  int32_t k0;
+  int32_t pad;
   int32_t job[kMaxLaunchJobs];
   int32_t start[kMaxLaunchJobs + 1];
+  int32_t kf[kMaxLaunchJobs];  // per entry: iteration index of a folded finalize, or -1
 };
+static_assert(sizeof(LaunchList) + 64 <= 4096, "kernel arguments stay below 4 KiB");
 
 // Stages launched by the runtime.
 enum Stage : int32_t {

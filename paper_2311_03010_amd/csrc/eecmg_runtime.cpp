@@ -628,7 +628,9 @@ struct Job {
   uint32_t uid = 0;           // engine-assigned id, part of the progress tag
   std::shared_ptr<struct HipEvent> done_ev;  // output complete (shared by jobs finishing in one step)
   bool needs_upload = false;                  // descriptors and taps still in pinned host memory
-  bool fin_b_pending = false;                 // the last issued pass B has no finalize yet (see kLaunchFoldB)
+  // a finalize the job still owes on its level (see kLaunchFoldB): that of
+  // its initialisation or of its last issued pass B
+  enum Owed { kOwesNone = 0, kOwesInit = 1, kOwesB = 2 } owed = kOwesNone;
   // served requests: the input copy runs on the context's copy stream; the
   // first kernel of the job waits for in_ev, the output copy for comp_ev
   hipEvent_t in_ev = nullptr, comp_ev = nullptr;
@@ -841,6 +843,7 @@ class Engine {
     std::vector<std::pair<Job*, int>> iter_l;  // job, chunk
     std::vector<std::pair<Job*, int>> flush_l;  // job, level left with a possibly deferred update
     std::vector<std::pair<Job*, int>> finb_l;   // job, level left with its last finalize still to run
+    std::vector<std::pair<Job*, int>> fini_l;   // job, level left before its first iteration, init owed
     bool launched = false;
     for (int s = 0; s < n_slots_; ++s) {
       Job* j = slots_[s];
@@ -888,10 +891,12 @@ class Engine {
             // more pass, because its first pass only forms q = H r
             const int limit = j->plan.lv[j->cur_level()].cap + (j->plan.prm.smoother == EECMG_SMOOTHER_MR ? 1 : 0);
             if (j->cancelled || j->level_done_seen || j->issued >= limit) {
-              if (j->fin_b_pending) {
-                finb_l.push_back({j, j->cur_level()});
-                j->fin_b_pending = false;
-              }
+              // the last pass B's finalize is still owed -- unless the stop was
+              // already seen: that finalize would then find the level stopped
+              // and do nothing
+              if (j->owed == Job::kOwesB && !j->level_done_seen) finb_l.push_back({j, j->cur_level()});
+              if (j->owed == Job::kOwesInit && !j->cancelled) fini_l.push_back({j, j->cur_level()});
+              j->owed = Job::kOwesNone;
               if (lazy_level(j, j->cur_level())) flush_l.push_back({j, j->cur_level()});
               if (!j->cancelled && j->oi + 1 < (int)j->plan.order.size()) {
                 j->oi += 1;
@@ -965,12 +970,18 @@ class Engine {
       }
       launched = true;
     }
-    for (auto& x : finb_l) {
-      // the finalize of the level's last pass B (its records, stop reason and
-      // iteration count; a level that already stopped leaves it unchanged)
-      std::vector<Job*> one{x.first};
-      std::vector<int> lv{x.second};
-      launch_group(kCgFinB, one, -1, x.first->plan.f64, 0, -1, -1, nullptr, &lv);
+    for (auto* fl : {&fini_l, &finb_l}) {
+      // the finalize of each level's last pass B (its records, stop reason and
+      // iteration count; a level that already stopped leaves it unchanged),
+      // or of an initialisation no iteration followed
+      if (fl->empty()) continue;
+      std::vector<Job*> js;
+      std::vector<int> lv;
+      for (auto& x : *fl) {
+        js.push_back(x.first);
+        lv.push_back(x.second);
+      }
+      launch_group(fl == &fini_l ? kCgFinInit : kCgFinB, js, -1, false, 0, -1, -1, nullptr, &lv);
       launched = true;
     }
     if (!flush_l.empty()) {
@@ -1316,12 +1327,12 @@ class Engine {
   // splitting by nothing: caller groups jobs of one precision / variant.
   void launch_group(Stage st, const std::vector<Job*>& jobs, int level, bool f64, int variant, int src, int dst,
                     const std::vector<int>* kidx = nullptr, const std::vector<int>* levels = nullptr,
-                    int flags = 0) {
+                    int flags = 0, const std::vector<int>* kfold = nullptr) {
     LaunchList ll;
     ll.n = 0;
     ll.total = 0;
     ll.flags = flags;
-    ll.k0 = kidx && !kidx->empty() ? (*kidx)[0] : 0;
+    ll.pad = 0;
     auto level_of = [&](size_t i) { return levels ? (*levels)[i] : level >= 0 ? level : jobs[i]->cur_level(); };
     for (size_t i = 0; i < jobs.size(); ++i) {
       Job* j = jobs[i];
@@ -1333,6 +1344,7 @@ class Engine {
       const int di = j->slot * kMaxLevels + l;
       const JobDesc& hd = h_desc_[di];
       ll.job[ll.n] = di;
+      ll.kf[ll.n] = kfold ? (*kfold)[i] : -1;
       ll.start[ll.n] = ll.total;
       ll.total += blocks_for_stage(st, hd);
       ll.n += 1;
@@ -1410,74 +1422,116 @@ class Engine {
     if (!jobs.empty()) launch_group(st, jobs, -1, jobs.front()->plan.f64, 0, -1, -1);
   }
 
+  // The initialisation of each group's level, then one finalize launch for
+  // the jobs whose level cannot fold it into its first pass A (see
+  // issue_iterations); the others owe it.
   void issue_inits(const std::vector<Job*>& js) {
     std::map<std::pair<int, int>, std::vector<Job*>> groups;  // (smoother, variant)
     for (Job* j : js) groups[{j->plan.prm.smoother, variant_key(j)}].push_back(j);
+    std::vector<Job*> fin_cg, fin_mr;
     for (auto& kv : groups) {
       const bool f64 = kv.first.second >= 100000;
       const int rc = kv.first.second % 100000;
       if (kv.first.first == EECMG_SMOOTHER_CGLS) {
         launch_group(kCgInit1, kv.second, -1, f64, rc, -1, -1);
         launch_group(kCgInit2, kv.second, -1, f64, rc, -1, -1);
-        launch_fin(kCgFinInit, kv.second);
+        for (Job* j : kv.second) {
+          const LevelPlan& lp = j->plan.lv[j->cur_level()];
+          if (lp.fold_a && lp.cap >= 1)
+            j->owed = Job::kOwesInit;
+          else
+            fin_cg.push_back(j);
+        }
       } else {
         launch_group(kMrInit, kv.second, -1, f64, rc, -1, -1);
-        launch_fin(kMrFinInit, kv.second);
+        fin_mr.insert(fin_mr.end(), kv.second.begin(), kv.second.end());
       }
     }
+    launch_fin(kCgFinInit, fin_cg);
+    launch_fin(kMrFinInit, fin_mr);
   }
 
+  // One round of iterations per chunk index.  Jobs are grouped by smoother
+  // and blur kernel.  A CGLS group of a single job on a fold_a level folds
+  // its finalizes into the passes: its pass B evaluates pass A's finalize,
+  // and its next pass A the one it owes (the previous pass B's, or at
+  // iteration 0 the initialisation's).  A launch shared by several jobs does
+  // not fold (every block would repeat its job's whole partial sum, which
+  // costs more than the one finalize launch all of them share): the
+  // finalizes such jobs owe are launched first, then every group's pass A,
+  // one finalize launch for the groups that do not fold, every pass B and
+  // again one finalize launch.  The finalize kernels are precision- and
+  // kernel-independent, so one launch serves jobs of every group.
   void issue_iterations(const std::vector<std::pair<Job*, int>>& its) {
     int maxc = 0;
     for (auto& x : its) maxc = std::max(maxc, x.second);
     for (int it = 0; it < maxc; ++it) {
-      std::map<std::pair<int, int>, std::vector<Job*>> groups;
-      std::map<std::pair<int, int>, std::vector<int>> kidx;  // iteration index per job
+      struct Group {
+        std::vector<Job*> js;
+        std::vector<int> ks;  // iteration index per job
+        bool fold = false;
+      };
+      std::map<std::pair<int, int>, Group> groups;  // (smoother, variant)
       for (auto& x : its)
         if (x.second > it) {
-          const std::pair<int, int> key{x.first->plan.prm.smoother, variant_key(x.first)};
-          groups[key].push_back(x.first);
-          kidx[key].push_back(x.first->issued - x.second + it);
+          Group& g = groups[{x.first->plan.prm.smoother, variant_key(x.first)}];
+          g.js.push_back(x.first);
+          g.ks.push_back(x.first->issued - x.second + it);
         }
+      std::vector<Job*> owe_init, owe_b;
       for (auto& kv : groups) {
-        const bool f64 = kv.first.second >= 100000;
-        const int rc = kv.first.second % 100000;
-        const std::vector<int>* ki = &kidx[kv.first];
-        if (kv.first.first == EECMG_SMOOTHER_CGLS) {
-          // pass A: a job whose previous pass B went without a finalize runs
-          // alone and evaluates that finalize itself (kLaunchFoldB)
-          std::vector<Job*> rest;
-          std::vector<int> rest_k;
-          for (size_t i = 0; i < kv.second.size(); ++i) {
-            Job* j = kv.second[i];
-            if (j->fin_b_pending) {
-              std::vector<Job*> one{j};
-              std::vector<int> k1{(*ki)[i]};
-              launch_group(kCgA, one, -1, f64, rc, -1, -1, &k1, nullptr, kLaunchFoldB);
-              j->fin_b_pending = false;
-            } else {
-              rest.push_back(j);
-              rest_k.push_back((*ki)[i]);
-            }
-          }
-          if (!rest.empty()) launch_group(kCgA, rest, -1, f64, rc, -1, -1, &rest_k);
-          // fold the finalizes into the passes when the launch is small: each
-          // block then repeats the sum, which pays off only while a separate
-          // launch costs more than that (a launch shared by many jobs does not)
-          bool fold = (int)kv.second.size() <= kFoldMaxJobs;
-          for (Job* j : kv.second) fold = fold && j->plan.lv[j->cur_level()].fold_a;
-          if (!fold) launch_fin(kCgFinA, kv.second);
-          const Stage sb = kv.second.front()->plan.lv[kv.second.front()->cur_level()].dconv ? kCgBD : kCgB;
-          launch_group(sb, kv.second, -1, f64, rc, -1, -1, ki, nullptr, fold ? kLaunchFoldA : 0);
-          if (fold)
-            for (Job* j : kv.second) j->fin_b_pending = true;  // the next pass A, or the level end, runs it
-          else
-            launch_fin(kCgFinB, kv.second);
-        } else {
-          launch_group(kMrPass, kv.second, -1, f64, rc, -1, -1, ki);
-          launch_fin(kMrFin, kv.second);
+        Group& g = kv.second;
+        g.fold = kv.first.first == EECMG_SMOOTHER_CGLS && (int)g.js.size() <= kFoldMaxJobs;
+        for (Job* j : g.js) g.fold = g.fold && j->plan.lv[j->cur_level()].fold_a;
+        if (g.fold) continue;
+        for (Job* j : g.js) {
+          if (j->owed == Job::kOwesInit) owe_init.push_back(j);
+          if (j->owed == Job::kOwesB) owe_b.push_back(j);
+          j->owed = Job::kOwesNone;
         }
       }
+      launch_fin(kCgFinInit, owe_init);
+      launch_fin(kCgFinB, owe_b);
+      std::vector<Job*> fin_a, fin_b, fin_m;
+      for (auto& kv : groups) {
+        if (kv.first.first != EECMG_SMOOTHER_CGLS) continue;
+        const bool f64 = kv.first.second >= 100000;
+        const int rc = kv.first.second % 100000;
+        Group& g = kv.second;
+        if (g.fold) {
+          std::vector<int> kf(g.js.size());
+          for (size_t i = 0; i < g.js.size(); ++i) {
+            kf[i] = g.js[i]->owed == Job::kOwesNone ? -1 : g.ks[i];
+            g.js[i]->owed = Job::kOwesNone;  // evaluated by this pass A
+          }
+          launch_group(kCgA, g.js, -1, f64, rc, -1, -1, &g.ks, nullptr, kLaunchFoldB, &kf);
+        } else {
+          launch_group(kCgA, g.js, -1, f64, rc, -1, -1, &g.ks);
+          fin_a.insert(fin_a.end(), g.js.begin(), g.js.end());
+        }
+      }
+      launch_fin(kCgFinA, fin_a);
+      for (auto& kv : groups) {
+        if (kv.first.first != EECMG_SMOOTHER_CGLS) continue;
+        const bool f64 = kv.first.second >= 100000;
+        const int rc = kv.first.second % 100000;
+        Group& g = kv.second;
+        const Stage sb = g.js.front()->plan.lv[g.js.front()->cur_level()].dconv ? kCgBD : kCgB;
+        launch_group(sb, g.js, -1, f64, rc, -1, -1, &g.ks, nullptr, g.fold ? kLaunchFoldA : 0);
+        if (g.fold)
+          for (Job* j : g.js) j->owed = Job::kOwesB;  // the next pass A, or the level end, runs it
+        else
+          fin_b.insert(fin_b.end(), g.js.begin(), g.js.end());
+      }
+      launch_fin(kCgFinB, fin_b);
+      for (auto& kv : groups) {
+        if (kv.first.first == EECMG_SMOOTHER_CGLS) continue;
+        const bool f64 = kv.first.second >= 100000;
+        const int rc = kv.first.second % 100000;
+        launch_group(kMrPass, kv.second.js, -1, f64, rc, -1, -1, &kv.second.ks);
+        fin_m.insert(fin_m.end(), kv.second.js.begin(), kv.second.js.end());
+      }
+      launch_fin(kMrFin, fin_m);
     }
   }
 
