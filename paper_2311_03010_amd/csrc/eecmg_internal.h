@@ -100,7 +100,7 @@ struct JobDesc {
   int32_t lh[kMaxLevels], lw[kMaxLevels], lp[kMaxLevels];
   // bytes of the job's PSF-taps region (it starts at level 0's taps)
   int32_t taps_bytes;
-  int32_t pad2;
+  int32_t f64;  // element type double (else float)
 };
 
 static_assert(sizeof(JobDesc) % 4 == 0, "descriptors are copied as 32-bit words");

@@ -245,35 +245,26 @@ struct SWeight<float> {
 // Local smoothing S (Section 3.3, eq. 18-19): weighted LS fit of
 // a0 + a1 s + a2 t on the 3x3 window with w = exp(-((u_c - u_n)/h)^2)
 // (exactly 0 beyond (./h)^2 > 30, out-of-image neighbours dropped), output
-// a0.  nb[3 (s+1) + (t+1)] holds the window (any finite value where the
-// neighbour is outside the image); up/down/left/right tell whether rows
-// s = -1 / +1 and columns t = -1 / +1 are inside.  The fit is centred on the
-// pixel value and on the weighted centroid, which leaves a 2x2 system
-// S a = c for the slopes and a0 = u_c + vb - (sb, tb) . a.  A well
-// conditioned S (det > 1e-3 tr^2, so both eigenvalues exceed 1e-3 of the
-// larger) is solved by its adjugate; otherwise through its eigen-decomposition
-// (one Jacobi rotation, no trigonometric calls) with eigenvalues below the
-// compute type's noise level (Ar<C>::kEig of the largest) dropped, so
-// near-collinear weight patterns stay accurate.  The window moments are
-// formed from row and column sums (the offsets are -1, 0, 1).
+// a0.  nb[3 (s+1) + (t+1)] holds the window and w the neighbours' weights
+// (w[4] unused: the centre weighs 1).  The fit is centred on the pixel value
+// and on the weighted centroid, which leaves a 2x2 system S a = c for the
+// slopes and a0 = u_c + vb - (sb, tb) . a.  A well conditioned S
+// (det > 1e-3 tr^2, so both eigenvalues exceed 1e-3 of the larger) is solved
+// by its adjugate; otherwise through its eigen-decomposition (one Jacobi
+// rotation, no trigonometric calls) with eigenvalues below the compute type's
+// noise level (Ar<C>::kEig of the largest) dropped, so near-collinear weight
+// patterns stay accurate.  The window moments are formed from row and column
+// sums (the offsets are -1, 0, 1).
 template <typename C>
-__device__ __forceinline__ C smooth_core(const C (&nb)[9], bool up, bool down, bool left, bool right,
-                                         const SWeight<C>& W) {
+__device__ __forceinline__ C smooth_solve(const C (&nb)[9], const C (&w)[9]) {
+  // no implicit multiply-add contraction: which of two products a sum such
+  // as x y + z t absorbs would otherwise depend on the code around each
+  // inlined copy, and the fused transfer must round as the stage kernels do
+#pragma clang fp contract(off)
   const C uc = nb[4];
-  C w[9], wv[9];
+  C wv[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    if (k == 4) {
-      w[k] = wv[k] = C(0);
-      continue;
-    }
-    const int si = k / 3 - 1, ti = k % 3 - 1;
-    const bool in = (si < 0 ? up : (si > 0 ? down : true)) && (ti < 0 ? left : (ti > 0 ? right : true));
-    const C v = nb[k] - uc;
-    const C wt = W(v, in);
-    w[k] = wt;
-    wv[k] = wt * v;
-  }
+  for (int k = 0; k < 9; ++k) wv[k] = k == 4 ? C(0) : w[k] * (nb[k] - uc);
   const C rA = (w[0] + w[1]) + w[2], rB = (w[6] + w[7]) + w[8];
   const C cL = (w[0] + w[3]) + w[6], cR = (w[2] + w[5]) + w[8];
   const C m00 = ((C(1) + rA) + rB) + (w[3] + w[5]);
@@ -310,6 +301,27 @@ __device__ __forceinline__ C smooth_core(const C (&nb)[9], bool up, bool down, b
     if (l2 > Ar<C>::kEig * lmax && l2 > C(0)) corr += Ar<C>::div((sb * sn + tb * cs) * (c1 * sn + c2 * cs), l2);
   }
   return uc + (vb - corr);
+}
+
+// S of the window nb: the weight of each neighbour from its difference to the
+// centre (up/down/left/right tell whether rows s = -1 / +1 and columns
+// t = -1 / +1 are inside the image; outside ones weigh 0).
+template <typename C>
+__device__ __forceinline__ C smooth_core(const C (&nb)[9], bool up, bool down, bool left, bool right,
+                                         const SWeight<C>& W) {
+  const C uc = nb[4];
+  C w[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    if (k == 4) {
+      w[k] = C(0);
+      continue;
+    }
+    const int si = k / 3 - 1, ti = k % 3 - 1;
+    const bool in = (si < 0 ? up : (si > 0 ? down : true)) && (ti < 0 ? left : (ti > 0 ? right : true));
+    w[k] = W(nb[k] - uc, in);
+  }
+  return smooth_solve<C>(nb, w);
 }
 
 // S at (i, j) of an H x W image read through U(ii, jj) (in-image positions
@@ -623,6 +635,152 @@ __device__ __forceinline__ void fused_tile(const FArgs& a, int t) {
   }
 }
 
+// FP32 form of the fused transfer with fewer instructions per pixel.  A
+// tile is 64 columns of the prolongation wide (one lane per column) and
+// TY + 2 HP rows tall; it writes OW = 64 - 2 HP columns of TY output rows.
+// After P (as above: FP64 coarse panels, one LDS row per tile row), each wave
+// walks a quarter of the S rows down its 64 columns keeping three rows of
+// values in registers; an edge's weight exp(-(difference/h)^2) is the same
+// seen from both of its pixels (the difference only changes sign), so every
+// weight is evaluated once: a pixel computes its east, south, south-east and
+// south-west edges, takes its west and north-west ones from the lane to its
+// left, its north-east one from the lane to its right (cross-lane shuffles)
+// and its north ones from the previous row.  The weights, the fit and D are
+// the same expressions in the same order as the separate stage kernels, so
+// the output is bit for bit theirs.
+template <bool QUAD, bool DO_D, int TY>
+struct SGeo {
+  static constexpr int HS = DO_D ? 2 : 0;  // S halo
+  static constexpr int HP = HS + 1;        // P halo
+  static constexpr int OW = kTW - 2 * HP;  // output columns per tile
+  static constexpr int PH = TY + 2 * HP;   // tile rows (P rows; S runs on rows 1 .. PH - 2)
+  static constexpr int LW = kTW + 2;       // LDS row: columns -1 .. 64
+  static constexpr int BH = PH / 2 + 5, BW = kTW / 2 + 5;  // coarse panel bound
+  static constexpr int NQ = QUAD ? BH * BW + PH * BW : 0;  // doubles
+  static constexpr int NC = DO_D ? (PH * LW + 1) / 2 : 0;  // diffusivities (floats, in doubles)
+  static constexpr int XN = (NQ > NC ? NQ : NC) > 0 ? (NQ > NC ? NQ : NC) : 1;
+};
+
+__host__ __device__ constexpr int sgeo_ow(bool do_d) { return kTW - 2 * ((do_d ? 2 : 0) + 1); }
+
+template <bool QUAD, bool DO_D, int TY>
+__device__ __forceinline__ void fused_tile_f32(const FArgs& a, int t) {
+  using G = SGeo<QUAD, DO_D, TY>;
+  constexpr int LW = G::LW;
+  __shared__ double xs[G::XN];  // coarse panels (P), then diffusivities (D)
+  __shared__ float pt[G::PH * LW];
+  __shared__ float stl[DO_D ? G::PH * LW : 1];
+  const int h = a.h, w = a.w;
+  const int tiles_x = (w + G::OW - 1) / G::OW;
+  const int ty = t / tiles_x, tx = t - ty * tiles_x;
+  const int I0 = ty * TY, J0 = tx * G::OW;
+  const int pi0 = I0 - G::HP, pj0 = J0 - G::HP;  // image position of tile row 0, column 0
+  const int Ia = max(pi0, 0), Ib = min(pi0 + G::PH, h) - 1;
+  const int Ja = max(pj0, 0), Jb = min(pj0 + kTW, w) - 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const float* src = (const float*)a.src;
+  const int J = pj0 + lane;  // this lane's column
+  const bool jin = J >= Ja && J <= Jb;
+
+  if constexpr (QUAD) {
+    const QExt<float> E{src, a.hB, a.wB, a.pB};
+    const int pa = max((Ia >> 1) - 1, 0), pb = min((Ib >> 1) + 2, a.hB + 1);
+    const int qa = max((Ja >> 1) - 1, 0), qb = min((Jb >> 1) + 2, a.wB + 1);
+    double* bt = xs;                  // E(p, q)
+    double* rt = xs + G::BH * G::BW;  // R(I, q) = quad1 along i
+    for (int k = threadIdx.x; k < G::BH * G::BW; k += 256) {
+      const int r = k / G::BW, c = k - r * G::BW;
+      if (pa + r <= pb && qa + c <= qb) bt[k] = E(pa + r, qa + c);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < G::PH * G::BW; k += 256) {
+      const int r = k / G::BW, c = k - r * G::BW;
+      const int I = pi0 + r;
+      if (I >= Ia && I <= Ib && qa + c <= qb) rt[k] = quad1(I, [&](int p) { return bt[(p - pa) * G::BW + c]; });
+    }
+    __syncthreads();
+    for (int r = wave; r < G::PH; r += 4) {
+      const int I = pi0 + r;
+      float v = 0.0f;  // outside the image: a finite filler S never weighs
+      if (I >= Ia && I <= Ib && jin) v = to_t<float>(quad1(J, [&](int q) { return rt[r * G::BW + (q - qa)]; }));
+      pt[r * LW + lane + 1] = v;
+      if (lane < 2) pt[r * LW + lane * (LW - 1)] = 0.0f;  // the columns -1 and 64
+    }
+  } else {
+    const LExt<float> E{src, a.hB, a.wB, a.pB};
+    for (int r = wave; r < G::PH; r += 4) {
+      const int I = pi0 + r;
+      pt[r * LW + lane + 1] = (I >= Ia && I <= Ib && jin) ? to_t<float>(linear_value(I, J, E)) : 0.0f;
+      if (lane < 2) pt[r * LW + lane * (LW - 1)] = 0.0f;
+    }
+  }
+  __syncthreads();
+
+  // S on tile rows 1 .. PH - 2, a contiguous quarter of them per wave
+  {
+    const SWeight<float> W(a.smooth_h);
+    constexpr int NSR = G::PH - 2, CH = (NSR + 3) / 4;
+    const int rs0 = 1 + wave * CH, rs1 = min(rs0 + CH, G::PH - 1);
+    const bool c0 = J - 1 >= 0 && J - 1 < w, c1 = J >= 0 && J < w, c2 = J + 1 >= 0 && J + 1 < w;
+    auto rin = [&](int r) { const int I = pi0 + r; return I >= 0 && I < h; };
+    float* out = (float*)a.dst;
+    if (rs0 < rs1) {
+      const float* pr = pt + (rs0 - 1) * LW + lane;  // pr[0..2]: columns lane - 1 .. lane + 1
+      float z0 = pr[0], z1 = pr[1], z2 = pr[2];
+      float y0 = pr[LW], y1 = pr[LW + 1], y2 = pr[LW + 2];
+      bool rz = rin(rs0 - 1), ry = rin(rs0);
+      // the edges from row rs0 - 1 down to row rs0
+      float pS = W(y1 - z1, rz && ry && c1);
+      float pSE = W(y2 - z1, rz && ry && c1 && c2);
+      float pSW = W(y0 - z1, rz && ry && c1 && c0);
+      for (int r = rs0; r < rs1; ++r) {
+        const float* xr = pt + (r + 1) * LW + lane;
+        const float x0 = xr[0], x1 = xr[1], x2 = xr[2];
+        const bool rx = rin(r + 1);
+        const float wE = W(y2 - y1, ry && c1 && c2);
+        const float wS = W(x1 - y1, ry && rx && c1);
+        const float wSE = W(x2 - y1, ry && rx && c1 && c2);
+        const float wSW = W(x0 - y1, ry && rx && c1 && c0);
+        const float wW = __shfl_up(wE, 1, 64);
+        const float wNW = __shfl_up(pSE, 1, 64);
+        const float wNE = __shfl_down(pSW, 1, 64);
+        const float nb[9] = {z0, z1, z2, y0, y1, y2, x0, x1, x2};
+        const float wt[9] = {wNW, pS, wNE, wW, 0.0f, wE, wSW, wS, wSE};
+        const float v = smooth_solve<float>(nb, wt);
+        if constexpr (DO_D) {
+          stl[r * LW + lane + 1] = v;
+        } else {
+          const int I = pi0 + r;
+          if (lane >= G::HP && lane < kTW - G::HP && ry && c1) out[(size_t)I * a.pitch + J] = v;
+        }
+        z0 = y0; z1 = y1; z2 = y2;
+        y0 = x0; y1 = x1; y2 = x2;
+        rz = ry; ry = rx;
+        pS = wS; pSE = wSE; pSW = wSW;
+      }
+    }
+  }
+  if constexpr (DO_D) {
+    __syncthreads();
+    const float ik2 = (float)(1.0 / (a.pm_k * a.pm_k));
+    auto Us = [&](int ii, int jj) { return stl[(ii - pi0) * LW + (jj - pj0) + 1]; };
+    float* ct = reinterpret_cast<float*>(xs);  // the P panels are no longer needed
+    const bool cl = lane >= G::HP - 1 && lane < kTW - G::HP + 1 && J >= 0 && J < w;
+    for (int r = G::HP - 1 + wave; r < G::HP + TY + 1; r += 4) {
+      const int I = pi0 + r;
+      if (cl && I >= 0 && I < h) ct[r * LW + lane + 1] = pm_c<float>(I, J, h, w, ik2, Us);
+    }
+    __syncthreads();
+    auto Cc = [&](int ii, int jj) { return ct[(ii - pi0) * LW + (jj - pj0) + 1]; };
+    float* out = (float*)a.dst;
+    const bool ol = lane >= G::HP && lane < kTW - G::HP && J < w;
+    for (int r = G::HP + wave; r < G::HP + TY; r += 4) {
+      const int I = pi0 + r;
+      if (ol && I < h) out[(size_t)I * a.pitch + J] = pm_value<float>(I, J, h, w, (float)a.tau, Us, Cc);
+    }
+  }
+}
+
 // Engine form: grids and buffers from the job's descriptor.
 template <typename T, bool QUAD, bool DO_D, int TY>
 __global__ __launch_bounds__(256) void k_xfer_fused(LaunchList ll, const JobDesc* __restrict__ descs, int src,
@@ -641,13 +799,19 @@ __global__ __launch_bounds__(256) void k_xfer_fused(LaunchList ll, const JobDesc
   a.smooth_h = d.smooth_h;
   a.pm_k = d.pm_k;
   a.tau = d.tau;
-  fused_tile<T, QUAD, DO_D, TY>(a, L.t);
+  if constexpr (sizeof(T) == 4)
+    fused_tile_f32<QUAD, DO_D, TY>(a, L.t);
+  else
+    fused_tile<T, QUAD, DO_D, TY>(a, L.t);
 }
 
 // Operator form on one dense image.
 template <typename T, bool QUAD, bool DO_D>
 __global__ __launch_bounds__(256) void k_xfer_fused_op(FArgs a) {
-  fused_tile<T, QUAD, DO_D, kFY>(a, blockIdx.x);
+  if constexpr (sizeof(T) == 4)
+    fused_tile_f32<QUAD, DO_D, kFY>(a, blockIdx.x);
+  else
+    fused_tile<T, QUAD, DO_D, kFY>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1205,8 +1369,8 @@ int blocks_for_stage(Stage st, const JobDesc& d) {
     case kMrFinInit:
     case kMrFin: return 1;
     case kXfExtrap: return tiles2((d.hB + 1) / 2, (d.wB + 1) / 2, kXH, kXW);  // 2 x 2 outputs per thread
-    case kXfFused: return tiles2(d.h, d.w, kFY, kFX);
-    case kXfFusedSmall: return tiles2(d.h, d.w, kFYSmall, kFX);
+    case kXfFused: return tiles2(d.h, d.w, kFY, d.f64 ? kFX : sgeo_ow(d.pm_steps >= 1));
+    case kXfFusedSmall: return tiles2(d.h, d.w, kFYSmall, d.f64 ? kFX : sgeo_ow(d.pm_steps >= 1));
     case kFlushU: return tiles2(d.h, d.w, kXH, kXW);
     case kCoarse: return 1;
     default: return tiles2(d.h, d.w, kXH, kXW);
@@ -1407,7 +1571,7 @@ hipError_t op_pm_step(const void* u, void* out, int H, int W, double k, double t
 
 template <typename T>
 static void launch_fused_op(const FArgs& a, bool quad, bool denoise, hipStream_t s) {
-  const dim3 grid(tiles2(a.h, a.w, kFY, kFX)), block(256);
+  const dim3 grid(tiles2(a.h, a.w, kFY, sizeof(T) == 8 ? kFX : sgeo_ow(denoise))), block(256);
   if (quad && denoise)
     hipLaunchKernelGGL((k_xfer_fused_op<T, true, true>), grid, block, 0, s, a);
   else if (quad)

@@ -1289,6 +1289,7 @@ class Engine {
     d.mirror = d_mirror_ + j->slot;
     d.tag = level_tag(j, l);
     d.taps_bytes = (int32_t)P.taps_bytes;
+    d.f64 = P.f64 ? 1 : 0;
     if (l >= 1) {
       d.uB = u_at(l - 1);
       d.hB = P.lv[l - 1].h;
