@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libeecmg.so")
 SOURCES = ["eecmg_kernels.hip", "eecmg_sm_f32_sep.hip", "eecmg_sm_f32_sym.hip", "eecmg_sm_f64.hip", "eecmg_sm_box.hip",
-           "eecmg_sm_gen.hip", "eecmg_runtime.cpp"]
+           "eecmg_sm_gen.hip", "eecmg_sm_short.hip", "eecmg_runtime.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled for every HIP translation unit.

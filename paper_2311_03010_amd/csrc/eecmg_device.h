@@ -233,11 +233,11 @@ constexpr int stream_waves(int R, int regs) {
 // Rank-one PSF psf(a,b) = col(a) row(b) (the Gaussian of Section 5 and its
 // coarse levels).  For each input row the lane forms the horizontal filter
 // h = sum_b row(b) x(., j-b) once and adds col(a) h to the pending outputs.
-// Taps: row(-R..R) followed by col(-R..R).  TALL: strips of strip_th(R, true) rows.
-template <typename T, int R, bool TALL = false>
+// Taps: row(-R..R) followed by col(-R..R).  SM: strip mode (strip_th).
+template <typename T, int R, int SM = 0>
 struct ConvSep {
   using S = Slide<R>;
-  static constexpr int NT = 64, TW = kTW, TH = strip_th(R, TALL), LW = kTW + 2 * R, RC = R;
+  static constexpr int NT = 64, TW = kTW, TH = strip_th(R, SM), LW = kTW + 2 * R, RC = R;
   static constexpr bool kRuntimeR = false, kStream = true;
   static constexpr bool kVSym = false;  // the column filter need not be symmetric
   static constexpr bool kDconv = false;  // two windows of 2 (2R + 1) taps would crowd the registers
@@ -293,10 +293,10 @@ constexpr int sym_ntaps(int R, bool disk) { return sym_offset(R, disk, R + 1); }
 // rows below and above: about (R+1)(R+2)/2 + 2R ops per row and pixel
 // instead of (2R+1)^2 FMAs.  Taps: the quadrant a, b >= 0, row by row
 // (b = 0..span(a)).
-template <typename T, int R, bool DISK, bool TALL = false>
+template <typename T, int R, bool DISK, int SM = 0>
 struct ConvSym {
   using S = Slide<R>;
-  static constexpr int NT = 64, TW = kTW, TH = strip_th(R, TALL), LW = kTW + 2 * R, RC = R;
+  static constexpr int NT = 64, TW = kTW, TH = strip_th(R, SM), LW = kTW + 2 * R, RC = R;
   static constexpr bool kRuntimeR = false, kStream = true;
   static constexpr bool kVSym = true;  // symmetric in the vertical direction: strips may walk up
   static constexpr bool kDconv = false;  // two quadrant windows would crowd the registers
@@ -345,15 +345,15 @@ struct ConvSym {
 // |b| <= span(a).  The spans are nested, so one running sum of the pair sums
 // gives every row filter: 2R adds per input row instead of one FMA per tap,
 // and the weight is applied once per output.  Taps: {w}.
-template <typename T, int R, bool TALL = false>
+template <typename T, int R, int SM = 0>
 struct ConvBox {
   using S = Slide<R>;
-  static constexpr int NT = 64, TW = kTW, TH = strip_th(R, TALL), LW = kTW + 2 * R, RC = R;
+  static constexpr int NT = 64, TW = kTW, TH = strip_th(R, SM), LW = kTW + 2 * R, RC = R;
   static constexpr bool kRuntimeR = false, kStream = true;
   static constexpr bool kVSym = true;  // symmetric in the vertical direction: strips may walk up
   // pass B may recompute q (k_cg_bd): the window state is small (not with
   // tall strips, whose levels keep the stored q)
-  static constexpr bool kDconv = !TALL;
+  static constexpr bool kDconv = SM == 0;
   // streaming kernels hide memory latency with waves: ask the register
   // allocator for at least this many per SIMD where the state fits (it
   // otherwise trades occupancy for instruction-level parallelism)

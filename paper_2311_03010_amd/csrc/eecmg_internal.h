@@ -195,8 +195,15 @@ __host__ __device__ constexpr int strip_group(int R) {
 // Tall strips (at least 2 kTH rows) serve large FP32 levels: half the halo
 // rows per output and half the strips in flight per XCD.
 constexpr int kTHTall = 2 * kTH;
-__host__ __device__ constexpr int strip_th(int R, bool tall = false) {
-  return strip_group(R) * (((tall ? kTHTall : kTH) + 2 * R + strip_group(R) - 1) / strip_group(R)) - 2 * R;
+// Short strips (at least kTH / 2 rows) serve streaming levels that give the
+// chip too few strips of the usual height (mid-size levels, which the
+// Infinity Cache holds, so the extra halo rows cost little).
+constexpr int kTHShortStrip = kTH / 2;
+// Strip mode: 0 usual height, 1 tall, 2 short.
+__host__ __device__ constexpr int strip_th(int R, int mode = 0) {
+  return strip_group(R) *
+             (((mode == 1 ? kTHTall : mode == 2 ? kTHShortStrip : kTH) + 2 * R + strip_group(R) - 1) / strip_group(R)) -
+         2 * R;
 }
 // Strips of the double-convolution pass B: TH2 output rows of kTW - 2R
 // columns, walked in TH2 + 4R + 1 steps (whole row groups).
@@ -204,16 +211,18 @@ __host__ __device__ constexpr int strip_th2(int R) {
   return strip_group(R) * ((kTH + 4 * R + 1 + strip_group(R) - 1) / strip_group(R)) - 4 * R - 1;
 }
 __host__ __device__ constexpr int strip_tw2(int R) { return kTW - 2 * R; }
-// A variant id is kind * 100 + R, plus kTallVariant for a streaming kind on
-// tall strips.
+// A variant id is kind * 100 + R, plus kTallVariant (kShortVariant) for a
+// streaming kind on tall (short) strips.
 constexpr int kTallVariant = 10000;
+constexpr int kShortVariant = 20000;
 __host__ __device__ constexpr int variant_kind(int variant) { return (variant % kTallVariant) / 100; }
 __host__ __device__ constexpr int variant_r(int variant) { return variant % 100; }
-__host__ __device__ constexpr bool variant_tall(int variant) { return variant >= kTallVariant; }
+__host__ __device__ constexpr int variant_strip_mode(int variant) { return variant / kTallVariant; }
+__host__ __device__ constexpr bool variant_tall(int variant) { return variant_strip_mode(variant) == 1; }
 __host__ __device__ constexpr int tile_h_for_variant(int variant) {
   return variant_kind(variant) == kConvGeneral    ? kTH
          : variant_kind(variant) == kConvGenShort ? kTHShort
-                                                  : strip_th(variant_r(variant), variant_tall(variant));
+                                                  : strip_th(variant_r(variant), variant_strip_mode(variant));
 }
 
 // Host-side launchers (defined in eecmg_kernels.hip).

@@ -1333,8 +1333,8 @@ __global__ __launch_bounds__(256) void k_op_restrict(const T* __restrict__ gf, i
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
-hipError_t sm_f32_sep(Stage st, int R, bool tall, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
-hipError_t sm_f32_sym(Stage st, bool disk, int R, bool tall, const LaunchList& ll, const JobDesc* descs,
+hipError_t sm_f32_sep(Stage st, int R, int sm, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
+hipError_t sm_f32_sym(Stage st, bool disk, int R, int sm, const LaunchList& ll, const JobDesc* descs,
                       hipStream_t s);
 hipError_t sm_f64_sep(Stage st, int R, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
 hipError_t sm_f64_sym(Stage st, bool disk, int R, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
@@ -1345,7 +1345,7 @@ hipError_t opc_f32_sym(bool disk, const void* x, void* y, int H, int W, const vo
 hipError_t opc_f64_sep(const void* x, void* y, int H, int W, const void* taps, int R, hipStream_t s);
 hipError_t opc_f64_sym(bool disk, const void* x, void* y, int H, int W, const void* taps, int R, hipStream_t s);
 hipError_t opc_gen(bool f64, const void* x, void* y, int H, int W, const void* taps, int R, hipStream_t s);
-hipError_t sm_box(Stage st, bool f64, int R, bool tall, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
+hipError_t sm_box(Stage st, bool f64, int R, int sm, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
 hipError_t opc_box(bool f64, const void* x, void* y, int H, int W, const void* taps, int R, hipStream_t s);
 
 int rmax_class_for(int r) { return r <= 3 ? 3 : (r <= 6 ? 6 : 12); }
@@ -1380,7 +1380,7 @@ int blocks_for_stage(Stage st, const JobDesc& d) {
 static hipError_t launch_smoother(Stage st, bool f64, int variant, const LaunchList& ll, const JobDesc* descs,
                                   hipStream_t s) {
   const int kind = variant_kind(variant), R = variant_r(variant);
-  const bool tall = variant_tall(variant);
+  const int tall = variant_strip_mode(variant);  // strip mode: 0 usual, 1 tall, 2 short
   if (tall && (f64 || kind == kConvGeneral || kind == kConvGenShort)) return hipErrorInvalidValue;
   switch (kind) {
     case kConvGeneral: return sm_gen(st, f64, R, ll, descs, s);

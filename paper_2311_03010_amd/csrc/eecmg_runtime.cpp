@@ -145,6 +145,14 @@ static long tall_min_tiles() {
   const char* e = std::getenv("EECMG_TALL_MIN_TILES");
   return e ? std::atol(e) : kTallMinTiles;
 }
+// FP32 streaming levels whose usual strips number fewer than this (two waves
+// per SIMD of the chip) use short strips (EECMG_SHORT_MAX_TILES; 0 turns
+// them off).
+constexpr long kShortMaxTiles = 2048;
+static long short_max_tiles() {
+  const char* e = std::getenv("EECMG_SHORT_MAX_TILES");
+  return e ? std::atol(e) : kShortMaxTiles;
+}
 static long fold_max_tiles() {
   const char* e = std::getenv("EECMG_FOLD_MAX_TILES");
   return e ? std::atol(e) : kFoldMaxTiles;
@@ -400,14 +408,18 @@ static int build_plan(int H, int W, const double* psf, int r, int L, const int* 
     // FP32 streaming kernels walk tall strips on levels that still give the
     // chip enough of them (the choice depends on the level's shape only, so
     // an image gets the same kernels alone and in a batch)
-    if (!general && !P.f64 && tall_strips_enabled() &&
-        (long)lp.tiles_x * ((lp.h + strip_th(variant_r(lp.variant), true) - 1) / strip_th(variant_r(lp.variant), true)) >=
-            tall_min_tiles())
+    auto strips = [&](int mode) {
+      const int th = strip_th(variant_r(lp.variant), mode);
+      return (long)lp.tiles_x * ((lp.h + th - 1) / th);
+    };
+    if (!general && !P.f64 && tall_strips_enabled() && strips(1) >= tall_min_tiles())
       lp.variant += kTallVariant;
+    else if (!general && !P.f64 && strips(0) < short_max_tiles())
+      lp.variant += kShortVariant;
     const int th = tile_h_for_variant(lp.variant);
     lp.ntiles = lp.tiles_x * ((lp.h + th - 1) / th);
     lp.dconv = l >= P.coarse && P.prm.smoother == EECMG_SMOOTHER_CGLS && !P.f64 && kind == kConvBoxDisk &&
-               !variant_tall(lp.variant) && dconv_enabled();
+               variant_strip_mode(lp.variant) == 0 && dconv_enabled();
     // (the recomputed-q pass B takes alpha from a finalize launch)
     lp.fold_a = l >= P.coarse && P.prm.smoother == EECMG_SMOOTHER_CGLS && !lp.dconv &&
                 lp.ntiles <= (general ? fold_max_tiles() : fold_max_tiles_stream());

@@ -11,8 +11,12 @@ namespace eecmg {
 #define EECMG_BOX_OP(T, R) \
   case R: return launch_op_conv<T, ConvBox<T, R>>(x, y, H, W, taps, R, s);
 
-hipError_t sm_box(Stage st, bool f64, int R, bool tall, const LaunchList& ll, const JobDesc* descs, hipStream_t s) {
-  if (tall) {
+hipError_t sm_box_short(Stage st, int R, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
+
+// sm: strip mode (0 usual, 1 tall, 2 short; tall and short FP32 only)
+hipError_t sm_box(Stage st, bool f64, int R, int sm, const LaunchList& ll, const JobDesc* descs, hipStream_t s) {
+  if (sm == 2) return f64 ? hipErrorInvalidValue : sm_box_short(st, R, ll, descs, s);
+  if (sm == 1) {
     if (f64) return hipErrorInvalidValue;
     switch (R) {
       EECMG_BOX_TALL(1) EECMG_BOX_TALL(2) EECMG_BOX_TALL(3) EECMG_BOX_TALL(4)

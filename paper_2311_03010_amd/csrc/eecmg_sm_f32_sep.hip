@@ -11,8 +11,12 @@ namespace eecmg {
 #define EECMG_SEP_OP(R) \
   case R: return launch_op_conv<float, ConvSep<float, R>>(x, y, H, W, taps, R, s);
 
-hipError_t sm_f32_sep(Stage st, int R, bool tall, const LaunchList& ll, const JobDesc* descs, hipStream_t s) {
-  if (tall) {
+hipError_t sm_f32_sep_short(Stage st, int R, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
+
+// sm: strip mode (0 usual, 1 tall, 2 short)
+hipError_t sm_f32_sep(Stage st, int R, int sm, const LaunchList& ll, const JobDesc* descs, hipStream_t s) {
+  if (sm == 2) return sm_f32_sep_short(st, R, ll, descs, s);
+  if (sm == 1) {
     switch (R) {
       EECMG_SEP_TALL(0) EECMG_SEP_TALL(1) EECMG_SEP_TALL(2) EECMG_SEP_TALL(3) EECMG_SEP_TALL(4)
       EECMG_SEP_TALL(5) EECMG_SEP_TALL(6) EECMG_SEP_TALL(7) EECMG_SEP_TALL(8) EECMG_SEP_TALL(9)

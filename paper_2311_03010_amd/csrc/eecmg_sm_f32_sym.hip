@@ -11,8 +11,13 @@ namespace eecmg {
 #define EECMG_SYM_OP(R, D) \
   case R: return launch_op_conv<float, ConvSym<float, R, D>>(x, y, H, W, taps, R, s);
 
-hipError_t sm_f32_sym(Stage st, bool disk, int R, bool tall, const LaunchList& ll, const JobDesc* descs,
+hipError_t sm_f32_sym_short(Stage st, bool disk, int R, const LaunchList& ll, const JobDesc* descs, hipStream_t s);
+
+// sm: strip mode (0 usual, 1 tall, 2 short)
+hipError_t sm_f32_sym(Stage st, bool disk, int R, int sm, const LaunchList& ll, const JobDesc* descs,
                       hipStream_t s) {
+  if (sm == 2) return sm_f32_sym_short(st, disk, R, ll, descs, s);
+  const bool tall = sm == 1;
   if (tall && disk) {
     switch (R) {
       EECMG_SYM_TALL(1, true) EECMG_SYM_TALL(2, true) EECMG_SYM_TALL(3, true) EECMG_SYM_TALL(4, true)

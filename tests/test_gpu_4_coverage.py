@@ -140,3 +140,39 @@ def test_fp64_cascade_with_1024_level(torch_cuda):
     p = synth.workload(2, precision="f64")
     u, st = _gpu(torch_cuda, p, "f64")
     _check(p, "f64", u, st, *_oracle(p, "f64"))
+
+
+# ------------------------------------------------------------ short strips
+@pytest.mark.parametrize("psfname", ["gauss7", "symdisk5", "disk5"])
+def test_short_strip_smoother_parity(torch_cuda, monkeypatch, psfname):
+    """A 700 x 900 FP32 level gives the streaming kernels too few strips of
+    the usual height, so it runs on short strips: CGLS from zero matches the
+    oracle with the separable, symmetric-disk and uniform-disk kernels, and the
+    usual strips (EECMG_SHORT_MAX_TILES=0) to FP32 rounding (the partial sums
+    are grouped by other tiles)."""
+    H, W = 700, 900
+    rng = np.random.Generator(np.random.PCG64(H + 3 * len(psfname)))
+    a = np.arange(-5, 6)
+    d2 = a[:, None] ** 2 + a[None, :] ** 2
+    symdisk = np.where(d2 <= 25, 1.0 / (1.0 + d2), 0.0)
+    psf = {"gauss7": synth.gaussian_psf(2.5, 7), "symdisk5": symdisk / symdisk.sum(), "disk5": synth.disk_psf(5)}[psfname]
+    u_true = synth.scene(H, W, 120, rng)
+    g = (synth.blur(u_true, psf) + rng.standard_normal((H, W))).astype(np.float32).astype(np.float64)
+    cap = 6
+    t = torch_cuda
+    gd = t.from_numpy(g.astype(np.float32)).to("cuda:0")
+    res = {}
+    for mode, env in (("short", "2048"), ("usual", "0")):
+        monkeypatch.setenv("EECMG_SHORT_MAX_TILES", env)
+        print(f"  {psfname} {mode} strips", flush=True)
+        ud = t.zeros_like(gd)
+        u, st = eecmg.smoother_dev(gd, ud, psf, cap, precision="f32", stop_rule=False)
+        t.cuda.synchronize()
+        res[mode] = (u.cpu().numpy().astype(np.float64), st)
+    u_ref, it, hist, why = oracle.cgls(g, psf, u0=np.zeros_like(g), cap=cap, eps=GUARD["f32"])
+    for mode in ("short", "usual"):
+        u, st = res[mode]
+        print(f"  {mode}: iters gpu={st['iters']} oracle={it} rel={_rel(u, u_ref):.2e}", flush=True)
+        assert st["iters"] == it and st["reason"] == why
+        assert _rel(u, u_ref) <= 2e-5
+    assert _rel(res["short"][0], res["usual"][0]) <= 1e-5
