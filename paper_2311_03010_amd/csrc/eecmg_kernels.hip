@@ -688,9 +688,15 @@ __device__ __forceinline__ void fused_tile_f32(const FArgs& a, int t) {
     const int qa = max((Ja >> 1) - 1, 0), qb = min((Jb >> 1) + 2, a.wB + 1);
     double* bt = xs;                  // E(p, q)
     double* rt = xs + G::BH * G::BW;  // R(I, q) = quad1 along i
-    for (int k = threadIdx.x; k < G::BH * G::BW; k += 256) {
-      const int r = k / G::BW, c = k - r * G::BW;
-      if (pa + r <= pb && qa + c <= qb) bt[k] = E(pa + r, qa + c);
+    if (pb < a.hB && qb < a.wB) {
+      // no virtual node: plain loads, one panel row per wave and step
+      for (int r = wave; r <= pb - pa; r += 4)
+        if (lane <= qb - qa) bt[r * G::BW + lane] = (double)src[(size_t)(pa + r) * a.pB + qa + lane];
+    } else {
+      for (int k = threadIdx.x; k < G::BH * G::BW; k += 256) {
+        const int r = k / G::BW, c = k - r * G::BW;
+        if (pa + r <= pb && qa + c <= qb) bt[k] = E(pa + r, qa + c);
+      }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < G::PH * G::BW; k += 256) {
@@ -1195,11 +1201,22 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse(LaunchList ll, const 
 // solution of every level that receives no transfer (zero, or the given
 // initial guess on the finest level); the other levels are written whole by
 // their transfer before their smoother reads them.
+// Rows of the dense input the restriction visits: every row when the finest
+// level gets a pitched copy or a starting value, else only the even rows,
+// which are all that feed the coarser levels.
+__host__ __device__ inline int restrict_row_step(const JobDesc& d) {
+  const bool copy_fine = d.g_lv[d.L - 1] != d.g_in;
+  const bool init_fine = (d.zero_u >> (d.L - 1)) & 1;
+  return (copy_fine || init_fine) ? 1 : 2;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_restrict(LaunchList ll, const JobDesc* __restrict__ descs) {
   const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
   const JobDesc& d = descs[L.d];
   const int H = d.H, W = d.W, NL = d.L;
+  const int rs = restrict_row_step(d);
+  if (rs == 2 && NL == 1) return;
   const int tiles_x = (W + kXW - 1) / kXW;
   const int ty = L.t / tiles_x, tx = L.t - ty * tiles_x;
   const int x = tx * kXW + (threadIdx.x & 63);
@@ -1211,15 +1228,20 @@ __global__ __launch_bounds__(256) void k_restrict(LaunchList ll, const JobDesc* 
   // have the level's pitch; otherwise it gets a pitched copy
   const bool copy_fine = d.g_lv[NL - 1] != d.g_in;
   const bool init_fine = (zero >> (NL - 1)) & 1;
-  // with neither, only the even rows feed coarser levels
-  const int skip_odd = (copy_fine || init_fine) ? 0 : 1;
-  if (skip_odd && NL == 1) return;
+  // tile row r covers input row r * rs; the lane's rows are loaded first
+  T vals[kXH / 4];
+  int ys[kXH / 4];
+#pragma unroll
   for (int k = 0; k < kXH / 4; ++k) {
-    const int y = ty * kXH + (threadIdx.x >> 6) * (kXH / 4) + k;
+    const int y = (ty * kXH + (threadIdx.x >> 6) * (kXH / 4) + k) * rs;
+    ys[k] = y;
+    vals[k] = gin[(size_t)min(y, H - 1) * W + x];
+  }
+  for (int k = 0; k < kXH / 4; ++k) {
+    const int y = ys[k];
     if (y >= H) break;
-    if (y & skip_odd) continue;
     const size_t fo = (size_t)y * W + x;
-    const T v = gin[fo];
+    const T v = vals[k];
     const size_t of = (size_t)y * d.fine_pitch + x;
     if (copy_fine) ((T*)d.g_lv[NL - 1])[of] = v;
     if (init_fine) ((T*)d.u_lv[NL - 1])[of] = uin ? uin[fo] : T(0);
@@ -1354,7 +1376,7 @@ static int tiles2(int h, int w, int th, int tw) { return ((h + th - 1) / th) * (
 
 int blocks_for_stage(Stage st, const JobDesc& d) {
   switch (st) {
-    case kRestrict:
+    case kRestrict: return tiles2((d.H + restrict_row_step(d) - 1) / restrict_row_step(d), d.W, kXH, kXW);
     case kOutCopy: return tiles2(d.H, d.W, kXH, kXW);
     case kCgInit1:
     case kCgInit2:
