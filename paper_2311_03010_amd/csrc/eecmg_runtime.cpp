@@ -310,7 +310,11 @@ static int build_plan(int H, int W, const double* psf, int r, int L, const int* 
   } else {
     default_params(&prm);
   }
-  if (prm.precision < 0 || prm.precision > 2) return fail(EECMG_EINVAL, "precision must be 0, 1 or 2");
+  if (prm.precision == EECMG_FP32_FP16COARSE)
+    return fail(EECMG_EINVAL,
+                "FP16 storage of coarse levels is not provided: it stays within the FP32 error bar only on levels "
+                "of at most 128^2 pixels, which are launch-bound, so it would add error and save no time");
+  if (prm.precision < 0 || prm.precision > 1) return fail(EECMG_EINVAL, "precision must be 0 (FP64) or 1 (FP32)");
   if (L < 1 || L > kMaxLevels) return fail(EECMG_EINVAL, "n_levels must be in [1, 16]");
   if (H < 3 || W < 3) return fail(EECMG_EINVAL, "image must be at least 3 x 3");
   if ((long long)H * W > (1LL << 31)) return fail(EECMG_EINVAL, "image too large");
@@ -2018,7 +2022,7 @@ static int op_taps(const double* psf, int r, bool f64, bool flip, void** d_taps,
 }
 
 static int check_prec(int precision) {
-  if (precision < 0 || precision > 2) return fail(EECMG_EINVAL, "precision must be 0, 1 or 2");
+  if (precision < 0 || precision > 1) return fail(EECMG_EINVAL, "precision must be 0 (FP64) or 1 (FP32)");
   return EECMG_OK;
 }
 

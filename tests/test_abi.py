@@ -68,3 +68,17 @@ def test_host_only_entry_points_without_gpu():
     assert eecmg.lib().eecmg_profile_min_pixels(-1.0) == eecmg.EINVAL
     assert eecmg.lib().eecmg_profile_min_pixels(float("nan")) == eecmg.EINVAL
     assert eecmg.lib().eecmg_profile_min_pixels(0.0) == eecmg.OK
+
+
+def test_fp16_coarse_precision_is_refused_before_any_device_work():
+    # the parameters are validated before the device is touched (see
+    # test_fp16_coarse_error.py for why the mode is not provided)
+    import numpy as np
+
+    from paper_2311_03010_amd import eecmg, synth
+
+    g = np.zeros((64, 64), np.float32)
+    with pytest.raises(eecmg.EecmgError) as e:
+        eecmg.restore(g, synth.disk_psf(2), 3, precision="f32_f16coarse")
+    assert e.value.status == eecmg.EINVAL
+    assert "FP16" in str(e.value)
