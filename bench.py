@@ -523,6 +523,9 @@ def main():
     ap.add_argument("--only-set", action="store_true", help="only run the uneven set (for profiling it)")
     ap.add_argument("--no-profile", action="store_true",
                     help="no profiled regions (for runs under an external profiler)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="run with the library's default thresholds (no autotuning)")
+    ap.add_argument("--tune-cache", default=None, help="autotune cache file (default: the package's tuning.json)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
@@ -542,6 +545,13 @@ def main():
     import torch
 
     from paper_2311_03010_amd import eecmg, synth
+
+    tuning = None
+    if not args.no_autotune:
+        from paper_2311_03010_amd import autotune
+
+        _log("bench: autotune (launch-shape thresholds)")
+        tuning = autotune.load_or_tune(torch, eecmg, synth, cache=args.tune_cache or autotune.CACHE, log=_log)
 
     _log(f"bench: generating workload {args.workload}")
     p = synth.workload(args.workload)
@@ -691,7 +701,7 @@ def main():
                        "caps": "economic m_l rule", "form": "plain"},
             "roofline": roofline, "cpu_baseline": cpu, "accuracy_vs_oracle": acc, "batched": batched,
             "uneven_set": uneven, "served": served, "edge": edge, "workloads": workloads, "one_level": one_level,
-            "cpu_oracle": cpu_table, "detail": extra}
+            "cpu_oracle": cpu_table, "autotune": tuning, "detail": extra}
     print(json.dumps(line), flush=True)
 
 

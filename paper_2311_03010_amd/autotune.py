@@ -1,0 +1,176 @@
+"""Autotuner of the library's launch-shape thresholds on the GPU it runs on.
+
+The library picks, per level, the strip height of the streaming blur kernels
+(tall, usual or short strips, by how many strips the level yields), whether a
+level folds its finalize kernels into the smoother passes (by tile count),
+whether the CGLS solution update runs every second iteration (by level size)
+and how many unconfirmed iterations the scheduler keeps queued.  Each choice
+is a threshold read from the environment when a restore is planned
+(EECMG_TALL_MIN_TILES, EECMG_SHORT_MAX_TILES, EECMG_FOLD_MAX_TILES,
+EECMG_FOLD_MAX_TILES_STREAM, EECMG_LAZY_MIN_PIXELS, EECMG_MAX_AHEAD).  This
+module times restores of representative workloads -- the 4096^2 disk and
+1024^2 Gaussian single images and a batch of images of the uneven set -- and
+walks the thresholds one at a time over a few candidates (coordinate
+descent, two passes), keeping a change only when the geometric mean of the
+workloads' times improves by more than `min_gain`.  The result is cached as
+JSON keyed by a hash of the library's sources and the device name, so a
+rebuilt library or another device tunes again.
+
+Only thresholds that leave every result unchanged within the library's
+parity bars are tuned: folding and the every-second-iteration update are
+bit-identical schedules, and the strip height only regroups the partial sums
+of inner products (tests cover every choice against the oracle).
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import math
+import os
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+CACHE = os.path.join(HERE, "tuning.json")
+
+# threshold -> (library default, candidates)
+KNOBS = {
+    "EECMG_TALL_MIN_TILES": (2048, [1024, 2048, 4096, 1 << 30]),
+    "EECMG_SHORT_MAX_TILES": (2048, [0, 1024, 2048, 4096]),
+    "EECMG_FOLD_MAX_TILES": (4096, [0, 1024, 4096, 16384]),
+    "EECMG_FOLD_MAX_TILES_STREAM": (512, [0, 256, 512, 2048]),
+    "EECMG_LAZY_MIN_PIXELS": (1 << 20, [1 << 18, 1 << 20, 1 << 40]),
+    "EECMG_MAX_AHEAD": (2, [2, 3]),
+}
+
+
+def defaults() -> dict:
+    return {k: v[0] for k, v in KNOBS.items()}
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def apply(settings: dict) -> None:
+    """Set the thresholds for restores planned from now on in this process."""
+    for k, v in settings.items():
+        os.environ[k] = str(int(v))
+
+
+class _Workloads:
+    """Device-resident inputs of the tuning workloads and a timer for them."""
+
+    def __init__(self, torch, eecmg, synth, batch_images=64):
+        self.torch, self.eecmg = torch, eecmg
+        self.items = []
+        for wid in (3, 2):
+            p = synth.workload(wid)
+            g = torch.from_numpy(p.g_delta.astype(np.float32)).to("cuda:0")
+            self.items.append(("plain " + p.name, "plain", (p, g, torch.empty_like(g))))
+        probs = synth.batch_problems(batch_images)
+        gs = [torch.from_numpy(q.g_delta.astype(np.float32)).to("cuda:0") for q in probs]
+        self.items.append((f"batched uneven x{batch_images}", "batch", (probs, gs, [torch.empty_like(g) for g in gs])))
+
+    def _run(self, kind, data):
+        e = self.eecmg
+        if kind == "plain":
+            p, g, out = data
+            e.restore_dev(g, p.psf, p.n_levels, out=out, precision="f32", delta=p.delta, k=p.k)
+        else:
+            probs, gs, outs = data
+            e.restore_batch_dev(gs, [q.psf for q in probs], [q.n_levels for q in probs], ks=[q.k for q in probs],
+                                outs=outs, precision="f32", params=[{"delta": q.delta} for q in probs])
+
+    def time(self, reps=5) -> dict:
+        t = self.torch
+        res = {}
+        for name, kind, data in self.items:
+            self._run(kind, data)
+            t.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                self._run(kind, data)
+                t.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            res[name] = float(np.median(ts))
+        return res
+
+
+def _score(times: dict, base: dict) -> float:
+    return math.exp(sum(math.log(times[k] / base[k]) for k in base) / len(base))
+
+
+def tune(torch, eecmg, synth, passes=2, min_gain=0.01, reps=5, log=None) -> dict:
+    """Coordinate descent over the thresholds from the library defaults."""
+    wl = _Workloads(torch, eecmg, synth)
+    best = defaults()
+    apply(best)
+    base = wl.time(reps)
+    best_score, trials = 1.0, 1
+    for _ in range(passes):
+        changed = False
+        for knob, (_, cands) in KNOBS.items():
+            for c in cands:
+                if c == best[knob]:
+                    continue
+                trial = dict(best, **{knob: c})
+                apply(trial)
+                s = _score(wl.time(reps), base)
+                trials += 1
+                if log:
+                    log(f"autotune: {knob}={c} score {s:.4f} (best {best_score:.4f})")
+                if s < best_score * (1.0 - min_gain):
+                    best, best_score, changed = trial, s, True
+            apply(best)
+        if not changed:
+            break
+    apply(best)
+    final = wl.time(reps)
+    return {"settings": best, "defaults": defaults(), "trials": trials,
+            "time_vs_defaults": round(_score(final, base), 4),
+            "workload_ms": {k: round(v * 1e3, 4) for k, v in final.items()},
+            "default_ms": {k: round(v * 1e3, 4) for k, v in base.items()}}
+
+
+def load_or_tune(torch, eecmg, synth, cache=CACHE, force=False, log=None) -> dict:
+    """Settings for this library build and device: from the cache when its key
+    matches, else tuned now (and written to the cache when it is writable).
+    The settings are applied to this process."""
+    key = {"source_hash": source_hash(), "device": torch.cuda.get_device_name(0)}
+    if not force:
+        try:
+            with open(cache) as f:
+                c = json.load(f)
+            if c.get("key") == key:
+                apply(c["result"]["settings"])
+                return dict(c["result"], source="cache")
+        except (OSError, ValueError, KeyError):
+            pass
+    res = tune(torch, eecmg, synth, log=log)
+    try:
+        with open(cache, "w") as f:
+            json.dump({"key": key, "result": res}, f, indent=1)
+    except OSError:
+        pass
+    return dict(res, source="tuned")
+
+
+if __name__ == "__main__":
+    import sys
+
+    import torch
+
+    from paper_2311_03010_amd import eecmg, synth
+
+    out = load_or_tune(torch, eecmg, synth, force="--force" in sys.argv,
+                       log=lambda m: print(m, file=sys.stderr, flush=True))
+    print(json.dumps(out))
