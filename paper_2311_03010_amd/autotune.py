@@ -3,22 +3,26 @@
 The library picks, per level, the strip height of the streaming blur kernels
 (tall, usual or short strips, by how many strips the level yields), whether a
 level folds its finalize kernels into the smoother passes (by tile count),
-whether the CGLS solution update runs every second iteration (by level size)
-and how many unconfirmed iterations the scheduler keeps queued.  Each choice
-is a threshold read from the environment when a restore is planned
-(EECMG_TALL_MIN_TILES, EECMG_SHORT_MAX_TILES, EECMG_FOLD_MAX_TILES,
-EECMG_FOLD_MAX_TILES_STREAM, EECMG_LAZY_MIN_PIXELS, EECMG_MAX_AHEAD).  This
-module times restores of representative workloads -- the 4096^2 disk and
-1024^2 Gaussian single images and a batch of images of the uneven set -- and
-walks the thresholds one at a time over a few candidates (coordinate
-descent, two passes), keeping a change only when the geometric mean of the
-workloads' times improves by more than `min_gain`.  The result is cached as
-JSON keyed by a hash of the library's sources and the device name, so a
-rebuilt library or another device tunes again.
+whether the CGLS solution update runs every second iteration (by level size),
+how many unconfirmed iterations the scheduler keeps queued per job and how
+many steps it keeps queued on the device before it issues the next one.
+Each choice is a threshold read from the environment when a restore is
+planned (EECMG_TALL_MIN_TILES, EECMG_SHORT_MAX_TILES, EECMG_FOLD_MAX_TILES,
+EECMG_FOLD_MAX_TILES_STREAM, EECMG_LAZY_MIN_PIXELS, EECMG_MAX_AHEAD,
+EECMG_PACE_STEPS).  This module times restores of representative workloads
+-- the 4096^2 disk and 1024^2 Gaussian single images and a batch of images
+of the uneven set -- and walks the thresholds one at a time over a few
+candidates (coordinate descent, two passes), keeping a change only when,
+timed in turn against the current setting, the geometric mean of the
+workloads' times improves by more than `min_gain` and no workload gets
+slower by more than `min_gain`.  The result is cached as JSON keyed by a
+hash of the library's sources and the device name, so a rebuilt library or
+another device tunes again.
 
 Only thresholds that leave every result unchanged within the library's
 parity bars are tuned: folding and the every-second-iteration update are
-bit-identical schedules, and the strip height only regroups the partial sums
+bit-identical schedules, run-ahead and pacing only regroup jobs into
+launches, and the strip height only regroups the partial sums
 of inner products (tests cover every choice against the oracle).
 """
 from __future__ import annotations
@@ -43,6 +47,7 @@ KNOBS = {
     "EECMG_FOLD_MAX_TILES_STREAM": (512, [0, 256, 512, 2048]),
     "EECMG_LAZY_MIN_PIXELS": (1 << 20, [1 << 18, 1 << 20, 1 << 40]),
     "EECMG_MAX_AHEAD": (2, [2, 3]),
+    "EECMG_PACE_STEPS": (2, [0, 2, 3]),
 }
 
 
@@ -105,17 +110,37 @@ class _Workloads:
         return res
 
 
-def _score(times: dict, base: dict) -> float:
-    return math.exp(sum(math.log(times[k] / base[k]) for k in base) / len(base))
+def _ratios(trial: dict, ref: dict) -> dict:
+    return {k: trial[k] / ref[k] for k in ref}
+
+
+def _geomean(r: dict) -> float:
+    return math.exp(sum(math.log(v) for v in r.values()) / len(r))
+
+
+def _ab(wl, a: dict, b: dict, reps: int) -> dict:
+    """Per-workload time ratios of settings a to settings b, each workload
+    timed under a and b in turn (so drift of the device's speed cancels)."""
+    ta, tb = {}, {}
+    for _ in range(2):
+        apply(a)
+        for k, v in wl.time(reps).items():
+            ta.setdefault(k, []).append(v)
+        apply(b)
+        for k, v in wl.time(reps).items():
+            tb.setdefault(k, []).append(v)
+    return {k: float(np.median(ta[k])) / float(np.median(tb[k])) for k in ta}
 
 
 def tune(torch, eecmg, synth, passes=2, min_gain=0.01, reps=5, log=None) -> dict:
-    """Coordinate descent over the thresholds from the library defaults."""
+    """Coordinate descent over the thresholds from the library defaults.  A
+    candidate replaces the current setting when, timed against it, the
+    geometric mean of the workloads' times drops by more than `min_gain` and
+    no single workload gets slower by more than `min_gain` (so a gain on the
+    batches never costs the single large image, or the reverse)."""
     wl = _Workloads(torch, eecmg, synth)
     best = defaults()
-    apply(best)
-    base = wl.time(reps)
-    best_score, trials = 1.0, 1
+    trials = 0
     for _ in range(passes):
         changed = False
         for knob, (_, cands) in KNOBS.items():
@@ -123,22 +148,23 @@ def tune(torch, eecmg, synth, passes=2, min_gain=0.01, reps=5, log=None) -> dict
                 if c == best[knob]:
                     continue
                 trial = dict(best, **{knob: c})
-                apply(trial)
-                s = _score(wl.time(reps), base)
+                r = _ab(wl, trial, best, reps)
                 trials += 1
+                g = _geomean(r)
                 if log:
-                    log(f"autotune: {knob}={c} score {s:.4f} (best {best_score:.4f})")
-                if s < best_score * (1.0 - min_gain):
-                    best, best_score, changed = trial, s, True
-            apply(best)
+                    log(f"autotune: {knob}={c} time ratio {g:.4f} "
+                        f"(per workload {', '.join(f'{v:.3f}' for v in r.values())})")
+                if g < 1.0 - min_gain and max(r.values()) < 1.0 + min_gain:
+                    best, changed = trial, True
         if not changed:
             break
+    final = _ab(wl, best, defaults(), reps)
     apply(best)
-    final = wl.time(reps)
+    times = wl.time(reps)
     return {"settings": best, "defaults": defaults(), "trials": trials,
-            "time_vs_defaults": round(_score(final, base), 4),
-            "workload_ms": {k: round(v * 1e3, 4) for k, v in final.items()},
-            "default_ms": {k: round(v * 1e3, 4) for k, v in base.items()}}
+            "time_vs_defaults": round(_geomean(final), 4),
+            "workload_vs_defaults": {k: round(v, 4) for k, v in final.items()},
+            "workload_ms": {k: round(v * 1e3, 4) for k, v in times.items()}}
 
 
 def load_or_tune(torch, eecmg, synth, cache=CACHE, force=False, log=None) -> dict:

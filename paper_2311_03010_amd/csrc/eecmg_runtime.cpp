@@ -842,6 +842,16 @@ class Engine {
   // Issue one round of work for every active job.  Returns true if anything
   // was launched.
   bool step(std::vector<Job*>& finished) {
+    if (paced()) {
+      // the device still has pace_ steps queued: only report finished jobs
+      finished.clear();
+      for (Job* j : slots_)
+        if (j && j->phase == Job::kWaitOut && event_done(j->done_ev->e)) {
+          finish(j);
+          finished.push_back(j);
+        }
+      return false;
+    }
     const bool idle_before = !step_pending_;  // everything enqueued so far had completed
     const uint64_t progress_before = progress_sum();
     poll_mirror();
@@ -1071,6 +1081,7 @@ class Engine {
       step_cur_ = (step_cur_ + 1) % kStepEvents;
       chk(hipEventRecord(step_ev_[step_cur_], stream_));
       step_pending_ = true;
+      n_out_ = std::min(n_out_ + 1, kStepEvents - 1);
     }
     note_progress(launched || !finished.empty() || progress_sum() != progress_before || !idle_before);
     return launched;
@@ -1085,6 +1096,16 @@ class Engine {
       chk(hipMemcpyAsync((void*)h_mirror_, d_mirror_, sizeof(uint64_t) * n_slots_, hipMemcpyDeviceToHost, stream_));
       chk(hipStreamSynchronize(stream_));
       step_pending_ = false;
+      return;
+    }
+    if (paced()) {
+      // wait for the oldest queued step (or a job's output) instead of the
+      // next progress word: the jobs confirmed meanwhile then share launches
+      for (long spin = 0; paced() && err_ == hipSuccess; ++spin) {
+        for (Job* j : slots_)
+          if (j && j->phase == Job::kWaitOut && event_done(j->done_ev->e)) return;
+        if (spin > 2000) std::this_thread::yield();
+      }
       return;
     }
     const std::vector<uint64_t> before = snapshot();
@@ -1141,6 +1162,8 @@ class Engine {
     stall_ms_ = e ? std::max(0.0, std::atof(e)) : kStallMs;
     e = std::getenv("EECMG_TEST_FAIL_STEP");
     fail_step_ = e ? std::atol(e) : 0;
+    e = std::getenv("EECMG_PACE_STEPS");
+    pace_ = e ? std::min(kStepEvents - 1, std::max(0, std::atoi(e))) : kPaceSteps;
     steps_ = 0;
   }
   // The engine can make no further progress: a HIP error was reported, or the
@@ -1171,6 +1194,7 @@ class Engine {
     err_ = hipSuccess;
     stalled_ = false;
     step_pending_ = false;
+    n_out_ = 0;
     idle_steps_ = 0;
   }
 
@@ -1208,6 +1232,27 @@ class Engine {
   }
 
   static constexpr int kStepEvents = 4;
+
+  // Step pacing.  Every step that launches records one of kStepEvents
+  // events; n_out_ counts those not yet seen complete (they complete in
+  // order, so only the oldest is polled).  While pace_ steps are queued on
+  // the device, no new step launches: jobs confirmed in the meantime are
+  // issued together in the next step, one launch per stage for all of them,
+  // instead of one small launch each time a progress word changes.  The
+  // queued steps keep the device busy while the host builds the next one.
+  // Without it a batch of many jobs splits into groups that drift apart and
+  // the host spends its time issuing launches of one or two jobs.
+  // EECMG_PACE_STEPS moves the depth (0 = off, at most kStepEvents - 1).
+  static constexpr int kPaceSteps = 2;
+  int outstanding() {
+    while (n_out_ > 0) {
+      const int oldest = ((step_cur_ - n_out_ + 1) % kStepEvents + kStepEvents) % kStepEvents;
+      if (!event_done(step_ev_[oldest])) break;
+      --n_out_;
+    }
+    return n_out_;
+  }
+  bool paced() { return pace_ > 0 && !noalloc_ && n_out_ >= pace_ && outstanding() >= pace_; }
 
   std::vector<uint64_t> snapshot() const {
     std::vector<uint64_t> v(n_slots_);
@@ -1592,6 +1637,8 @@ class Engine {
   hipEvent_t step_ev_[kStepEvents] = {};
   int step_cur_ = 0;
   bool step_pending_ = false;
+  int n_out_ = 0;                        // queued steps, see paced()
+  int pace_ = kPaceSteps;
   int max_ahead_ = kMaxAhead;
   bool noalloc_ = false;                 // see init_noalloc
   int n_slots_ = kMaxSlots;

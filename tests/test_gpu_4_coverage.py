@@ -176,3 +176,34 @@ def test_short_strip_smoother_parity(torch_cuda, monkeypatch, psfname):
         assert st["iters"] == it and st["reason"] == why
         assert _rel(u, u_ref) <= 2e-5
     assert _rel(res["short"][0], res["usual"][0]) <= 1e-5
+
+
+# ------------------------------------------------------------ step pacing
+def test_step_pacing_depth_leaves_batched_results_bitwise_unchanged(torch_cuda, monkeypatch):
+    """The scheduler's step pacing (how many steps it keeps queued on the
+    device before issuing the next) only regroups jobs into launches: a batch
+    of uneven-set images gives the same bits and per-level statistics with
+    pacing off, at depth 2 and at depth 3, and the same as each image alone."""
+    t = torch_cuda
+    probs = synth.batch_problems(24)
+    gs = [t.from_numpy(q.g_delta.astype(np.float32)).to("cuda:0") for q in probs]
+    kw = dict(ks=[q.k for q in probs], precision="f32", params=[{"delta": q.delta} for q in probs])
+    res = {}
+    for depth in ("0", "2", "3"):
+        monkeypatch.setenv("EECMG_PACE_STEPS", depth)
+        print(f"  batched, pacing depth {depth}", flush=True)
+        outs, sts = eecmg.restore_batch_dev(gs, [q.psf for q in probs], [q.n_levels for q in probs], **kw)
+        t.cuda.synchronize()
+        res[depth] = ([o.cpu().numpy() for o in outs], sts)
+    monkeypatch.setenv("EECMG_PACE_STEPS", "2")
+    for i in (0, 7, 23):
+        q = probs[i]
+        print(f"  alone {q.name} {q.shape}", flush=True)
+        u, st = eecmg.restore_dev(gs[i], q.psf, q.n_levels, precision="f32", delta=q.delta, k=q.k)
+        t.cuda.synchronize()
+        np.testing.assert_array_equal(u.cpu().numpy(), res["2"][0][i])
+        assert st == res["2"][1][i]
+    for depth in ("0", "3"):
+        for a, b in zip(res[depth][0], res["2"][0]):
+            np.testing.assert_array_equal(a, b)
+        assert res[depth][1] == res["2"][1]
