@@ -20,6 +20,8 @@ constexpr int kTH = 4 * kV;
 // Transfer / element-wise tiles: 64 x 16 pixels per 256-thread block.
 constexpr int kXW = 64;
 constexpr int kXH = 16;
+// Extrapolation (Pi) tiles: kPiTH x kXW nodes of the coarser grid per block.
+constexpr int kPiTH = 4;
 
 // Smoother and cascade ids (same values as eecmg_smoother / eecmg_cascade).
 enum : int32_t { kSmootherCgls = 0, kSmootherMr = 1 };

@@ -452,23 +452,24 @@ __device__ __forceinline__ XArgs make_xargs(const JobDesc& d, int src, int dst) 
 // Pi on the engine's levels, one 2 x 2 block of grid B per thread: the four
 // outputs (2a + i, 2b + j) share the corrections d(a..a+1, b..b+1), so each
 // is computed once instead of up to four times; every output is the same
-// expression as pi_value (bit-identical).
+// expression as pi_value (bit-identical).  A block covers kPiTH x kXW nodes
+// of grid A, one per thread: a single chain of loads per thread keeps the
+// kernel short on the small levels, where its latency is all it costs.
 template <typename T>
 __device__ __forceinline__ void pi_tile2(const XArgs& x, int t) {
   const int HA = (x.hd + 1) / 2, WA = (x.wd + 1) / 2;
   const int tiles_x = (WA + kXW - 1) / kXW;
   const int ty = t / tiles_x, tx = t - ty * tiles_x;
   const int b = tx * kXW + (threadIdx.x & 63);
-  if (b >= WA) return;
+  const int a = ty * kPiTH + (threadIdx.x >> 6);
+  if (b >= WA || a >= HA) return;
   const T* uA = (const T*)x.s0;
   const T* uB = (const T*)x.s1;
   T* out = (T*)x.dst;
   const PiD<T> D{uA, uB, x.h0, x.w0, x.p0, x.p1};
   const int q = 2 * b;
   const bool q1 = q + 1 < x.wd;
-  for (int k = 0; k < kXH / 4; ++k) {
-    const int a = ty * kXH + (threadIdx.x >> 6) * (kXH / 4) + k;
-    if (a >= HA) break;
+  {
     const int p = 2 * a;
     const bool p1 = p + 1 < x.hd;
     // d beyond the virtual nodes is never needed: those outputs do not exist
@@ -1390,7 +1391,7 @@ int blocks_for_stage(Stage st, const JobDesc& d) {
     case kCgFinB:
     case kMrFinInit:
     case kMrFin: return 1;
-    case kXfExtrap: return tiles2((d.hB + 1) / 2, (d.wB + 1) / 2, kXH, kXW);  // 2 x 2 outputs per thread
+    case kXfExtrap: return tiles2((d.hB + 1) / 2, (d.wB + 1) / 2, kPiTH, kXW);  // 2 x 2 outputs per thread
     case kXfFused: return tiles2(d.h, d.w, kFY, d.f64 ? kFX : sgeo_ow(d.pm_steps >= 1));
     case kXfFusedSmall: return tiles2(d.h, d.w, kFYSmall, d.f64 ? kFX : sgeo_ow(d.pm_steps >= 1));
     case kFlushU: return tiles2(d.h, d.w, kXH, kXW);

@@ -227,6 +227,25 @@ def restore_dev(g_delta, psf, n_levels, caps=None, k=10.0, out=None, stream=None
     return out, st.to_dict()
 
 
+def _override_params(p, kv):
+    """Set the given fields of an eecmg_params struct (as make_params does)."""
+    for k, v in kv.items():
+        conv = _PARAM_CONV.get(k)
+        if conv is None:
+            raise TypeError(f"unknown parameter {k!r}")
+        setattr(p, k, conv(v))
+
+
+_PARAM_CONV = {
+    "precision": lambda v: PRECISIONS[v] if isinstance(v, str) else int(v),
+    "stop_rule": lambda v: 1 if v else 0,
+    "delta": float, "c": float, "tau": float, "pm_steps": int, "smooth_h": float, "coarse_psf_mode": int,
+    "guard_eps": float,
+    "smoother": lambda v: SMOOTHERS[v] if isinstance(v, str) else int(v),
+    "cascade": lambda v: CASCADES[v] if isinstance(v, str) else int(v),
+}
+
+
 def restore_batch_dev(gs, psfs, n_levels, caps=None, ks=None, outs=None, stream=None, params=None, **kw):
     """Batched device restore of a list of tensors with per-image PSFs and
     level counts.  params: optional list of per-image keyword dicts (override
@@ -236,26 +255,30 @@ def restore_batch_dev(gs, psfs, n_levels, caps=None, ks=None, outs=None, stream=
     n = len(gs)
     if outs is None:
         outs = [torch.empty_like(g) for g in gs]
+    # one default struct with kw applied, copied per image and overridden
+    # with that image's params (marshalling stays small next to the cascade)
+    base = make_params(**kw)
     P = (Params * n)()
-    sts = [Stats() for _ in range(n)]
+    sts = (Stats * n)()
+    stats_size = ctypes.sizeof(Stats)
     psf_arrs, radii = [], []
     for i in range(n):
-        kwi = dict(kw)
-        if params is not None:
-            kwi.update(params[i])
-        pi = make_params(**kwi)
-        sts[i].struct_size = ctypes.sizeof(Stats)
-        pi.stats = ctypes.cast(ctypes.pointer(sts[i]), ctypes.c_void_p)
-        P[i] = pi
+        P[i] = base
+        pi = P[i]
+        if params is not None and params[i]:
+            _override_params(pi, params[i])
+        sts[i].struct_size = stats_size
+        pi.stats = ctypes.addressof(sts[i])
         a, r = _psf_arr(psfs[i])
         psf_arrs.append(a)
         radii.append(r)
     vp = ctypes.c_void_p
-    g_ptrs = (vp * n)(*[vp(g.data_ptr()) for g in gs])
-    o_ptrs = (vp * n)(*[vp(o.data_ptr()) for o in outs])
+    g_ptrs = (vp * n)(*[g.data_ptr() for g in gs])
+    o_ptrs = (vp * n)(*[o.data_ptr() for o in outs])
     Hs = (ctypes.c_int * n)(*[g.shape[0] for g in gs])
     Ws = (ctypes.c_int * n)(*[g.shape[1] for g in gs])
-    psf_ptrs = (ctypes.POINTER(ctypes.c_double) * n)(*[_dptr(a) for a in psf_arrs])
+    psf_ptrs = ctypes.cast((vp * n)(*[a.ctypes.data for a in psf_arrs]),
+                           ctypes.POINTER(ctypes.POINTER(ctypes.c_double)))
     rads = (ctypes.c_int * n)(*radii)
     Ls = (ctypes.c_int * n)(*[int(x) for x in n_levels])
     kk = (ctypes.c_double * n)(*[float(x) for x in (ks if ks is not None else [10.0] * n)])
