@@ -407,18 +407,41 @@ __device__ __forceinline__ TileGeo tile_geo(const JobDesc& d, int t) {
 // combine(load(o)), elements outside the image are zero (the operator's zero
 // boundary condition); o is the element's 32-bit offset in the level's
 // pitched array.
+// The loads of up to 16 elements per thread are issued together (from
+// clamped, always valid addresses) before any is used, so a small level's
+// pass waits for one round of memory latency instead of one per tile row.
 template <typename T, typename P, typename LoadF, typename CombF>
 __device__ __forceinline__ void load_tile(T* __restrict__ tile, const TileGeo& g, LoadF load, CombF combine) {
   const int R = g.R;
   constexpr int NWV = P::NT / 64;
-  for (int ly = g.wave; ly < P::TH + 2 * R; ly += NWV) {
-    const int gy = g.y0 - R + ly;
-    const bool row_in = gy >= 0 && gy < g.h;
-    for (int lx = g.lane; lx < P::TW + 2 * R; lx += 64) {
-      const int gx = g.x0 - R + lx;
-      T v = T(0);
-      if (row_in && gx >= 0 && gx < g.w) v = combine(load((unsigned)(gy * g.pitch + gx)));
-      tile[ly * P::LW + lx] = v;
+  constexpr int NR = (P::LH + NWV - 1) / NWV, NC = (P::LW + 63) / 64;  // per thread, at the largest radius
+  constexpr int CR = NR * NC <= 16 ? NR : (16 / NC > 0 ? 16 / NC : 1);  // rows per burst
+  const int rows = P::TH + 2 * R, cols = P::TW + 2 * R;
+  using V = decltype(load(0u));
+#pragma unroll
+  for (int r0 = 0; r0 < NR; r0 += CR) {
+    V v[CR][NC];
+#pragma unroll
+    for (int i = 0; i < CR; ++i) {
+      const int gy = min(max(g.y0 - R + g.wave + (r0 + i) * NWV, 0), g.h - 1);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int gx = min(max(g.x0 - R + g.lane + 64 * c, 0), g.w - 1);
+        v[i][c] = load((unsigned)(gy * g.pitch + gx));
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < CR; ++i) {
+      const int ly = g.wave + (r0 + i) * NWV;
+      const int gy = g.y0 - R + ly;
+      const bool row_in = r0 + i < NR && ly < rows && gy >= 0 && gy < g.h;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int lx = g.lane + 64 * c;
+        const int gx = g.x0 - R + lx;
+        if (r0 + i < NR && ly < rows && lx < cols)
+          tile[ly * P::LW + lx] = (row_in && gx >= 0 && gx < g.w) ? combine(v[i][c]) : T(0);
+      }
     }
   }
 }
