@@ -4,24 +4,25 @@ The library picks, per level, the strip height of the streaming blur kernels
 (tall, usual or short strips, by how many strips the level yields), whether a
 level folds its finalize kernels into the smoother passes (by tile count),
 whether the CGLS solution update runs every second iteration (by level size),
-how many unconfirmed iterations the scheduler keeps queued per job and how
-many steps it keeps queued on the device before it issues the next one.
+how many unconfirmed iterations the scheduler keeps queued per job, how many
+steps it keeps queued on the device before it issues the next one and over
+how many lanes (engines with their own streams) a batched call is split.
 Each choice is a threshold read from the environment when a restore is
 planned (EECMG_TALL_MIN_TILES, EECMG_SHORT_MAX_TILES, EECMG_FOLD_MAX_TILES,
 EECMG_FOLD_MAX_TILES_STREAM, EECMG_LAZY_MIN_PIXELS, EECMG_MAX_AHEAD,
-EECMG_PACE_STEPS).  This module times restores of representative workloads
--- the 4096^2 disk and 1024^2 Gaussian single images and a batch of images
-of the uneven set -- and walks the thresholds one at a time over a few
-candidates (coordinate descent, two passes), keeping a change only when,
-timed in turn against the current setting, the geometric mean of the
-workloads' times improves by more than `min_gain` and no workload gets
-slower by more than `min_gain`.  The result is cached as JSON keyed by a
+EECMG_PACE_STEPS, EECMG_BATCH_LANES).  This module times restores of
+representative workloads -- the 4096^2 disk and 1024^2 Gaussian single
+images and a batch of images of the uneven set -- and walks the thresholds
+one at a time over a few candidates (coordinate descent, two passes),
+keeping a change only when, timed in turn against the current setting, the
+geometric mean of the workloads' times improves by more than `min_gain` and
+no workload gets slower by more than `min_gain`.  The result is cached as JSON keyed by a
 hash of the library's sources and the device name, so a rebuilt library or
 another device tunes again.
 
 Only thresholds that leave every result unchanged within the library's
 parity bars are tuned: folding and the every-second-iteration update are
-bit-identical schedules, run-ahead and pacing only regroup jobs into
+bit-identical schedules, run-ahead, pacing and lanes only regroup jobs into
 launches, and the strip height only regroups the partial sums
 of inner products (tests cover every choice against the oracle).
 """
@@ -48,6 +49,7 @@ KNOBS = {
     "EECMG_LAZY_MIN_PIXELS": (1 << 20, [1 << 18, 1 << 20, 1 << 40]),
     "EECMG_MAX_AHEAD": (2, [2, 3]),
     "EECMG_PACE_STEPS": (2, [0, 2, 3]),
+    "EECMG_BATCH_LANES": (3, [1, 2, 3]),
 }
 
 

@@ -207,3 +207,26 @@ def test_step_pacing_depth_leaves_batched_results_bitwise_unchanged(torch_cuda, 
         for a, b in zip(res[depth][0], res["2"][0]):
             np.testing.assert_array_equal(a, b)
         assert res[depth][1] == res["2"][1]
+
+
+# ------------------------------------------------------------ batch lanes
+def test_batch_lanes_leave_results_bitwise_unchanged(torch_cuda, monkeypatch):
+    """A batched call split over several lanes (engines with their own
+    streams and host threads) gives the same bits and per-level statistics as
+    one lane: each image's arithmetic does not depend on what shares its
+    launches."""
+    t = torch_cuda
+    probs = synth.batch_problems(24)
+    gs = [t.from_numpy(q.g_delta.astype(np.float32)).to("cuda:0") for q in probs]
+    kw = dict(ks=[q.k for q in probs], precision="f32", params=[{"delta": q.delta} for q in probs])
+    res = {}
+    for lanes in ("1", "2", "3"):
+        monkeypatch.setenv("EECMG_BATCH_LANES", lanes)
+        print(f"  batched, {lanes} lane(s)", flush=True)
+        outs, sts = eecmg.restore_batch_dev(gs, [q.psf for q in probs], [q.n_levels for q in probs], **kw)
+        t.cuda.synchronize()
+        res[lanes] = ([o.cpu().numpy() for o in outs], sts)
+    for lanes in ("2", "3"):
+        for a, b in zip(res[lanes][0], res["1"][0]):
+            np.testing.assert_array_equal(a, b)
+        assert res[lanes][1] == res["1"][1]
