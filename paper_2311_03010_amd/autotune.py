@@ -16,9 +16,9 @@ images and a batch of images of the uneven set -- and walks the thresholds
 one at a time over a few candidates (coordinate descent, two passes),
 keeping a change only when, timed in turn against the current setting, the
 geometric mean of the workloads' times improves by more than `min_gain` and
-no workload gets slower by more than `min_gain`.  The result is cached as JSON keyed by a
-hash of the library's sources and the device name, so a rebuilt library or
-another device tunes again.
+no workload gets slower by more than `min_gain`.  The result is cached as
+JSON keyed by a hash of the library's sources and the device name, so a
+rebuilt library or another device tunes again.
 
 Only thresholds that leave every result unchanged within the library's
 parity bars are tuned: folding and the every-second-iteration update are
