@@ -46,6 +46,7 @@ regions come after it.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -378,22 +379,34 @@ def set_leg(torch, eecmg, synth, n_images, steps, form="both"):
         eecmg.restore_batch_dev(gs, psfs, Ls, ks=ks, outs=bo, precision="f32", params=prm)
 
     def timed(fn):
+        # every step timed on its own, the interpreter's cyclic garbage
+        # collector paused meanwhile (a collection over the many image objects
+        # takes tens of ms); the median step is reported
         fn()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / steps
+        gc.collect()
+        gc.disable()
+        ts = []
+        try:
+            for _ in range(steps):
+                t0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+        finally:
+            gc.enable()
+        return float(np.median(ts)), [round(t * 1e3, 3) for t in ts]
 
-    tp = timed(plain) if form != "batched" else float("nan")
-    tb = timed(batched) if form != "plain" else float("nan")
+    tp, tps = timed(plain) if form != "batched" else (float("nan"), [])
+    tb, tbs = timed(batched) if form != "plain" else (float("nan"), [])
     equal = form == "both" and all(torch.equal(a, b) for a, b in zip(po, bo))
     return {"workload": f"uneven batch of {n_images} images, sides log-uniform in [128, 2048], "
                         "Gaussian sigma U[1,4] / disk r U{2..6} PSFs, FP32",
             "images": n_images, "mpixels": round(px / 1e6, 3), "steps": steps,
-            "plain": {"value": round(px / tp / 1e6, 3), "unit": "Mpixel/s", "ms_per_step": round(tp * 1e3, 3)},
-            "batched": {"value": round(px / tb / 1e6, 3), "unit": "Mpixel/s", "ms_per_step": round(tb * 1e3, 3)},
+            "plain": {"value": round(px / tp / 1e6, 3), "unit": "Mpixel/s", "ms_per_step": round(tp * 1e3, 3),
+                      "ms_each": tps},
+            "batched": {"value": round(px / tb / 1e6, 3), "unit": "Mpixel/s", "ms_per_step": round(tb * 1e3, 3),
+                        "ms_each": tbs},
             "speedup_vs_plain": round(tp / tb, 3), "bitwise_equal_to_plain": bool(equal)}
 
 
@@ -511,7 +524,7 @@ def main():
     ap.add_argument("--batch", type=int, default=4, help="images in the batched leg (0 = skip)")
     ap.add_argument("--set-images", type=int, default=256,
                     help="images in the uneven plain-vs-batched set (0 = skip)")
-    ap.add_argument("--set-steps", type=int, default=2)
+    ap.add_argument("--set-steps", type=int, default=5)
     ap.add_argument("--set-form", default="both", choices=["both", "plain", "batched"],
                     help="which forms of the uneven set to run (profiling one form)")
     ap.add_argument("--served-requests", type=int, default=2000, help="served requests (0 = skip)")
@@ -569,8 +582,11 @@ def main():
         restore_once()
     torch.cuda.synchronize()
 
-    # the throughput: kernel timing off
+    # the throughput: kernel timing off, the interpreter's cyclic garbage
+    # collector paused
     _log(f"bench: timing {args.steps} steps")
+    gc.collect()
+    gc.disable()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = None
@@ -578,6 +594,7 @@ def main():
         _, stats = restore_once()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    gc.enable()
     ms_step = dt / args.steps * 1e3
     value = H * W * args.steps / dt / 1e6
     u_gpu = out.cpu().numpy()

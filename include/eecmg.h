@@ -284,9 +284,8 @@ int eecmg_op_pm_step_dev(const void* u_dev, void* out_dev, int H, int W, double 
  * finalize, 12 extrapolation, 13 quadratic interpolation, 14 linear
  * prolongation, 15 smoothing S, 16 denoising D, 17 output copy, 18 fused
  * prolongation + S (+ first D step), 19 the same on short tiles, 20 coarse
- * levels in one block per image, 21 deferred solution update, 22 CGLS pass B
- * recomputing q = H p (FP32 levels with a streaming blur kernel, where pass A
- * stores no q).  eecmg_profile_read_level returns, for the launches whose
+ * levels in one block per image, 21 deferred solution update (22 is
+ * unused).  eecmg_profile_read_level returns, for the launches whose
  * jobs all worked on level index `level` (0 = coarsest; the coarse-level
  * kernel counts as level 0), the number of launches of one stage (-1: every
  * stage) and their summed duration, including the passes that found their

@@ -106,6 +106,16 @@ __device__ __forceinline__ GPtrC<T> gpc(const void* p) {
   return GPtrC<T>{(const EECMG_G T*)p};
 }
 
+// Order a wave's LDS stores before its following LDS loads (of other lanes'
+// values).  The LDS unit performs one wave's operations in issue order, so
+// only the compiler has to be kept from moving them across each other; the
+// waves of a block run independently.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -164,7 +174,7 @@ struct ConvGeneral {
   static_assert(TH_ % 4 == 0, "four waves share the tile rows");
   static constexpr int KV = TH_ / 4;
   static constexpr int NT = 256, TW = kTW, TH = TH_, LW = kTW + 2 * RMAX, LH = TH_ + 2 * RMAX, RC = RMAX;
-  static constexpr bool kRuntimeR = true, kStream = false, kVSym = false, kDconv = false;
+  static constexpr bool kRuntimeR = true, kStream = false, kVSym = false;
   static constexpr int kWavesPerEU = 1;
   template <typename Emit>
   __device__ static __forceinline__ void conv(const T* __restrict__ tile, const T* __restrict__ taps, int R, int wave,
@@ -237,10 +247,9 @@ constexpr int stream_waves(int R, int regs) {
 template <typename T, int R, int SM = 0>
 struct ConvSep {
   using S = Slide<R>;
-  static constexpr int NT = 64, TW = kTW, TH = strip_th(R, SM), LW = kTW + 2 * R, RC = R;
+  static constexpr int NT = 64 * kStripsPerBlock, TW = kTW, TH = strip_th(R, SM), LW = kTW + 2 * R, RC = R;
   static constexpr bool kRuntimeR = false, kStream = true;
   static constexpr bool kVSym = false;  // the column filter need not be symmetric
-  static constexpr bool kDconv = false;  // two windows of 2 (2R + 1) taps would crowd the registers
   // streaming kernels hide memory latency with waves: ask the register
   // allocator for at least this many per SIMD where the state fits (it
   // otherwise trades occupancy for instruction-level parallelism)
@@ -296,10 +305,9 @@ constexpr int sym_ntaps(int R, bool disk) { return sym_offset(R, disk, R + 1); }
 template <typename T, int R, bool DISK, int SM = 0>
 struct ConvSym {
   using S = Slide<R>;
-  static constexpr int NT = 64, TW = kTW, TH = strip_th(R, SM), LW = kTW + 2 * R, RC = R;
+  static constexpr int NT = 64 * kStripsPerBlock, TW = kTW, TH = strip_th(R, SM), LW = kTW + 2 * R, RC = R;
   static constexpr bool kRuntimeR = false, kStream = true;
   static constexpr bool kVSym = true;  // symmetric in the vertical direction: strips may walk up
-  static constexpr bool kDconv = false;  // two quadrant windows would crowd the registers
   // streaming kernels hide memory latency with waves: ask the register
   // allocator for at least this many per SIMD where the state fits (it
   // otherwise trades occupancy for instruction-level parallelism)
@@ -348,12 +356,9 @@ struct ConvSym {
 template <typename T, int R, int SM = 0>
 struct ConvBox {
   using S = Slide<R>;
-  static constexpr int NT = 64, TW = kTW, TH = strip_th(R, SM), LW = kTW + 2 * R, RC = R;
+  static constexpr int NT = 64 * kStripsPerBlock, TW = kTW, TH = strip_th(R, SM), LW = kTW + 2 * R, RC = R;
   static constexpr bool kRuntimeR = false, kStream = true;
   static constexpr bool kVSym = true;  // symmetric in the vertical direction: strips may walk up
-  // pass B may recompute q (k_cg_bd): the window state is small (not with
-  // tall strips, whose levels keep the stored q)
-  static constexpr bool kDconv = SM == 0;
   // streaming kernels hide memory latency with waves: ask the register
   // allocator for at least this many per SIMD where the state fits (it
   // otherwise trades occupancy for instruction-level parallelism)
@@ -387,6 +392,10 @@ struct TileGeo {
   int R, h, w, pitch, y0, x0, wave, lane;
 };
 
+// Block t of a smoother pass: the tile t (general policy, four waves share
+// it), or the strips kStripsPerBlock t + wave (streaming policies, one per
+// wave; a strip index past the level's last strip lies below the image, and
+// stream_strip returns at once for it).
 template <typename P>
 __device__ __forceinline__ TileGeo tile_geo(const JobDesc& d, int t) {
   TileGeo g;
@@ -394,12 +403,13 @@ __device__ __forceinline__ TileGeo tile_geo(const JobDesc& d, int t) {
   g.h = uni(d.h);
   g.w = uni(d.w);
   g.pitch = uni(d.pitch);
-  const int tiles_x = uni(d.tiles_x);
-  const int ty = t / tiles_x, tx = t - ty * tiles_x;
-  g.y0 = ty * P::TH;
-  g.x0 = tx * P::TW;
   g.wave = uni(threadIdx.x >> 6);
   g.lane = threadIdx.x & 63;
+  const int tiles_x = uni(d.tiles_x);
+  const int s = P::kStream ? t * kStripsPerBlock + g.wave : t;
+  const int ty = s / tiles_x, tx = s - ty * tiles_x;
+  g.y0 = ty * P::TH;
+  g.x0 = tx * P::TW;
   return g;
 }
 
@@ -549,7 +559,9 @@ __device__ __forceinline__ void stream_strip(const TileGeo& g, bool up, unsigned
   constexpr int D = GS < kPrefetch ? GS : kPrefetch;
   constexpr int RW = 2 * kTW;  // row buffer width: every lane writes both of its values
   static_assert(LW <= RW, "row buffer too narrow");
-  __shared__ T rowbuf[2 * RW];
+  __shared__ T rowbufs[kStripsPerBlock][2 * RW];  // one row buffer per wave
+  if (g.y0 >= g.h) return;  // a strip index past the level's last strip
+  T* const rowbuf = rowbufs[g.wave];
   using VI = decltype(load_in(0u));
   using VN = decltype(load_int(0u));
   using VE = decltype(load_em(0u));
@@ -605,7 +617,7 @@ __device__ __forceinline__ void stream_strip(const TileGeo& g, bool up, unsigned
         const bool in = t >= R && t < R + TH && y < g.h && inic;
         interior(in ? (unsigned)(y * g.pitch + ic) : none, lane >= R ? v1 : v2, in, n);
       }
-      __syncthreads();
+      wave_lds_sync();
       const T* row = rb + lane + R;
       cen[k] = row[0];
       const T out = P::step(st, row, k);
@@ -954,7 +966,7 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
     beta = T(0);
   } else if (foldb && k > 0) {
     double v[2];
-    sum_partials<2, P::NT>(d.partials, uni(d.dconv) ? uni(d.ntiles_b) : uni(d.ntiles), d.pstride, kCompCgB, v);
+    sum_partials<2, P::NT>(d.partials, uni(d.ntiles), d.pstride, kCompCgB, v);
     const int reason = stop_reason(d, k, v[0], v[1], st->gamma0, !finite_d(v[0]) || !finite_d(v[1]));
     if (L.t == 0 && threadIdx.x == 0) fin_cg_b(d, d.st, v);
     if (reason != kStopNone) return;
@@ -976,7 +988,7 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
     P::init(ps, (const T*)d.taps);
     const unsigned n = (unsigned)(g.h * g.pitch);
     const auto S = bview<T>(d.s, n), Po = bview<T>(d.p[par], first ? 0u : n), Pn = bview<T>(d.p[par ^ 1], n);
-    const auto Q = bview<T>(d.q[0], uni(d.dconv) ? 0u : n);  // pass B recomputes q (dconv): no store
+    const auto Q = bview<T>(d.q[0], n);
     stream_strip<T, P>(
         g, strip_up<P>(g), n, ps, [&](unsigned o) { return Two<T>{S.ld(o), Po.ld(o)}; }, comb, NoLoadF{},
         [&](unsigned o, T v, bool, NoLoad) { Pn.st(o, v); }, NoLoadF{},
@@ -1093,106 +1105,6 @@ __device__ __forceinline__ void cg_b_body(const JobDesc& d, const TileGeo& g, in
   }
 }
 
-// Pass B on levels whose pass A does not store q (dconv): the strip
-// recomputes q = H p_k from p_k itself and then s = H^T r_new, two sliding
-// windows one after the other.  Lane l holds p_k at columns x0 - 2R + l (and
-// x0 + 64 - 2R + l for l < 2R), so the first window gives q at column
-// x0 - R + l for all 64 lanes; r_new = r - alpha q there (zero outside the
-// image: the operator's boundary condition for H^T), and the second window
-// gives s at the 64 - 2R columns x0 .. x0 + 63 - 2R (lanes R .. 63 - R),
-// which is the strip's output width.  Step t reads p row y0 - 2R + t; the
-// first window completes q row y0 - 3R + t; the second window consumes the
-// r_new row of the previous step (one barrier per step) and completes s row
-// y0 - 4R - 1 + t.  q is bit-identical to pass A's (same policy, same order
-// of rows) except where pass A walked its strip bottom-up.
-template <typename T, typename P, int UM>
-__device__ __forceinline__ void cg_b_dconv(const JobDesc& d, int tile, int par, T alpha, T alpha_prev,
-                                           double (&part)[2]) {
-  constexpr int R = P::RC, NW = 2 * R + 1, GS = strip_group(R), TH = strip_th2(R), TWB = strip_tw2(R);
-  constexpr int LH = TH + 4 * R + 1, NG = LH / GS;
-  static_assert(NG * GS == LH && GS % NW == 0, "strip height must fill whole row groups");
-  constexpr int D = GS < kPrefetch ? GS : kPrefetch;
-  constexpr int RWP = 2 * kTW, RWR = kTW + 2 * R;
-  __shared__ T rowp[2 * RWP];
-  __shared__ T rowr[2 * RWR];
-  const int h = uni(d.h), w = uni(d.w), pitch = uni(d.pitch);
-  const int tiles_x = uni(d.tiles_x_b);
-  const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
-  const int y0 = ty * TH, x0 = tx * TWB;
-  const int lane = threadIdx.x & 63;
-  const unsigned n = (unsigned)(h * pitch), none = n;
-  const auto Pk = bview<T>(d.p[par ^ 1], n), Pk1 = bview<T>(d.p[par], n), Ro = bview<T>(d.r[par], n);
-  const auto Rn = bview<T>(d.r[par ^ 1], n), U = bview<T>(d.u, n), S = bview<T>(d.s, n);
-  typename P::St s1, s2;
-  P::init(s1, (const T*)d.taps);
-  P::init(s2, (const T*)d.taps_t);
-  const int cp1 = x0 - 2 * R + lane, cp2 = x0 + kTW - 2 * R + lane;
-  const bool inp1 = cp1 >= 0 && cp1 < w, inp2 = lane < 2 * R && cp2 < w;
-  const int cq = x0 - R + lane;
-  const bool inq = cq >= 0 && cq < w;
-  const bool outl = lane >= R && lane < kTW - R && inq;
-  T pa[GS], pb[GS], rr[GS];
-  Three<T> ex[GS];
-  auto issue = [&](int t, T& a, T& b, T& r, Three<T>& e) {
-    const int yp = y0 - 2 * R + t;
-    const bool pok = t < TH + 4 * R && yp >= 0 && yp < h;
-    a = Pk.ld((pok && inp1) ? (unsigned)(yp * pitch + cp1) : none);
-    b = Pk.ld((pok && inp2) ? (unsigned)(yp * pitch + cp2) : none);
-    const int yq = yp - R;
-    const bool qok = t >= 2 * R && t < TH + 4 * R && yq >= 0 && yq < h;
-    r = Ro.ld((qok && inq) ? (unsigned)(yq * pitch + cq) : none);
-    const int ys = yp - 2 * R - 1;
-    const unsigned os = (t >= 4 * R + 1 && t < LH && ys < h && outl) ? (unsigned)(ys * pitch + cq) : none;
-    if constexpr (UM == kUDefer) {
-      e = Three<T>{T(0), T(0), T(0)};
-    } else if constexpr (UM == kUTwo) {
-      e = Three<T>{U.ld(os), Pk.ld(os), Pk1.ld(os)};
-    } else {
-      e = Three<T>{U.ld(os), Pk.ld(os), T(0)};
-    }
-  };
-#pragma unroll
-  for (int t = 0; t < D; ++t) issue(t, pa[t], pb[t], rr[t], ex[t]);
-#pragma unroll 1
-  for (int gi = 0; gi < NG; ++gi) {
-#pragma unroll
-    for (int kg = 0; kg < GS; ++kg) {
-      const int t = gi * GS + kg, k1 = kg % NW, k2 = (kg + NW - 1) % NW;
-      const T a = pa[kg], b = pb[kg], r = rr[kg];
-      const Three<T> e = ex[kg];
-      issue(t + D, pa[(kg + D) % GS], pb[(kg + D) % GS], rr[(kg + D) % GS], ex[(kg + D) % GS]);
-      T* bp = rowp + (t & 1) * RWP;
-      bp[lane] = a;
-      bp[kTW + lane] = b;
-      __syncthreads();
-      // first window: q at column cq of row yq = y0 - 3R + t
-      const T q = P::step(s1, bp + lane + R, k1);
-      const int yq = y0 - 3 * R + t;
-      const bool qrow = t >= 2 * R && t < TH + 4 * R && yq >= 0 && yq < h;
-      const T rn = (qrow && inq) ? fma(-alpha, q, r) : T(0);
-      {
-        const bool own = outl && yq >= y0 && yq < y0 + TH && qrow;
-        Rn.st(own ? (unsigned)(yq * pitch + cq) : none, rn);
-        part[0] += own ? (double)rn * (double)rn : 0.0;
-      }
-      T* br = rowr + (t & 1) * RWR;
-      br[R + lane] = rn;
-      // second window: the r_new row written in the previous step
-      const T* brp = rowr + ((t + 1) & 1) * RWR;
-      const T sv = P::step(s2, brp + R + lane, k2);
-      {
-        const int ys = y0 - 4 * R - 1 + t;
-        const bool own = outl && t >= 4 * R + 1 && ys < h;
-        const unsigned o = own ? (unsigned)(ys * pitch + cq) : none;
-        S.st(o, sv);
-        part[1] += own ? (double)sv * (double)sv : 0.0;
-        if constexpr (UM == kUTwo) U.st(o, fma(alpha, e.b, fma(alpha_prev, e.c, e.a)));
-        else if constexpr (UM == kUOne) U.st(o, fma(alpha, e.b, e.a));
-      }
-    }
-  }
-}
-
 template <typename T, typename P>
 __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWavesPerEU))) void k_cg_b(LaunchList ll, const JobDesc* __restrict__ descs) {
   const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
@@ -1227,28 +1139,6 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
     cg_b_body<T, P, kUTwo>(d, g, par, alpha, (T)st->alph[(k - 1) & 1], part);
   else
     cg_b_body<T, P, kUOne>(d, g, par, alpha, T(0), part);
-  block_sum_store<P::NT, 2>(part, d.partials + (size_t)1 * d.pstride + L.t, d.pstride);
-}
-
-// Pass B of the levels whose pass A stores no q (see cg_b_dconv): a kernel of
-// its own, so the register budget of the plain pass B is not affected.
-template <typename T, typename P>
-__global__ __launch_bounds__(P::NT) void k_cg_bd(LaunchList ll, const JobDesc* __restrict__ descs) {
-  const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
-  const JobDesc& d = descs[L.d];
-  const SolverState* st = d.st;
-  if (__builtin_amdgcn_readfirstlane(st->done)) return;
-  const int par = uni(st->par);
-  const int k = uni(st->k);
-  const T alpha = (T)st->alph[k & 1];
-  const int um = uni(d.lazy_u) == 0 ? kUOne : ((k & 1) ? kUTwo : kUDefer);
-  double part[2] = {0.0, 0.0};
-  if (um == kUDefer)
-    cg_b_dconv<T, P, kUDefer>(d, L.t, par, alpha, T(0), part);
-  else if (um == kUTwo)
-    cg_b_dconv<T, P, kUTwo>(d, L.t, par, alpha, (T)st->alph[(k - 1) & 1], part);
-  else
-    cg_b_dconv<T, P, kUOne>(d, L.t, par, alpha, T(0), part);
   block_sum_store<P::NT, 2>(part, d.partials + (size_t)1 * d.pstride + L.t, d.pstride);
 }
 
@@ -1341,10 +1231,11 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
   g.h = H;
   g.w = W;
   g.pitch = W;
-  g.y0 = (blockIdx.x / tiles_x) * P::TH;
-  g.x0 = (blockIdx.x % tiles_x) * P::TW;
   g.wave = uni(threadIdx.x >> 6);
   g.lane = threadIdx.x & 63;
+  const int t = P::kStream ? (int)blockIdx.x * kStripsPerBlock + g.wave : (int)blockIdx.x;
+  g.y0 = (t / tiles_x) * P::TH;
+  g.x0 = (t % tiles_x) * P::TW;
   const auto xg = gpc<T>(x);
   auto yg = gp<T>(y);
   if constexpr (P::kStream) {
@@ -1377,12 +1268,6 @@ hipError_t launch_policy(Stage st, const LaunchList& ll, const JobDesc* descs, h
     case kCgInit2: hipLaunchKernelGGL((k_cg_init2<T, P>), grid, block, 0, s, ll, descs); break;
     case kCgA: hipLaunchKernelGGL((k_cg_a<T, P>), grid, block, 0, s, ll, descs); break;
     case kCgB: hipLaunchKernelGGL((k_cg_b<T, P>), grid, block, 0, s, ll, descs); break;
-    case kCgBD:
-      if constexpr (P::kDconv) {
-        hipLaunchKernelGGL((k_cg_bd<T, P>), grid, block, 0, s, ll, descs);
-        break;
-      }
-      return hipErrorInvalidValue;
     case kMrPass: hipLaunchKernelGGL((k_mr_pass<T, P>), grid, block, 0, s, ll, descs); break;
     default: return hipErrorInvalidValue;
   }
@@ -1391,7 +1276,8 @@ hipError_t launch_policy(Stage st, const LaunchList& ll, const JobDesc* descs, h
 
 template <typename T, typename P>
 hipError_t launch_op_conv(const void* x, void* y, int H, int W, const void* taps, int R, hipStream_t s) {
-  const int blocks = ((H + P::TH - 1) / P::TH) * ((W + P::TW - 1) / P::TW);
+  const int tiles = ((H + P::TH - 1) / P::TH) * ((W + P::TW - 1) / P::TW);
+  const int blocks = P::kStream ? (tiles + kStripsPerBlock - 1) / kStripsPerBlock : tiles;
   hipLaunchKernelGGL((k_op_conv<T, P>), dim3(blocks), dim3(P::NT), 0, s, (const T*)x, (T*)y, H, W, (const T*)taps,
                      R);
   return hipGetLastError();

@@ -75,9 +75,8 @@ struct JobDesc {
   int32_t zero_u;         // bit l: level l's smoother starts from zero (no transfer into it)
   int32_t lazy_u;         // CGLS pass B updates u every second iteration (see k_cg_b)
   int32_t fold_a;         // CGLS pass B may compute alpha itself (when its launch says so)
-  // CGLS pass B recomputes q = H p itself (pass A does not store q) on its
-  // own strips of strip_th2 x strip_tw2 outputs
-  int32_t dconv, tiles_x_b, ntiles_b, pad3;
+  int32_t nstrips;       // streaming policies: strips of the level (ntiles counts blocks)
+  int32_t pad2, pad3, pad4;
   double cdelta, eps2;
   SolverState* st;
   LevelRecord* rec;  // kMaxLevels records of this job
@@ -163,7 +162,7 @@ enum Stage : int32_t {
   kXfFusedSmall,    // the same with short tiles, for small levels
   kCoarse,          // the leading small levels of each job in one block per job
   kFlushU,          // apply a deferred CGLS solution update when a lazy_u level stops
-  kCgBD,            // CGLS pass B that recomputes q = H p (levels with dconv)
+  kReserved22,      // (unused id, kept so the stage numbers stay stable)
   kNumStages
 };
 
@@ -201,18 +200,16 @@ constexpr int kTHTall = 2 * kTH;
 // chip too few strips of the usual height (mid-size levels, which the
 // Infinity Cache holds, so the extra halo rows cost little).
 constexpr int kTHShortStrip = kTH / 2;
+// Streaming strips per block (one per wave): the blocks of a pass, and so the
+// partial sums of its inner products, are a quarter of its strips, which keeps
+// the finalize that every block of the next pass may evaluate cheap.
+constexpr int kStripsPerBlock = 4;
 // Strip mode: 0 usual height, 1 tall, 2 short.
 __host__ __device__ constexpr int strip_th(int R, int mode = 0) {
   return strip_group(R) *
              (((mode == 1 ? kTHTall : mode == 2 ? kTHShortStrip : kTH) + 2 * R + strip_group(R) - 1) / strip_group(R)) -
          2 * R;
 }
-// Strips of the double-convolution pass B: TH2 output rows of kTW - 2R
-// columns, walked in TH2 + 4R + 1 steps (whole row groups).
-__host__ __device__ constexpr int strip_th2(int R) {
-  return strip_group(R) * ((kTH + 4 * R + 1 + strip_group(R) - 1) / strip_group(R)) - 4 * R - 1;
-}
-__host__ __device__ constexpr int strip_tw2(int R) { return kTW - 2 * R; }
 // A variant id is kind * 100 + R, plus kTallVariant (kShortVariant) for a
 // streaming kind on tall (short) strips.
 constexpr int kTallVariant = 10000;

@@ -26,7 +26,7 @@ __global__ __launch_bounds__(256) void k_fin_cg_a(LaunchList ll, const JobDesc* 
 __global__ __launch_bounds__(256) void k_fin_cg_b(LaunchList ll, const JobDesc* __restrict__ descs) {
   const JobDesc& d = descs[ll.job[blockIdx.x]];
   // pass B's partials come from its own strips when it recomputes q
-  finalize_block(d, kCompCgB, true, d.dconv ? d.ntiles_b : d.ntiles,
+  finalize_block(d, kCompCgB, true, d.ntiles,
                  [](const JobDesc& dd, const double(&v)[2]) { fin_cg_b(dd, dd.st, v); });
 }
 
@@ -1385,7 +1385,6 @@ int blocks_for_stage(Stage st, const JobDesc& d) {
     case kMrInit:
     case kMrPass: return d.ntiles;
     case kCgB: return d.ntiles;
-    case kCgBD: return d.ntiles_b;
     case kCgFinInit:
     case kCgFinA:
     case kCgFinB:

@@ -71,11 +71,10 @@ constexpr size_t kTapsSlotBytes = 32 << 10;  // pinned staging of one job's PSF 
 // ---------------------------------------------------------------------------
 struct LevelPlan {
   int h = 0, w = 0, pitch = 0, rad = 0, cap = 0, ntiles = 0, tiles_x = 0;
+  int nstrips = 0;  // smoother tiles (general) or strips (streaming); ntiles counts blocks
   int variant = 0;                    // blur-operator kernel family (ConvKind * 100 + R)
   bool lazy = false;                  // CGLS solution update every second iteration
   bool fold_a = false;                // CGLS pass B evaluates pass A's finalize itself
-  bool dconv = false;                 // CGLS pass B recomputes q = H p (pass A stores no q)
-  int tiles_x_b = 0, ntiles_b = 0;    // pass B's own strips when dconv
   std::vector<double> psf;            // (2 rad + 1)^2, FP64
   std::vector<double> taps, taps_t;   // the variant's tap layout for H and H^T
 };
@@ -113,26 +112,18 @@ static long lazy_min_pixels() {
   const char* e = std::getenv("EECMG_LAZY_MIN_PIXELS");
   return e ? std::atol(e) : kLazyPixels;
 }
-// CGLS levels with at most this many tiles let every block of pass B sum
-// pass A's partials itself, and every block of pass A the previous pass B's
-// (the same fixed order as the finalize kernel, so alpha and beta are
-// bit-identical), which saves two launches per iteration where launches
-// weigh most.  The one-wave streaming kernels read the partials with a
-// quarter of the threads, so their limit is lower.  EECMG_FOLD_MAX_TILES and
-// EECMG_FOLD_MAX_TILES_STREAM move the limits (0 turns folding off).
+// CGLS levels with at most this many blocks per pass let every block of
+// pass B sum pass A's partials itself, and every block of pass A the previous
+// pass B's (the same fixed order as the finalize kernel, so alpha and beta
+// are bit-identical), which saves two launches per iteration.  Each block
+// reads every partial of the pass before, so the cost grows with the square
+// of the block count; with four strips per streaming block even the 4096^2
+// level (1008 blocks) gains (restore -2.5% against no fold on the two largest
+// levels).  EECMG_FOLD_MAX_TILES and EECMG_FOLD_MAX_TILES_STREAM move the
+// limits (0 turns folding off).
 constexpr long kFoldMaxTiles = 4096;
-constexpr long kFoldMaxTilesStream = 512;
+constexpr long kFoldMaxTilesStream = 1L << 30;
 constexpr int kFoldMaxJobs = 1;
-// FP32 CGLS levels with the uniform-disk streaming kernel can let pass B
-// recompute q = H p from p instead of pass A storing q: 8 bytes per pixel and
-// iteration less, but two chained windows per strip make pass B slower by
-// about what pass A saves on this hardware, so it is off unless
-// EECMG_DCONV=1.  FP64, and the separable and symmetric kernels, always keep
-// the stored q (two of their windows would crowd the registers).
-static bool dconv_enabled() {
-  const char* e = std::getenv("EECMG_DCONV");
-  return e && e[0] == '1';
-}
 // Levels whose tall-strip tiles number at least this many (two waves per
 // SIMD of the 1024 on the chip) use tall strips; EECMG_TALL_MIN_TILES moves
 // the limit and EECMG_TALL_STRIPS=0 keeps every level on short strips.
@@ -421,18 +412,11 @@ static int build_plan(int H, int W, const double* psf, int r, int L, const int* 
     else if (!general && !P.f64 && strips(0) < short_max_tiles())
       lp.variant += kShortVariant;
     const int th = tile_h_for_variant(lp.variant);
-    lp.ntiles = lp.tiles_x * ((lp.h + th - 1) / th);
-    lp.dconv = l >= P.coarse && P.prm.smoother == EECMG_SMOOTHER_CGLS && !P.f64 && kind == kConvBoxDisk &&
-               variant_strip_mode(lp.variant) == 0 && dconv_enabled();
-    // (the recomputed-q pass B takes alpha from a finalize launch)
-    lp.fold_a = l >= P.coarse && P.prm.smoother == EECMG_SMOOTHER_CGLS && !lp.dconv &&
+    lp.nstrips = lp.tiles_x * ((lp.h + th - 1) / th);
+    // smoother blocks (= partial-sum slots): one tile, or kStripsPerBlock strips
+    lp.ntiles = general ? lp.nstrips : (lp.nstrips + kStripsPerBlock - 1) / kStripsPerBlock;
+    lp.fold_a = l >= P.coarse && P.prm.smoother == EECMG_SMOOTHER_CGLS &&
                 lp.ntiles <= (general ? fold_max_tiles() : fold_max_tiles_stream());
-    if (lp.dconv) {
-      const int R = variant_r(lp.variant);
-      lp.tiles_x_b = (lp.w + strip_tw2(R) - 1) / strip_tw2(R);
-      lp.ntiles_b = lp.tiles_x_b * ((lp.h + strip_th2(R) - 1) / strip_th2(R));
-      P.max_tiles = std::max(P.max_tiles, lp.ntiles_b);
-    }
     P.max_tiles = std::max(P.max_tiles, lp.ntiles);
     P.off_g[l] = take((size_t)lp.h * lp.pitch * P.esz);
     P.off_u[l] = take((size_t)lp.h * lp.pitch * P.esz);
@@ -1336,9 +1320,7 @@ class Engine {
     d.coarse_levels = l == 0 ? P.coarse : 0;
     d.lazy_u = lazy_level(j, l) ? 1 : 0;
     d.fold_a = lp.fold_a ? 1 : 0;
-    d.dconv = lp.dconv ? 1 : 0;
-    d.tiles_x_b = lp.tiles_x_b;
-    d.ntiles_b = lp.ntiles_b;
+    d.nstrips = lp.nstrips;
     for (int k = 0; k < P.L; ++k)
       if (!needs_transfer(j, k)) d.zero_u |= 1 << k;
     d.cdelta = P.prm.c * P.prm.delta;
@@ -1578,8 +1560,7 @@ class Engine {
         const bool f64 = kv.first.second >= 100000;
         const int rc = kv.first.second % 100000;
         Group& g = kv.second;
-        const Stage sb = g.js.front()->plan.lv[g.js.front()->cur_level()].dconv ? kCgBD : kCgB;
-        launch_group(sb, g.js, -1, f64, rc, -1, -1, &g.ks, nullptr, g.fold ? kLaunchFoldA : 0);
+        launch_group(kCgB, g.js, -1, f64, rc, -1, -1, &g.ks, nullptr, g.fold ? kLaunchFoldA : 0);
         if (g.fold)
           for (Job* j : g.js) j->owed = Job::kOwesB;  // the next pass A, or the level end, runs it
         else

@@ -273,9 +273,9 @@ def test_lazy_solution_update_is_bitwise_identical(torch_cuda, monkeypatch, prec
 @pytest.mark.parametrize("lazy", [False, True])
 def test_folded_finalize_is_bitwise_identical(torch_cuda, monkeypatch, prec, lazy):
     """On small levels pass B evaluates pass A's finalize in every block, and
-    pass A the previous pass B's (same partials, same summation order: the
-    one-wave streaming kernels play the finalize kernel's 256 threads)
-    instead of separate launches.  With the fold on or off the cascade (a
+    pass A the previous pass B's (same partials, same summation order: every
+    smoother block has the finalize kernel's 256 threads) instead of separate
+    launches.  With the fold on or off the cascade (a
     separable streaming finest level over general levels), its statistics and
     the one-level smoother with a general, a uniform-disk and a symmetric
     streaming PSF agree bit for bit, also combined with the
@@ -302,35 +302,6 @@ def test_folded_finalize_is_bitwise_identical(torch_cuda, monkeypatch, prec, laz
     for (xa, ya), (xb, yb) in zip(res["fold"][2], res["separate"][2]):
         np.testing.assert_array_equal(xa, xb)
         assert ya == yb
-
-
-@pytest.mark.parametrize("H,W,caps", [(300, 263, None), (517, 389, [2, 3, 5, 7]), (130, 709, [3, 4, 6, 9])])
-def test_recomputed_q_pass_matches_stored_q(torch_cuda, monkeypatch, H, W, caps):
-    """FP32 levels with the uniform-disk kernel can run the pass B that
-    recomputes q = H p on its own (64 - 2R)-wide strips instead of reading the
-    q that pass A stored (EECMG_DCONV=1).  Both schedules agree to FP32
-    rounding (q is summed in another row order where pass A walks a strip
-    bottom-up), with identical iteration counts; sizes leave ragged strips on
-    both axes."""
-    t = torch_cuda
-    p = synth.workload(3, H=H, W=W, n_levels=4, n_shapes=30, n_textures=3)
-    g = t.from_numpy(p.g_delta.astype(np.float32)).to("cuda:0")
-    kw = dict(precision="f32", delta=p.delta)
-    if caps is not None:
-        kw["stop_rule"] = False
-    res = {}
-    for mode, env in (("dconv", "1"), ("stored", "0")):
-        monkeypatch.setenv("EECMG_DCONV", env)
-        u, st = eecmg.restore_dev(g, p.psf, 4, caps=caps, **kw)
-        u0 = t.zeros_like(g)
-        _, su = eecmg.smoother_dev(g, u0, p.psf, 6, precision="f32", delta=p.delta, stop_rule=False)
-        t.cuda.synchronize()
-        res[mode] = (u.cpu().numpy().astype(np.float64), st, u0.cpu().numpy().astype(np.float64), su)
-    a, b = res["dconv"], res["stored"]
-    assert a[1]["iters"] == b[1]["iters"] and a[1]["reason"] == b[1]["reason"]
-    assert _rel(a[0], b[0]) <= 1e-5
-    assert a[3]["iters"] == b[3]["iters"]
-    assert _rel(a[2], b[2]) <= 1e-5
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
