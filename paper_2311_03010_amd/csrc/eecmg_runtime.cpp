@@ -123,7 +123,12 @@ static long lazy_min_pixels() {
 // limits (0 turns folding off).
 constexpr long kFoldMaxTiles = 4096;
 constexpr long kFoldMaxTilesStream = 1L << 30;
+// Launches of at most this many jobs fold (EECMG_FOLD_MAX_JOBS moves it).
 constexpr int kFoldMaxJobs = 1;
+static int fold_max_jobs() {
+  const char* e = std::getenv("EECMG_FOLD_MAX_JOBS");
+  return e ? std::max(0, std::atoi(e)) : kFoldMaxJobs;
+}
 // Levels whose tall-strip tiles number at least this many (two waves per
 // SIMD of the 1024 on the chip) use tall strips; EECMG_TALL_MIN_TILES moves
 // the limit and EECMG_TALL_STRIPS=0 keeps every level on short strips.
@@ -1146,6 +1151,7 @@ class Engine {
     stall_ms_ = e ? std::max(0.0, std::atof(e)) : kStallMs;
     e = std::getenv("EECMG_TEST_FAIL_STEP");
     fail_step_ = e ? std::atol(e) : 0;
+    fold_max_jobs_ = fold_max_jobs();
     e = std::getenv("EECMG_PACE_STEPS");
     pace_ = e ? std::min(kStepEvents - 1, std::max(0, std::atoi(e))) : kPaceSteps;
     steps_ = 0;
@@ -1525,7 +1531,7 @@ class Engine {
       std::vector<Job*> owe_init, owe_b;
       for (auto& kv : groups) {
         Group& g = kv.second;
-        g.fold = kv.first.first == EECMG_SMOOTHER_CGLS && (int)g.js.size() <= kFoldMaxJobs;
+        g.fold = kv.first.first == EECMG_SMOOTHER_CGLS && (int)g.js.size() <= fold_max_jobs_;
         for (Job* j : g.js) g.fold = g.fold && j->plan.lv[j->cur_level()].fold_a;
         if (g.fold) continue;
         for (Job* j : g.js) {
@@ -1619,6 +1625,7 @@ class Engine {
   int step_cur_ = 0;
   bool step_pending_ = false;
   int n_out_ = 0;                        // queued steps, see paced()
+  int fold_max_jobs_ = kFoldMaxJobs;
   int pace_ = kPaceSteps;
   int max_ahead_ = kMaxAhead;
   bool noalloc_ = false;                 // see init_noalloc
