@@ -43,7 +43,7 @@ CACHE = os.path.join(HERE, "tuning.json")
 # threshold -> (library default, candidates)
 KNOBS = {
     "EECMG_TALL_MIN_TILES": (2048, [1024, 2048, 4096, 1 << 30]),
-    "EECMG_SHORT_MAX_TILES": (2048, [0, 1024, 2048, 4096]),
+    "EECMG_SHORT_MAX_TILES": (1024, [0, 512, 1024, 2048]),
     "EECMG_FOLD_MAX_TILES": (4096, [0, 1024, 4096, 16384]),
     "EECMG_FOLD_MAX_TILES_STREAM": (1 << 30, [0, 512, 2048, 1 << 30]),
     "EECMG_LAZY_MIN_PIXELS": (1 << 20, [1 << 18, 1 << 20, 1 << 40]),

@@ -196,10 +196,10 @@ __host__ __device__ constexpr int strip_group(int R) {
 // Tall strips (at least 2 kTH rows) serve large FP32 levels: half the halo
 // rows per output and half the strips in flight per XCD.
 constexpr int kTHTall = 2 * kTH;
-// Short strips (at least kTH / 2 rows) serve streaming levels that give the
+// Short strips (at least kTH / 4 rows) serve streaming levels that give the
 // chip too few strips of the usual height (mid-size levels, which the
 // Infinity Cache holds, so the extra halo rows cost little).
-constexpr int kTHShortStrip = kTH / 2;
+constexpr int kTHShortStrip = kTH / 4;
 // Streaming strips per block (one per wave): the blocks of a pass, and so the
 // partial sums of its inner products, are a quarter of its strips, which keeps
 // the finalize that every block of the next pass may evaluate cheap.

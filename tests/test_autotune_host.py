@@ -20,7 +20,7 @@ def _restore_thresholds(monkeypatch):
 class _FakeWorkloads:
     # time of each workload as a function of the thresholds set in the
     # environment: separable, minimal at the chosen optimum
-    optimum = {"EECMG_TALL_MIN_TILES": 4096, "EECMG_SHORT_MAX_TILES": 1024, "EECMG_FOLD_MAX_TILES": 4096,
+    optimum = {"EECMG_TALL_MIN_TILES": 4096, "EECMG_SHORT_MAX_TILES": 512, "EECMG_FOLD_MAX_TILES": 4096,
                "EECMG_FOLD_MAX_TILES_STREAM": 512, "EECMG_LAZY_MIN_PIXELS": 1 << 20, "EECMG_MAX_AHEAD": 2,
                "EECMG_PACE_STEPS": 3, "EECMG_BATCH_LANES": 2}
 
