@@ -198,13 +198,14 @@ __device__ __forceinline__ void linear_point(const XArgs& x, int I, int J) {
 
 // Arithmetic of S and D in a compute type C: FP64 with IEEE division and
 // exp(), or FP32 (the FP32 storage mode) with the hardware reciprocal,
-// reciprocal square root and base-2 exponential.
+// square root, reciprocal square root and base-2 exponential.
 template <typename C>
 struct Ar;
 template <>
 struct Ar<double> {
   __device__ static double div(double a, double b) { return a / b; }
   __device__ static double rsqrt(double x) { return 1.0 / sqrt(x); }
+  __device__ static double sqrt_(double x) { return sqrt(x); }
   // eigenvalues below this fraction of the largest are rounding noise
   static constexpr double kEig = 1e-12;
 };
@@ -212,6 +213,7 @@ template <>
 struct Ar<float> {
   __device__ static float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
   __device__ static float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+  __device__ static float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
   static constexpr float kEig = 1e-5f;
 };
 
@@ -288,7 +290,7 @@ __device__ __forceinline__ C smooth_solve(const C (&nb)[9], const C (&w)[9]) {
     C cs = C(1), sn = C(0), l1 = S11, l2 = S22;
     if (S12 != C(0)) {
       const C tau = Ar<C>::div(S22 - S11, C(2) * S12);
-      const C t = Ar<C>::div(tau >= C(0) ? C(1) : C(-1), fabs(tau) + sqrt(C(1) + tau * tau));
+      const C t = Ar<C>::div(tau >= C(0) ? C(1) : C(-1), fabs(tau) + Ar<C>::sqrt_(C(1) + tau * tau));
       cs = Ar<C>::rsqrt(C(1) + t * t);
       sn = t * cs;
       l1 = S11 - t * S12;
@@ -348,13 +350,35 @@ __device__ __forceinline__ void smooth_point(const XArgs& x, int i, int j) {
 // One explicit Perona-Malik step (Section 4, eq. 21, 23-25):
 // out = u + tau sum_{in-image nb} (c_nb + c)/2 (u_nb - u), c = 1/(1+|grad u|^2/k^2)
 // with |grad u| from central differences on a replicated border.
+// The diffusivity from the values below (un), above (us), right (ue) and
+// left (uw) of a pixel, each already replaced by the pixel's own value where
+// that neighbour lies outside the image.
+template <typename C>
+__device__ __forceinline__ C pm_c_of(C un, C us, C ue, C uw, C ik2) {
+  const C ux = C(0.5) * (un - us);
+  const C uy = C(0.5) * (ue - uw);
+  return Ar<C>::div(C(1), fma(fma(ux, ux, uy * uy), ik2, C(1)));
+}
+
 template <typename C, typename F>
 __device__ __forceinline__ C pm_c(int i, int j, int H, int W, C ik2, F U) {
   const int ip = i + 1 < H ? i + 1 : H - 1, im = i > 0 ? i - 1 : 0;
   const int jp = j + 1 < W ? j + 1 : W - 1, jm = j > 0 ? j - 1 : 0;
-  const C ux = C(0.5) * (U(ip, j) - U(im, j));
-  const C uy = C(0.5) * (U(i, jp) - U(i, jm));
-  return Ar<C>::div(C(1), fma(fma(ux, ux, uy * uy), ik2, C(1)));
+  return pm_c_of<C>(U(ip, j), U(im, j), U(i, jp), U(i, jm), ik2);
+}
+
+// The step at a pixel (value uc, diffusivity cc) from its four neighbours'
+// values and diffusivities; hn/hs/he/hw tell which neighbours lie inside the
+// image (the others, whatever their values, contribute nothing).
+template <typename C>
+__device__ __forceinline__ C pm_step_of(C uc, C cc, C cn, C cs, C ce, C cw, C un, C us, C ue, C uw, bool hn,
+                                        bool hs, bool he, bool hw, C tau) {
+  C acc = C(0);
+  acc = hn ? fma(C(0.5) * (cn + cc), un - uc, acc) : acc;
+  acc = hs ? fma(C(0.5) * (cs + cc), us - uc, acc) : acc;
+  acc = he ? fma(C(0.5) * (ce + cc), ue - uc, acc) : acc;
+  acc = hw ? fma(C(0.5) * (cw + cc), uw - uc, acc) : acc;
+  return fma(tau, acc, uc);
 }
 
 // C(i, j) supplies the diffusivity (pm_c) at in-image pixels.
@@ -367,12 +391,7 @@ __device__ __forceinline__ C pm_value(int i, int j, int H, int W, C tau, F U, G 
   const int ip = min(i + 1, H - 1), im = max(i - 1, 0), jp = min(j + 1, W - 1), jm = max(j - 1, 0);
   const C cn = Cf(ip, j), cs = Cf(im, j), ce = Cf(i, jp), cw = Cf(i, jm);
   const C un = U(ip, j), us = U(im, j), ue = U(i, jp), uw = U(i, jm);
-  C acc = C(0);
-  acc = (i + 1 < H) ? fma(C(0.5) * (cn + cc), un - uc, acc) : acc;
-  acc = (i > 0) ? fma(C(0.5) * (cs + cc), us - uc, acc) : acc;
-  acc = (j + 1 < W) ? fma(C(0.5) * (ce + cc), ue - uc, acc) : acc;
-  acc = (j > 0) ? fma(C(0.5) * (cw + cc), uw - uc, acc) : acc;
-  return fma(tau, acc, uc);
+  return pm_step_of<C>(uc, cc, cn, cs, ce, cw, un, us, ue, uw, i + 1 < H, i > 0, j + 1 < W, j > 0, tau);
 }
 
 template <typename T>
@@ -646,7 +665,9 @@ __device__ __forceinline__ void fused_tile(const FArgs& a, int t) {
 // weight is evaluated once: a pixel computes its east, south, south-east and
 // south-west edges, takes its west and north-west ones from the lane to its
 // left, its north-east one from the lane to its right (cross-lane shuffles)
-// and its north ones from the previous row.  The weights, the fit and D are
+// and its north ones from the previous row.  D walks the output rows the same
+// way, its diffusivities computed once per pixel and shared with the
+// neighbours through registers and shuffles.  The weights, the fit and D are
 // the same expressions in the same order as the separate stage kernels, so
 // the output is bit for bit theirs.
 template <bool QUAD, bool DO_D, int TY>
@@ -658,8 +679,7 @@ struct SGeo {
   static constexpr int LW = kTW + 2;       // LDS row: columns -1 .. 64
   static constexpr int BH = PH / 2 + 5, BW = kTW / 2 + 5;  // coarse panel bound
   static constexpr int NQ = QUAD ? BH * BW + PH * BW : 0;  // doubles
-  static constexpr int NC = DO_D ? (PH * LW + 1) / 2 : 0;  // diffusivities (floats, in doubles)
-  static constexpr int XN = (NQ > NC ? NQ : NC) > 0 ? (NQ > NC ? NQ : NC) : 1;
+  static constexpr int XN = NQ > 0 ? NQ : 1;
 };
 
 __host__ __device__ constexpr int sgeo_ow(bool do_d) { return kTW - 2 * ((do_d ? 2 : 0) + 1); }
@@ -668,7 +688,7 @@ template <bool QUAD, bool DO_D, int TY>
 __device__ __forceinline__ void fused_tile_f32(const FArgs& a, int t) {
   using G = SGeo<QUAD, DO_D, TY>;
   constexpr int LW = G::LW;
-  __shared__ double xs[G::XN];  // coarse panels (P), then diffusivities (D)
+  __shared__ double xs[G::XN];  // coarse panels (P)
   __shared__ float pt[G::PH * LW];
   __shared__ float stl[DO_D ? G::PH * LW : 1];
   const int h = a.h, w = a.w;
@@ -726,12 +746,13 @@ __device__ __forceinline__ void fused_tile_f32(const FArgs& a, int t) {
   // S on tile rows 1 .. PH - 2, a contiguous quarter of them per wave
   {
     const SWeight<float> W(a.smooth_h);
-    constexpr int NSR = G::PH - 2, CH = (NSR + 3) / 4;
-    const int rs0 = 1 + wave * CH, rs1 = min(rs0 + CH, G::PH - 1);
+    constexpr int NSR = G::PH - 2, CH = NSR / 4;
+    static_assert(NSR % 4 == 0, "every wave smooths the same number of rows");
+    const int rs0 = 1 + wave * CH;
     const bool c0 = J - 1 >= 0 && J - 1 < w, c1 = J >= 0 && J < w, c2 = J + 1 >= 0 && J + 1 < w;
     auto rin = [&](int r) { const int I = pi0 + r; return I >= 0 && I < h; };
     float* out = (float*)a.dst;
-    if (rs0 < rs1) {
+    {
       const float* pr = pt + (rs0 - 1) * LW + lane;  // pr[0..2]: columns lane - 1 .. lane + 1
       float z0 = pr[0], z1 = pr[1], z2 = pr[2];
       float y0 = pr[LW], y1 = pr[LW + 1], y2 = pr[LW + 2];
@@ -740,7 +761,9 @@ __device__ __forceinline__ void fused_tile_f32(const FArgs& a, int t) {
       float pS = W(y1 - z1, rz && ry && c1);
       float pSE = W(y2 - z1, rz && ry && c1 && c2);
       float pSW = W(y0 - z1, rz && ry && c1 && c0);
-      for (int r = rs0; r < rs1; ++r) {
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        const int r = rs0 + k;
         const float* xr = pt + (r + 1) * LW + lane;
         const float x0 = xr[0], x1 = xr[1], x2 = xr[2];
         const bool rx = rin(r + 1);
@@ -768,22 +791,46 @@ __device__ __forceinline__ void fused_tile_f32(const FArgs& a, int t) {
     }
   }
   if constexpr (DO_D) {
+    // D on the output rows, a contiguous quarter of them per wave, walking
+    // down its columns with three rows of smoothed values and of
+    // diffusivities in registers (left and right neighbours from the adjacent
+    // lanes); out-of-image neighbours are replaced or dropped exactly as the
+    // separate step kernel's clamped reads do, so the output is bit for bit its.
     __syncthreads();
     const float ik2 = (float)(1.0 / (a.pm_k * a.pm_k));
-    auto Us = [&](int ii, int jj) { return stl[(ii - pi0) * LW + (jj - pj0) + 1]; };
-    float* ct = reinterpret_cast<float*>(xs);  // the P panels are no longer needed
-    const bool cl = lane >= G::HP - 1 && lane < kTW - G::HP + 1 && J >= 0 && J < w;
-    for (int r = G::HP - 1 + wave; r < G::HP + TY + 1; r += 4) {
-      const int I = pi0 + r;
-      if (cl && I >= 0 && I < h) ct[r * LW + lane + 1] = pm_c<float>(I, J, h, w, ik2, Us);
-    }
-    __syncthreads();
-    auto Cc = [&](int ii, int jj) { return ct[(ii - pi0) * LW + (jj - pj0) + 1]; };
-    float* out = (float*)a.dst;
+    const float tau = (float)a.tau;
+    constexpr int DCH = TY / 4;  // output rows per wave
+    static_assert(TY % 4 == 0, "every wave steps the same number of rows");
+    const int r0 = G::HP + wave * DCH;
+    const bool he = J + 1 < w, hw = J > 0;
     const bool ol = lane >= G::HP && lane < kTW - G::HP && J < w;
-    for (int r = G::HP + wave; r < G::HP + TY; r += 4) {
+    float* out = (float*)a.dst;
+    auto urow = [&](int r) { return stl[r * LW + lane + 1]; };
+    // diffusivity of tile row r from its values (u, ue, uw) and the rows above (um) and below (up)
+    auto cof = [&](int r, float um, float u, float up, float ue, float uw) {
       const int I = pi0 + r;
-      if (ol && I < h) out[(size_t)I * a.pitch + J] = pm_value<float>(I, J, h, w, (float)a.tau, Us, Cc);
+      return pm_c_of<float>(I + 1 < h ? up : u, I > 0 ? um : u, he ? ue : u, hw ? uw : u, ik2);
+    };
+    float u0 = urow(r0 - 1), u1 = urow(r0), u2 = urow(r0 + 1);
+    float c0, c1;
+    {
+      const float um = urow(r0 - 2);
+      c0 = cof(r0 - 1, um, u0, u1, __shfl_down(u0, 1, 64), __shfl_up(u0, 1, 64));
+    }
+    float ue1 = __shfl_down(u1, 1, 64), uw1 = __shfl_up(u1, 1, 64);
+    c1 = cof(r0, u0, u1, u2, ue1, uw1);
+#pragma unroll
+    for (int k = 0; k < DCH; ++k) {
+      const int r = r0 + k, I = pi0 + r;
+      const float u3 = urow(r + 2);
+      const float ue2 = __shfl_down(u2, 1, 64), uw2 = __shfl_up(u2, 1, 64);
+      const float c2 = cof(r + 1, u1, u2, u3, ue2, uw2);
+      const float ce = __shfl_down(c1, 1, 64), cw = __shfl_up(c1, 1, 64);
+      const float v = pm_step_of<float>(u1, c1, c2, c0, ce, cw, u2, u0, ue1, uw1, I + 1 < h, I > 0, he, hw, tau);
+      if (ol && I < h) out[(size_t)I * a.pitch + J] = v;
+      u0 = u1; u1 = u2; u2 = u3;
+      ue1 = ue2; uw1 = uw2;
+      c0 = c1; c1 = c2;
     }
   }
 }
