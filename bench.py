@@ -236,27 +236,35 @@ def cascade_roofline(eecmg, restore_once, p, stats, steps, ms_step, copy_gbs):
     eecmg.profile_enable(False)
     rows = []
     kern_ms = 0.0
+    other = {}
+    for st in ("restrict", "out_copy"):
+        n, ms, _ = eecmg.profile_read(st)
+        other[st] = (n, ms / steps)
+        kern_ms += ms / steps
     for l in range(len(sizes)):
         if 0 < l < coarse:
             continue
-        n, ms = eecmg.profile_read_level(l)
-        ms /= steps
-        kern_ms += ms
         lv = list(range(coarse)) if (l == 0 and coarse > 0) else [l]
-        b = sum(lb[i] for i in lv)
+        if l == 0 and coarse > 0:
+            # the coarse levels are solved inside the restriction launch
+            n, ms = other["restrict"]
+            b = sum(lb[i] for i in lv) + rb
+            name = "restriction + "
+        else:
+            n, ms = eecmg.profile_read_level(l)
+            ms /= steps
+            kern_ms += ms
+            b = sum(lb[i] for i in lv)
+            name = ""
         ws = 6 * sizes[l][0] * sizes[l][1] * esz
-        rows.append({"levels": f"{sizes[lv[0]][0]}x{sizes[lv[0]][1]}" + (f"..{sizes[lv[-1]][0]}x{sizes[lv[-1]][1]}"
-                                                                          if len(lv) > 1 else ""),
+        rows.append({"levels": name + f"{sizes[lv[0]][0]}x{sizes[lv[0]][1]}" +
+                     (f"..{sizes[lv[-1]][0]}x{sizes[lv[-1]][1]}" if len(lv) > 1 else ""),
                      "iters": [stats["iters"][i] for i in lv], "launches_per_step": round(n / steps, 1),
                      "alg_mb": round(b / 1e6, 3), "us": round(ms * 1e3, 1),
                      "achieved_gbs": round(b / (ms * 1e-3) / 1e9, 1) if ms > 0 else None,
                      "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ms > 0 else None,
                      "fits_mall": ws <= (256 << 20)})
-    other = {}
-    for st in ("restrict", "out_copy"):
-        n, ms, _ = eecmg.profile_read(st)
-        other[st] = round(ms / steps * 1e3, 1)
-        kern_ms += ms / steps
+    other = {k: round(v[1] * 1e3, 1) for k, v in other.items()}
     total_b = sum(lb) + rb
     ach = total_b / (ms_step * 1e-3) / 1e9
     return {"alg_bytes_per_step": int(total_b), "ms_per_step": round(ms_step, 4), "achieved": round(ach, 1),
@@ -264,6 +272,8 @@ def cascade_roofline(eecmg, restore_once, p, stats, steps, ms_step, copy_gbs):
             "frac_vs_copy": round(ach / copy_gbs, 4) if copy_gbs else None,
             "kernel_ms_per_step": round(kern_ms, 4), "gap_ms_per_step": round(ms_step - kern_ms, 4),
             "restrict_us": other["restrict"], "out_copy_us": other["out_copy"], "per_level": rows,
+            "restrict_note": "the restriction launch also solves the coarse levels (first per-level row)"
+            if coarse > 0 else None,
             "bytes": "CGLS 32 B/px per iteration + 20 at its start; transfer 7.25 per fine px (Pi 2.25, "
                      "prolongation+S+D 5); restriction 2 per fine px + the coarser right-hand sides (FP32)"}
 

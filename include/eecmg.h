@@ -278,18 +278,18 @@ int eecmg_op_pm_step_dev(const void* u_dev, void* out_dev, int H, int W, double 
  * events and returns, for one stage id, the number of launches, their summed
  * duration, and the pixels they covered (sum over the jobs of the level's
  * H x W); smoother passes that found their level already stopped are left
- * out.  Stage ids: 0 restriction, 1 CGLS init r, 2 CGLS init s, 3 CGLS init
- * finalize, 4 CGLS pass A (q = H p), 5 its finalize, 6 CGLS pass B
+ * out.  Stage ids: 0 restriction (with the coarse levels, solved in one
+ * block per image, in the same launch), 1 CGLS init r, 2 CGLS init s, 3 CGLS
+ * init finalize, 4 CGLS pass A (q = H p), 5 its finalize, 6 CGLS pass B
  * (s = H^T r), 7 its finalize, 8 MR init, 9 its finalize, 10 MR pass, 11 its
  * finalize, 12 extrapolation, 13 quadratic interpolation, 14 linear
  * prolongation, 15 smoothing S, 16 denoising D, 17 output copy, 18 fused
- * prolongation + S (+ first D step), 19 the same on short tiles, 20 coarse
- * levels in one block per image, 21 deferred solution update (22 is
- * unused).  eecmg_profile_read_level returns, for the launches whose
- * jobs all worked on level index `level` (0 = coarsest; the coarse-level
- * kernel counts as level 0), the number of launches of one stage (-1: every
- * stage) and their summed duration, including the passes that found their
- * level stopped (they take time too).
+ * prolongation + S (+ first D step), 19 the same on short tiles, 21 deferred
+ * solution update (20 and 22 are unused).  eecmg_profile_read_level returns,
+ * for the launches whose jobs all worked on level index `level` (0 =
+ * coarsest; the restriction launch counts as level -1), the number of
+ * launches of one stage (-1: every stage) and their summed duration,
+ * including the passes that found their level stopped (they take time too).
  * Process-wide; not meant for concurrent contexts.
  * ------------------------------------------------------------------------- */
 int eecmg_profile_enable(int enable, int min_blocks);

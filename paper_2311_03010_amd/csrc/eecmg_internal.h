@@ -140,7 +140,7 @@ static_assert(sizeof(LaunchList) + 64 <= 4096, "kernel arguments stay below 4 Ki
 
 // Stages launched by the runtime.
 enum Stage : int32_t {
-  kRestrict = 0,    // dense g -> level pyramid; zero u pyramid (or copy u_in)
+  kRestrict = 0,    // dense g -> level pyramid; zero u pyramid (or copy u_in); coarse levels solved
   kCgInit1,         // r = g - H u0
   kCgInit2,         // s = H^T r, p = s
   kCgFinInit,
@@ -160,7 +160,7 @@ enum Stage : int32_t {
   kOutCopy,         // u (finest, pitched) -> dense u_out
   kXfFused,         // prolongation -> S (-> one D step), fused; variant bit 0 quadratic, bit 1 with D
   kXfFusedSmall,    // the same with short tiles, for small levels
-  kCoarse,          // the leading small levels of each job in one block per job
+  kReserved20,      // (unused id: the coarse levels are solved inside the restriction launch)
   kFlushU,          // apply a deferred CGLS solution update when a lazy_u level stops
   kReserved22,      // (unused id, kept so the stage numbers stay stable)
   kNumStages

@@ -542,6 +542,8 @@ __global__ __launch_bounds__(256) void k_xfer_op(XArgs x) {
 // quadratic P is evaluated separably (along i into an FP64 LDS panel, then
 // along j), which is the evaluation order quad_value defines.
 constexpr int kFX = 64, kFY = 32, kFYSmall = 8;
+// rows per tile of the FP32 fused transfer on large levels
+constexpr int kFY32 = 32;
 
 struct FArgs {
   const void* src;  // level l-1 input of the prolongation (grid B)
@@ -679,7 +681,8 @@ struct SGeo {
   static constexpr int LW = kTW + 2;       // LDS row: columns -1 .. 64
   static constexpr int BH = PH / 2 + 5, BW = kTW / 2 + 5;  // coarse panel bound
   static constexpr int NQ = QUAD ? BH * BW + PH * BW : 0;  // doubles
-  static constexpr int XN = NQ > 0 ? NQ : 1;
+  static constexpr int NS = DO_D ? (PH * LW + 1) / 2 : 0;  // smoothed rows (floats, in doubles)
+  static constexpr int XN = (NQ > NS ? NQ : NS) > 0 ? (NQ > NS ? NQ : NS) : 1;
 };
 
 __host__ __device__ constexpr int sgeo_ow(bool do_d) { return kTW - 2 * ((do_d ? 2 : 0) + 1); }
@@ -688,9 +691,9 @@ template <bool QUAD, bool DO_D, int TY>
 __device__ __forceinline__ void fused_tile_f32(const FArgs& a, int t) {
   using G = SGeo<QUAD, DO_D, TY>;
   constexpr int LW = G::LW;
-  __shared__ double xs[G::XN];  // coarse panels (P)
+  __shared__ double xs[G::XN];  // coarse panels (P), then the smoothed rows (S -> D)
   __shared__ float pt[G::PH * LW];
-  __shared__ float stl[DO_D ? G::PH * LW : 1];
+  float* const stl = reinterpret_cast<float*>(xs);  // the panels are dead once P is done
   const int h = a.h, w = a.w;
   const int tiles_x = (w + G::OW - 1) / G::OW;
   const int ty = t / tiles_x, tx = t - ty * tiles_x;
@@ -1224,49 +1227,88 @@ __device__ void coarse_mr(const JobDesc& d) {
   }
 }
 
-// descs[ll.job[e]] is level 0 of job e; its coarse_levels leading levels are
-// solved here, level by level.
-template <typename T>
-__global__ __launch_bounds__(kCoarseThreads) void k_coarse(LaunchList ll, const JobDesc* __restrict__ descs) {
-  const int d0 = ll.job[blockIdx.x];
-  const int nl = descs[d0].coarse_levels;
-  for (int l = 0; l < nl; ++l) {
-    const JobDesc& d = descs[d0 + l];
-    coarse_transfer<T>(d);
-    if (d.smoother == kSmootherMr)
-      coarse_mr<T>(d);
-    else
-      coarse_cgls<T>(d);
-    __syncthreads();
-  }
-}
 
 // ---------------------------------------------------------------------------
-// Restriction (eq. 12-13) and output copy
+// Restriction (eq. 12-13), with the coarse levels solved in the same launch
 // ---------------------------------------------------------------------------
-// One pass over the dense finest-level input writes every level's
-// right-hand side g_l(i, j) = g(2^(L-l) i, 2^(L-l) j) and sets the starting
-// solution of every level that receives no transfer (zero, or the given
-// initial guess on the finest level); the other levels are written whole by
-// their transfer before their smoother reads them.
+// Every level's right-hand side g_l(i, j) = g(2^(L-l) i, 2^(L-l) j) and the
+// starting solution of every level that receives no transfer (zero, or the
+// given initial guess on the finest level); the other levels are written whole
+// by their transfer before their smoother reads them.  One launch does this
+// for a group of jobs, in blocks of kCoarseThreads threads: the head block of
+// a job with coarse levels restricts those levels itself (a few thousand
+// pixels) and then solves them (the coarse cascade above), while tiles
+// restrict the remaining levels in one pass over the dense input, so that
+// pass runs beside the one-block cascade instead of before it.
 // Rows of the dense input the restriction visits: every row when the finest
 // level gets a pitched copy or a starting value, else only the even rows,
 // which are all that feed the coarser levels.
+constexpr int kRH = 4;  // visited rows per wave of a restriction tile
 __host__ __device__ inline int restrict_row_step(const JobDesc& d) {
   const bool copy_fine = d.g_lv[d.L - 1] != d.g_in;
   const bool init_fine = (d.zero_u >> (d.L - 1)) & 1;
   return (copy_fine || init_fine) ? 1 : 2;
 }
 
+// Restriction tiles of a job (64 input columns x kRH * kCoarseWaves visited
+// rows each) for its levels C .. L - 1.  The launch has one head block per job
+// first (the coarse cascade, or nothing), then every job's tiles.
+__host__ __device__ inline int restrict_tiles(const JobDesc& d) {
+  const int C = d.coarse_levels, rs = restrict_row_step(d);
+  if (C >= d.L || (rs == 2 && d.L == 1)) return 0;
+  const int th = kRH * kCoarseWaves;
+  return ((d.H + rs - 1) / rs + th - 1) / th * ((d.W + kXW - 1) / kXW);
+}
+
+// The levels 0 .. C-1 of a job, by its head block (the finest level among
+// them only when every level is coarse), in one sweep over level C-1 that
+// also writes the coarser levels' pixels: kCoarseU pixels per thread at a
+// time, their loads first.  (Not inlined, like restrict_tile: the coarse
+// cascade after it already needs nearly every register a 1024-thread block
+// may have.)
 template <typename T>
-__global__ __launch_bounds__(256) void k_restrict(LaunchList ll, const JobDesc* __restrict__ descs) {
-  const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
-  const JobDesc& d = descs[L.d];
+__device__ __noinline__ void restrict_coarse(const JobDesc& d, int C) {
+  const int W = d.W, NL = d.L, top = C - 1, sh = NL - 1 - top, zero = d.zero_u;
+  const bool fine = top == NL - 1;
+  const bool copy = !fine || d.g_lv[top] != d.g_in;
+  const bool ztop = (zero >> top) & 1;
+  const T* gin = (const T*)d.g_in;
+  const T* uin = (const T*)d.u_in;
+  T* const gt = (T*)d.g_lv[top];
+  T* const ut = (T*)d.u_lv[top];
+  coarse_sweep(d.lh[top] * d.lw[top], d.lw[top], fine ? d.fine_pitch : d.lp[top], [&](const Px (&px)[kCoarseU]) {
+    T gv[kCoarseU], uv[kCoarseU];
+#pragma unroll
+    for (int m = 0; m < kCoarseU; ++m) {
+      const size_t fo = (size_t)(px[m].i << sh) * W + (px[m].j << sh);
+      gv[m] = gin[fo];
+      uv[m] = (ztop && fine && uin) ? uin[fo] : T(0);
+    }
+#pragma unroll
+    for (int m = 0; m < kCoarseU; ++m) {
+      if (!px[m].ok) continue;
+      if (copy) gt[px[m].o] = gv[m];
+      if (ztop) ut[px[m].o] = uv[m];
+      for (int l = top - 1; l >= 0; --l) {
+        const int s = top - l, msk = (1 << s) - 1;
+        if ((px[m].i & msk) || (px[m].j & msk)) break;
+        const size_t o = (size_t)(px[m].i >> s) * d.lp[l] + (px[m].j >> s);
+        ((T*)d.g_lv[l])[o] = gv[m];
+        if ((zero >> l) & 1) ((T*)d.u_lv[l])[o] = T(0);
+      }
+    }
+  });
+  __syncthreads();
+}
+
+// Restriction tile t of the levels C .. L-1: each lane one input column, each
+// wave kRH visited rows, all loaded before any store.
+template <typename T>
+__device__ __noinline__ void restrict_tile(const JobDesc& d, int t, int C) {
   const int H = d.H, W = d.W, NL = d.L;
   const int rs = restrict_row_step(d);
-  if (rs == 2 && NL == 1) return;
   const int tiles_x = (W + kXW - 1) / kXW;
-  const int ty = L.t / tiles_x, tx = L.t - ty * tiles_x;
+  const int ty = t / tiles_x, tx = t - ty * tiles_x;
   const int x = tx * kXW + (threadIdx.x & 63);
   if (x >= W) return;
   const T* gin = (const T*)d.g_in;
@@ -1276,16 +1318,16 @@ __global__ __launch_bounds__(256) void k_restrict(LaunchList ll, const JobDesc* 
   // have the level's pitch; otherwise it gets a pitched copy
   const bool copy_fine = d.g_lv[NL - 1] != d.g_in;
   const bool init_fine = (zero >> (NL - 1)) & 1;
-  // tile row r covers input row r * rs; the lane's rows are loaded first
-  T vals[kXH / 4];
-  int ys[kXH / 4];
+  // tile row r covers input row r * rs
+  T vals[kRH];
+  int ys[kRH];
 #pragma unroll
-  for (int k = 0; k < kXH / 4; ++k) {
-    const int y = (ty * kXH + (threadIdx.x >> 6) * (kXH / 4) + k) * rs;
+  for (int k = 0; k < kRH; ++k) {
+    const int y = (ty * (kRH * kCoarseWaves) + (threadIdx.x >> 6) * kRH + k) * rs;
     ys[k] = y;
     vals[k] = gin[(size_t)min(y, H - 1) * W + x];
   }
-  for (int k = 0; k < kXH / 4; ++k) {
+  for (int k = 0; k < kRH; ++k) {
     const int y = ys[k];
     if (y >= H) break;
     const size_t fo = (size_t)y * W + x;
@@ -1293,13 +1335,39 @@ __global__ __launch_bounds__(256) void k_restrict(LaunchList ll, const JobDesc* 
     const size_t of = (size_t)y * d.fine_pitch + x;
     if (copy_fine) ((T*)d.g_lv[NL - 1])[of] = v;
     if (init_fine) ((T*)d.u_lv[NL - 1])[of] = uin ? uin[fo] : T(0);
-    for (int l = NL - 2; l >= 0; --l) {
+    for (int l = NL - 2; l >= C; --l) {
       const int sh = NL - 1 - l, m = (1 << sh) - 1;
       if ((y & m) || (x & m)) break;
       const size_t o = (size_t)(y >> sh) * d.lp[l] + (x >> sh);
       ((T*)d.g_lv[l])[o] = v;
       if ((zero >> l) & 1) ((T*)d.u_lv[l])[o] = T(0);
     }
+  }
+}
+
+// descs[ll.job[e]] is level 0 of job e.  Blocks 0 .. ll.n - 1 are the jobs'
+// head blocks, so every coarse cascade starts at once; the tiles follow, as
+// ll.start counts them.
+template <typename T>
+__global__ __launch_bounds__(kCoarseThreads) void k_restrict(LaunchList ll, const JobDesc* __restrict__ descs) {
+  if ((int)blockIdx.x >= ll.n) {
+    const Loc L = locate(ll, blockIdx.x - ll.n);
+    const JobDesc& d = descs[L.d];
+    restrict_tile<T>(d, L.t, d.coarse_levels);
+    return;
+  }
+  const int d0 = ll.job[blockIdx.x];
+  const int C = descs[d0].coarse_levels;
+  if (C == 0) return;
+  restrict_coarse<T>(descs[d0], C);
+  for (int l = 0; l < C; ++l) {
+    const JobDesc& dl = descs[d0 + l];
+    coarse_transfer<T>(dl);
+    if (dl.smoother == kSmootherMr)
+      coarse_mr<T>(dl);
+    else
+      coarse_cgls<T>(dl);
+    __syncthreads();
   }
 }
 
@@ -1373,6 +1441,7 @@ hipError_t launch_upload(const UploadList& ul, const JobDesc* hdesc, JobDesc* dd
   return hipGetLastError();
 }
 
+// Output copy: the finest level's (pitched) solution into the dense output.
 template <typename T>
 __global__ __launch_bounds__(256) void k_out_copy(LaunchList ll, const JobDesc* __restrict__ descs) {
   const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
@@ -1424,7 +1493,7 @@ static int tiles2(int h, int w, int th, int tw) { return ((h + th - 1) / th) * (
 
 int blocks_for_stage(Stage st, const JobDesc& d) {
   switch (st) {
-    case kRestrict: return tiles2((d.H + restrict_row_step(d) - 1) / restrict_row_step(d), d.W, kXH, kXW);
+    case kRestrict: return restrict_tiles(d);
     case kOutCopy: return tiles2(d.H, d.W, kXH, kXW);
     case kCgInit1:
     case kCgInit2:
@@ -1438,10 +1507,9 @@ int blocks_for_stage(Stage st, const JobDesc& d) {
     case kMrFinInit:
     case kMrFin: return 1;
     case kXfExtrap: return tiles2((d.hB + 1) / 2, (d.wB + 1) / 2, kPiTH, kXW);  // 2 x 2 outputs per thread
-    case kXfFused: return tiles2(d.h, d.w, kFY, d.f64 ? kFX : sgeo_ow(d.pm_steps >= 1));
+    case kXfFused: return d.f64 ? tiles2(d.h, d.w, kFY, kFX) : tiles2(d.h, d.w, kFY32, sgeo_ow(d.pm_steps >= 1));
     case kXfFusedSmall: return tiles2(d.h, d.w, kFYSmall, d.f64 ? kFX : sgeo_ow(d.pm_steps >= 1));
     case kFlushU: return tiles2(d.h, d.w, kXH, kXW);
-    case kCoarse: return 1;
     default: return tiles2(d.h, d.w, kXH, kXW);
   }
 }
@@ -1482,7 +1550,9 @@ static hipError_t launch_typed(Stage st, int variant, const LaunchList& ll, cons
                                hipStream_t s) {
   const dim3 grid(ll.total), block(256);
   switch (st) {
-    case kRestrict: hipLaunchKernelGGL(k_restrict<T>, grid, block, 0, s, ll, descs); return hipGetLastError();
+    case kRestrict:  // the head blocks, then the tiles
+      hipLaunchKernelGGL(k_restrict<T>, dim3(ll.n + ll.total), dim3(kCoarseThreads), 0, s, ll, descs);
+      return hipGetLastError();
     case kOutCopy: hipLaunchKernelGGL(k_out_copy<T>, grid, block, 0, s, ll, descs); return hipGetLastError();
     case kFlushU: hipLaunchKernelGGL(k_flush_u<T>, grid, block, 0, s, ll, descs); return hipGetLastError();
     case kXfExtrap:
@@ -1503,10 +1573,7 @@ static hipError_t launch_typed(Stage st, int variant, const LaunchList& ll, cons
     case kXfPm:
       hipLaunchKernelGGL((k_xfer<T, kXfPm>), grid, block, 0, s, ll, descs, src, dst);
       return hipGetLastError();
-    case kCoarse:
-      hipLaunchKernelGGL(k_coarse<T>, dim3(ll.n), dim3(kCoarseThreads), 0, s, ll, descs);
-      return hipGetLastError();
-    case kXfFused: return launch_fused<T, kFY>(variant, grid, ll, descs, src, dst, s);
+    case kXfFused: return launch_fused<T, sizeof(T) == 8 ? kFY : kFY32>(variant, grid, ll, descs, src, dst, s);
     case kXfFusedSmall: return launch_fused<T, kFYSmall>(variant, grid, ll, descs, src, dst, s);
     default: break;
   }

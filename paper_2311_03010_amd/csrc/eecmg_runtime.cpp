@@ -856,7 +856,7 @@ class Engine {
       return false;
     }
     // action lists
-    std::vector<Job*> restrict_l, out_l, coarse_l;
+    std::vector<Job*> restrict_l, out_l;
     std::vector<std::pair<Job*, int>> xfer_l;  // job, level
     std::vector<Job*> init_l;
     std::vector<std::pair<Job*, int>> iter_l;  // job, chunk
@@ -876,9 +876,9 @@ class Engine {
             j->phase = Job::kStartLevel;
             j->oi = 0;
             if (j->plan.coarse > 0) {
-              // the leading small levels in one launch, stream-ordered
-              // before everything issued for the levels after them
-              coarse_l.push_back(j);
+              // the leading small levels are solved by the restriction
+              // launch, stream-ordered before everything issued for the
+              // levels after them
               j->oi = j->plan.coarse;
               if (j->oi >= (int)j->plan.order.size()) {
                 out_l.push_back(j);
@@ -975,17 +975,15 @@ class Engine {
           chk(hipStreamWaitEvent(stream_, j->in_ev, 0));
           j->in_wait = false;
         }
-      // level 0's descriptor: the restriction fields are the same on every
-      // level, and a job whose levels are all coarse has no current level
-      launch_group(kRestrict, restrict_l, 0, false, 0, -1, -1);
-      launched = true;
-    }
-    if (!coarse_l.empty()) {
+      // one launch per precision restricts every level and solves the
+      // leading coarse levels (level 0's descriptor: the restriction fields
+      // are the same on every level, and a job whose levels are all coarse
+      // has no current level)
       for (int f64 = 0; f64 < 2; ++f64) {
         std::vector<Job*> js;
-        for (Job* j : coarse_l)
+        for (Job* j : restrict_l)
           if ((int)j->plan.f64 == f64) js.push_back(j);
-        if (!js.empty()) launch_group(kCoarse, js, 0, f64 != 0, 0, -1, -1);
+        if (!js.empty()) launch_group(kRestrict, js, 0, f64 != 0, 0, -1, -1);
       }
       launched = true;
     }
@@ -1405,7 +1403,8 @@ class Engine {
       f64 = j->plan.f64;
     }
     ll.start[ll.n] = ll.total;
-    if (ll.total <= 0) return;
+    // (the restriction launch also has one head block per job)
+    if (ll.total <= 0 && !(st == kRestrict && ll.n > 0)) return;
     Profiler& pr = profiler();
     double px = 0.0;
     const bool prof = !noalloc_ && pr.on.load(std::memory_order_relaxed) && profiled_stage(st) &&

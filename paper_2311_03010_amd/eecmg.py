@@ -406,7 +406,7 @@ def transfer_dev(ub, HC, WC, prolongation="quad", smooth_h=1.0, pm_steps=1, k=10
 STAGES = {"restrict": 0, "cg_init_r": 1, "cg_init_s": 2, "cg_fin_init": 3, "cg_pass_a": 4, "cg_fin_a": 5,
           "cg_pass_b": 6, "cg_fin_b": 7, "mr_init": 8, "mr_fin_init": 9, "mr_pass": 10, "mr_fin": 11,
           "extrapolate": 12, "prolong_quad": 13, "prolong_linear": 14, "local_smooth": 15, "pm_step": 16,
-          "out_copy": 17, "transfer_fused": 18, "transfer_fused_small": 19, "coarse": 20, "flush_u": 21}
+          "out_copy": 17, "transfer_fused": 18, "transfer_fused_small": 19, "flush_u": 21}
 
 
 def profile_enable(enable=True, min_blocks=0, min_pixels=0.0):

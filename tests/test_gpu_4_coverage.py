@@ -230,3 +230,31 @@ def test_batch_lanes_leave_results_bitwise_unchanged(torch_cuda, monkeypatch):
         for a, b in zip(res[lanes][0], res["1"][0]):
             np.testing.assert_array_equal(a, b)
         assert res[lanes][1] == res["1"][1]
+
+
+# ------------------------------------------------------ restriction launch
+def test_served_step_with_both_precisions_and_every_coarse_layout(torch_cuda):
+    """Requests admitted in one served step share the restriction launch,
+    which also solves each job's coarse levels: it runs once per precision,
+    over jobs whose levels are all coarse (no restriction tiles), partly
+    coarse (a coarse block and tiles) or not coarse at all (one level: tiles
+    only).  Every result equals the request restored alone, bit for bit, and
+    FP32 and FP64 requests submitted together both match the oracle."""
+    t = torch_cuda
+    cases = [(synth.workload(1, H=64, W=64), "f64"),
+             (synth.workload(3, H=130, W=200, n_levels=4, n_shapes=20, n_textures=2), "f32"),
+             (synth.workload(3, H=130, W=200, n_levels=4, n_shapes=20, n_textures=2), "f64"),
+             (synth.workload(1, H=48, W=40, n_levels=3), "f32"),
+             (synth.workload(2, H=150, W=120, n_levels=1, n_shapes=20), "f32")]
+    alone = [_gpu(t, p, prec) for p, prec in cases]
+    with eecmg.Context(hbm_budget_bytes=256 << 20, max_slots=8) as ctx:
+        reqs = [ctx.submit(p.g_delta.astype(_dt(prec)), p.psf, p.n_levels, precision=prec, delta=p.delta, k=p.k)
+                for p, prec in cases]
+        got = [ctx.wait(r) for r in reqs]
+    for (p, prec), (ua, sa), (ub, sb) in zip(cases, alone, got):
+        print(f"  served {p.name} {p.shape} L={p.n_levels} {prec}", flush=True)
+        np.testing.assert_array_equal(ua, ub)
+        assert sa == sb
+    for i in (1, 2):
+        p, prec = cases[i]
+        _check(p, prec, got[i][0], got[i][1], *_oracle(p, prec))
