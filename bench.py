@@ -612,16 +612,16 @@ def main():
     roofline = None
     kern = {}
     if not args.no_profile:
-        # dominant kernel: finest-level CGLS pass B (r -= alpha q, s = H^T r,
-        # u += alpha p), timed with HIP events on the library's launch stream
-        # around each finest-level launch (the job's level holds all H x W
-        # pixels) in a timed region of its own.  Algorithmic HBM bytes per
-        # pixel and iteration are 32 (u, r, p, s each read and written once):
-        # 12 in pass A (read s, p; write p) and 20 in pass B (read r, u; write
-        # r, u, s).  The two passes actually move 16 and, on average, 26 bytes:
-        # q is stored by A and read by B; B reads p again; on levels of >=
-        # 1024^2 pixels B updates u every second iteration (alternately 20
-        # bytes without u and p, 32 with u and two directions).
+        # dominant kernel: finest-level CGLS pass B (r -= alpha q, s = H^T r),
+        # timed with HIP events on the library's launch stream around each
+        # finest-level launch (the job's level holds all H x W pixels) in a
+        # timed region of its own.  Algorithmic HBM bytes per pixel and
+        # iteration are 32 (u, r, p, s each read and written once): 12 in
+        # pass A (read s, p; write p), 12 in pass B (read r; write r, s) and 8
+        # for the solution update (read u, write u), which on levels of >=
+        # 1024^2 pixels a flush applies for up to seven iterations at once
+        # (reading u and those directions once, writing u).  The passes
+        # actually move 16 and 16 bytes: q is stored by A and read by B.
         _log("bench: profiled region (finest level)")
         eecmg.profile_reset()
         eecmg.profile_enable(True, min_pixels=H * W)
@@ -631,7 +631,7 @@ def main():
         torch.cuda.synchronize()
         ms_prof = (time.perf_counter() - tp0) / args.steps * 1e3
         eecmg.profile_enable(False)
-        for name, bpp, moved in (("cg_pass_a", 12, 16), ("cg_pass_b", 20, 26)):
+        for name, bpp, moved in (("cg_pass_a", 12, 16), ("cg_pass_b", 12, 16)):
             n, ms, px = eecmg.profile_read(name)
             if n:
                 avg_ms = ms / n
@@ -639,7 +639,7 @@ def main():
                 kern[name] = {"launches": n, "avg_us": avg_ms * 1e3, "alg_bytes_per_px": bpp,
                               "gbs": bpp * px_launch / (avg_ms * 1e-3) / 1e9, "moved_bytes_per_px": moved,
                               "moved_gbs": moved * px_launch / (avg_ms * 1e-3) / 1e9}
-        for name in ("cg_init_r", "cg_init_s", "transfer_fused", "extrapolate", "cg_fin_a", "cg_fin_b"):
+        for name in ("cg_init_r", "cg_init_s", "transfer_fused", "extrapolate", "flush_u", "cg_fin_a", "cg_fin_b"):
             n, ms, px = eecmg.profile_read(name)
             if n:
                 kern[name] = {"launches": n, "avg_us": ms / n * 1e3}
@@ -651,7 +651,7 @@ def main():
                         "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                         "copy_gbs": round(cbw, 1), "frac_vs_copy": round(ach / cbw, 4),
                         "kernel": "k_cg_b<float, ConvBox<float, 6, true>> (finest level, 4096^2, tall strips)",
-                        "avg_launch_us": round(rb["avg_us"], 2), "alg_bytes_per_launch": int(20 * H * W),
+                        "avg_launch_us": round(rb["avg_us"], 2), "alg_bytes_per_launch": int(12 * H * W),
                         "ms_per_step_profiled": round(ms_prof, 4)}
         _log("bench: profiled region (every level)")
         casc = cascade_roofline(eecmg, restore_once, p, stats, args.steps, ms_step, cbw)

@@ -736,7 +736,8 @@ __device__ inline void fin_cg_init(const JobDesc& d, SolverState* st, const doub
   st->par = 0;
   st->beta = 0.0;
   st->alpha = 0.0;
-  st->alph[0] = st->alph[1] = 0.0;
+  for (int i = 0; i < kPRing; ++i) st->alph[i] = 0.0;
+  st->na = 0;
   st->gam[1] = 0.0;
   st->done = kStopNone;
   st->pending = 0;
@@ -767,7 +768,8 @@ __device__ inline void fin_cg_a(const JobDesc& d, SolverState* st, const double 
     return;
   }
   st->alpha = st->gamma / eta;
-  st->alph[st->k & 1] = st->alpha;
+  st->alph[st->k % kPRing] = st->alpha;
+  st->na = st->k + 1;
 }
 
 // After pass B: <r,r> (1), gamma_new = <s,s> (2), beta = gamma_new / gamma.
@@ -935,6 +937,13 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
   block_sum_store<P::NT, 1>(part, d.partials + (size_t)2 * d.pstride + L.t, d.pstride);
 }
 
+// Direction buffer slot i, the slots evenly spaced from p[0] (p[1] is slot
+// 1): kPRing of them on lazy_u levels, two elsewhere.
+__device__ __forceinline__ int dir_slots(const JobDesc& d) { return uni(d.lazy_u) ? kPRing : 2; }
+__device__ __forceinline__ void* dir_slot(const JobDesc& d, int i) {
+  return (char*)d.p[0] + (size_t)i * (size_t)((char*)d.p[1] - (char*)d.p[0]);
+}
+
 // Pass A of iteration k: p_new = s + beta p_old (on tile + halo), q = H p_new;
 // partial <q,q> in slot 0.  Iteration 0 has beta = 0 and no previous
 // direction: p_old reads as zero (an empty buffer range), so p_0 = s.
@@ -974,11 +983,14 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
   } else {
     beta = (T)st->beta;
   }
-  const int par = foldb ? (k & 1) : uni(st->par);
+  // p_{k-1} in slot k, p_k into slot k + 1 (modulo the level's slot count)
+  const int ns = dir_slots(d);
+  void* const pold = dir_slot(d, k % ns);
+  void* const pnew = dir_slot(d, (k + 1) % ns);
   const bool first = k == 0;
   const auto s = gpc<T>(d.s);
-  const auto po = gpc<T>(d.p[par]);
-  auto pn = gp<T>(d.p[par ^ 1]);
+  const auto po = gpc<T>(pold);
+  auto pn = gp<T>(pnew);
   auto q = gp<T>(d.q[0]);
   double part[1] = {0.0};
   auto load = [&](unsigned o) { return Two<T>{s[o], first ? T(0) : po[o]}; };
@@ -987,7 +999,7 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
     typename P::St ps;
     P::init(ps, (const T*)d.taps);
     const unsigned n = (unsigned)(g.h * g.pitch);
-    const auto S = bview<T>(d.s, n), Po = bview<T>(d.p[par], first ? 0u : n), Pn = bview<T>(d.p[par ^ 1], n);
+    const auto S = bview<T>(d.s, n), Po = bview<T>(pold, first ? 0u : n), Pn = bview<T>(pnew, n);
     const auto Q = bview<T>(d.q[0], n);
     stream_strip<T, P>(
         g, strip_up<P>(g), n, ps, [&](unsigned o) { return Two<T>{S.ld(o), Po.ld(o)}; }, comb, NoLoadF{},
@@ -1018,22 +1030,19 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
 // Pass B of iteration k: r_new = r - alpha q (tile + halo), s = H^T r_new,
 // and the solution update; partials <r,r> (slot 1) and <s,s> (slot 2).
 // The solution update u += alpha_k p_k is applied per iteration (kUOne), or,
-// on levels the host marks lazy_u, every second iteration: even k defer
-// their term (kUDefer: no u or p traffic) and odd k apply both,
-// u = (u + alpha_{k-1} p_{k-1}) + alpha_k p_k, rounded to T after each term
-// exactly as two single updates; p_{k-1} is still in p[par] because pass A
-// writes p_k to the other buffer.  A level that stops with a deferred term
-// is completed by k_flush_u.
-enum : int { kUOne = 0, kUDefer = 1, kUTwo = 2 };
+// on levels the host marks lazy_u, deferred (kUDefer: no u or p traffic
+// here): pass A keeps the directions in a ring of kPRing slots and k_flush_u
+// applies up to kPRing - 1 terms at once, u = (..(u + alpha_j p_j) + ..) +
+// alpha_k p_k, rounded to T after each term exactly as single updates.
+enum : int { kUOne = 0, kUDefer = 1 };
 
 template <typename T, typename P, int UM>
-__device__ __forceinline__ void cg_b_body(const JobDesc& d, const TileGeo& g, int par, T alpha, T alpha_prev,
+__device__ __forceinline__ void cg_b_body(const JobDesc& d, const TileGeo& g, int par, T alpha,
                                           double (&part)[2]) {
   const auto ro = gpc<T>(d.r[par]);
   auto rn = gp<T>(d.r[par ^ 1]);
   const auto q = gpc<T>(d.q[0]);
   const auto pn = gpc<T>(d.p[par ^ 1]);
-  const auto po = gpc<T>(d.p[par]);
   auto u = gp<T>(d.u);
   auto s = gp<T>(d.s);
   auto load = [&](unsigned o) { return Two<T>{ro[o], q[o]}; };
@@ -1043,7 +1052,7 @@ __device__ __forceinline__ void cg_b_body(const JobDesc& d, const TileGeo& g, in
     P::init(ps, (const T*)d.taps_t);
     const unsigned n = (unsigned)(g.h * g.pitch);
     const auto Ro = bview<T>(d.r[par], n), Rn = bview<T>(d.r[par ^ 1], n), Q = bview<T>(d.q[0], n);
-    const auto Pn = bview<T>(d.p[par ^ 1], n), Po = bview<T>(d.p[par], n), U = bview<T>(d.u, n);
+    const auto Pn = bview<T>(d.p[par ^ 1], n), U = bview<T>(d.u, n);
     const auto S = bview<T>(d.s, n);
     auto emit = [&](unsigned o, T acc, bool in, T, NoLoad) {
       S.st(o, acc);
@@ -1055,15 +1064,6 @@ __device__ __forceinline__ void cg_b_body(const JobDesc& d, const TileGeo& g, in
           g, strip_up<P>(g), n, ps, ld_in, comb, NoLoadF{},
           [&](unsigned o, T v, bool in, NoLoad) {
             Rn.st(o, v);
-            part[0] += in ? (double)v * (double)v : 0.0;
-          },
-          NoLoadF{}, emit);
-    } else if constexpr (UM == kUTwo) {
-      stream_strip<T, P>(
-          g, strip_up<P>(g), n, ps, ld_in, comb, [&](unsigned o) { return Three<T>{U.ld(o), Pn.ld(o), Po.ld(o)}; },
-          [&](unsigned o, T v, bool in, Three<T> x) {
-            Rn.st(o, v);
-            U.st(o, fma(alpha, x.b, fma(alpha_prev, x.c, x.a)));
             part[0] += in ? (double)v * (double)v : 0.0;
           },
           NoLoadF{}, emit);
@@ -1080,11 +1080,7 @@ __device__ __forceinline__ void cg_b_body(const JobDesc& d, const TileGeo& g, in
   } else {
     __shared__ T tile[P::LH * P::LW];
     load_tile<T, P>(tile, g, load, comb);
-    if constexpr (UM == kUTwo) {
-      for_interior<P>(
-          g, [&](unsigned o) { return Three<T>{u[o], pn[o], po[o]}; },
-          [&](Three<T> x, unsigned o, int) { u[o] = fma(alpha, x.b, fma(alpha_prev, x.c, x.a)); });
-    } else if constexpr (UM == kUOne) {
+    if constexpr (UM == kUOne) {
       for_interior<P>(
           g, [&](unsigned o) { return Two<T>{u[o], pn[o]}; },
           [&](Two<T> x, unsigned o, int) { u[o] = fma(alpha, x.b, x.a); });
@@ -1129,16 +1125,13 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
     if (lead) fin_cg_a(d, d.st, v);
     alpha = (T)(st->gamma / v[0]);
   } else {
-    alpha = (T)st->alph[k & 1];
+    alpha = (T)st->alph[k % kPRing];
   }
-  const int um = uni(d.lazy_u) == 0 ? kUOne : ((k & 1) ? kUTwo : kUDefer);
   double part[2] = {0.0, 0.0};
-  if (um == kUDefer)
-    cg_b_body<T, P, kUDefer>(d, g, par, alpha, T(0), part);
-  else if (um == kUTwo)
-    cg_b_body<T, P, kUTwo>(d, g, par, alpha, (T)st->alph[(k - 1) & 1], part);
+  if (uni(d.lazy_u))
+    cg_b_body<T, P, kUDefer>(d, g, par, alpha, part);
   else
-    cg_b_body<T, P, kUOne>(d, g, par, alpha, T(0), part);
+    cg_b_body<T, P, kUOne>(d, g, par, alpha, part);
   block_sum_store<P::NT, 2>(part, d.partials + (size_t)1 * d.pstride + L.t, d.pstride);
 }
 

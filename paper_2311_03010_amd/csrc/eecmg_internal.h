@@ -33,10 +33,15 @@ enum : int32_t { kStopNone = 0, kStopDiscrepancy = 1, kStopCap = 2, kStopGuard =
 // Device-resident smoother scalars of one job (one per slot).  Every scalar
 // of the Krylov recurrences lives here in FP64 and is only touched by the
 // finalize kernels, so the host never reads them during a level.
+// Direction slots of a level whose CGLS solution update is deferred (lazy_u):
+// p_k lives in slot (k + 1) mod kPRing, so the kPRing - 1 latest directions
+// stay available and their updates are applied together (k_flush_u).
+constexpr int kPRing = 8;
+
 struct SolverState {
   double gamma, gamma0, alpha, beta;  // CGLS: <s,s>, initial <s,s>, step, direction update
   double rr, rr0, rq, eta;            // <r,r>, initial <r,r>, <r,q> (MR), <q,q>
-  double alph[2];                     // CGLS: step alpha_k of the last iteration k of each parity
+  double alph[kPRing];                // CGLS: step alpha_k of iteration k, in slot k mod kPRing
   double gam[2];                      // CGLS: gamma_k = <s_k,s_k> of the last iteration k of each parity
   int32_t k;                          // iterations completed on this level
   int32_t done;                       // stop reason, 0 while running
@@ -44,7 +49,8 @@ struct SolverState {
   int32_t level;                      // level the state belongs to
   int32_t pending;                    // MR: a step alpha is waiting to be applied
   int32_t seq;                        // finalize counter (diagnostics)
-  int32_t pad[2];
+  int32_t na;                         // CGLS: iterations whose step alpha is known (pass B then runs)
+  int32_t pad;
 };
 
 
@@ -73,7 +79,7 @@ struct JobDesc {
   int32_t cascade, pm_steps;
   int32_t coarse_levels;  // level 0 only: leading levels solved by the coarse kernel
   int32_t zero_u;         // bit l: level l's smoother starts from zero (no transfer into it)
-  int32_t lazy_u;         // CGLS pass B updates u every second iteration (see k_cg_b)
+  int32_t lazy_u;         // CGLS: u updated by k_flush_u from a ring of kPRing directions (see k_cg_b)
   int32_t fold_a;         // CGLS pass B may compute alpha itself (when its launch says so)
   int32_t nstrips;       // streaming policies: strips of the level (ntiles counts blocks)
   int32_t pad2, pad3, pad4;

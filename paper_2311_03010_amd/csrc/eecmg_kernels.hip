@@ -1371,28 +1371,72 @@ __global__ __launch_bounds__(kCoarseThreads) void k_restrict(LaunchList ll, cons
   }
 }
 
-// A lazy_u level (see k_cg_b) that stopped with k odd still owes the update
-// u += alpha_k p_k of its last even iteration: alpha is that step (a stop in
-// the next pass A leaves it unchanged) and p_k sits in p[par] (pass B flipped
-// the parity, or the stopping pass A never wrote over it).
+constexpr int kFlushChunkBytes = 16;  // k_flush_u: bytes of a row per thread
+
+// The deferred solution updates of a lazy_u level (see k_cg_b): terms are
+// applied in groups of G = kPRing - 1 consecutive iterations, in order,
+// u = (..(u + alpha_j p_j) + ..) + alpha_k p_k, rounded to T after each term
+// exactly as single updates.  ll.kf[e] >= 0: the launch follows pass B of
+// iteration j = ll.kf[e] (the last of its group; the host issues it before
+// the next pass A could overwrite the group's oldest slot) and applies that
+// group if the level got that far; -1: the level has ended and the last,
+// incomplete group is applied.  Which terms exist follows from st->na alone
+// (the iterations whose pass B ran), so every block agrees.
 template <typename T>
 __global__ __launch_bounds__(256) void k_flush_u(LaunchList ll, const JobDesc* __restrict__ descs) {
+  constexpr int G = kPRing - 1;
+  constexpr int E = kFlushChunkBytes / sizeof(T);  // elements per 16-byte chunk
+  typedef T V __attribute__((ext_vector_type(E)));
   const Loc L = locate(ll, remap_xcd(blockIdx.x, gridDim.x));
   const JobDesc& d = descs[L.d];
   const SolverState* st = d.st;
-  if (!__builtin_amdgcn_readfirstlane(d.lazy_u) || !(__builtin_amdgcn_readfirstlane(st->k) & 1)) return;
-  const int tiles_x = (d.w + kXW - 1) / kXW;
-  const int ty = L.t / tiles_x, tx = L.t - ty * tiles_x;
-  const int x = tx * kXW + (threadIdx.x & 63);
-  if (x >= d.w) return;
-  const T a = (T)st->alpha;
-  const T* p = (const T*)d.p[__builtin_amdgcn_readfirstlane(st->par)];
+  if (!__builtin_amdgcn_readfirstlane(d.lazy_u)) return;
+  const int na = __builtin_amdgcn_readfirstlane(st->na);
+  const int j = ll.kf[L.e];
+  int t0, t1;
+  if (j >= 0) {
+    if (na < j + 1) return;  // the level stopped before this pass B
+    t0 = j + 1 - G;
+    t1 = j + 1;
+  } else {
+    t0 = na - na % G;
+    t1 = na;
+  }
+  if (t0 >= t1) return;
+  // one 16-byte chunk of a row per thread (rows start 256-byte aligned)
+  const int cw = (d.w + E - 1) / E;
+  const int i = L.t * 256 + (int)threadIdx.x;
+  if (i >= d.h * cw) return;
+  const int y = i / cw, x = (i - y * cw) * E;
+  const size_t o = (size_t)y * d.pitch + x;
+  const int nt = t1 - t0;
+  T a[G];
+  const T* p[G];
+#pragma unroll
+  for (int m = 0; m < G; ++m) {
+    const int t = m < nt ? t0 + m : t0;  // (unused terms re-read the first one)
+    a[m] = (T)st->alph[t % kPRing];
+    p[m] = (const T*)((const char*)d.p[0] + (size_t)((t + 1) % kPRing) * (size_t)((char*)d.p[1] - (char*)d.p[0]));
+  }
   T* u = (T*)d.u;
-  for (int k = 0; k < kXH / 4; ++k) {
-    const int y = ty * kXH + (threadIdx.x >> 6) * (kXH / 4) + k;
-    if (y >= d.h) break;
-    const size_t o = (size_t)y * d.pitch + x;
-    u[o] = fma(a, p[o], u[o]);
+  if (x + E <= d.w) {
+    V v[G];
+#pragma unroll
+    for (int m = 0; m < G; ++m) v[m] = *(const V*)(p[m] + o);
+    V acc = *(const V*)(u + o);
+#pragma unroll
+    for (int m = 0; m < G; ++m)
+      if (m < nt) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[e] = fma(a[m], v[m][e], acc[e]);
+      }
+    *(V*)(u + o) = acc;
+  } else {
+    for (int e = 0; x + e < d.w; ++e) {
+      T acc = u[o + e];
+      for (int m = 0; m < nt; ++m) acc = fma(a[m], p[m][o + e], acc);
+      u[o + e] = acc;
+    }
   }
 }
 
@@ -1509,7 +1553,10 @@ int blocks_for_stage(Stage st, const JobDesc& d) {
     case kXfExtrap: return tiles2((d.hB + 1) / 2, (d.wB + 1) / 2, kPiTH, kXW);  // 2 x 2 outputs per thread
     case kXfFused: return d.f64 ? tiles2(d.h, d.w, kFY, kFX) : tiles2(d.h, d.w, kFY32, sgeo_ow(d.pm_steps >= 1));
     case kXfFusedSmall: return tiles2(d.h, d.w, kFYSmall, d.f64 ? kFX : sgeo_ow(d.pm_steps >= 1));
-    case kFlushU: return tiles2(d.h, d.w, kXH, kXW);
+    case kFlushU: {  // one 16-byte chunk per thread
+      const long chunks = (long)d.h * ((d.w + kFlushChunkBytes / (d.f64 ? 8 : 4) - 1) / (kFlushChunkBytes / (d.f64 ? 8 : 4)));
+      return (int)((chunks + 255) / 256);
+    }
     default: return tiles2(d.h, d.w, kXH, kXW);
   }
 }

@@ -73,7 +73,7 @@ struct LevelPlan {
   int h = 0, w = 0, pitch = 0, rad = 0, cap = 0, ntiles = 0, tiles_x = 0;
   int nstrips = 0;  // smoother tiles (general) or strips (streaming); ntiles counts blocks
   int variant = 0;                    // blur-operator kernel family (ConvKind * 100 + R)
-  bool lazy = false;                  // CGLS solution update every second iteration
+  bool lazy = false;                  // CGLS solution updates deferred (k_flush_u)
   bool fold_a = false;                // CGLS pass B evaluates pass A's finalize itself
   std::vector<double> psf;            // (2 rad + 1)^2, FP64
   std::vector<double> taps, taps_t;   // the variant's tap layout for H and H^T
@@ -104,9 +104,11 @@ constexpr long kSmallLevelPixels = 512L * 512L;
 // Levels up to this many pixels (the leading ones of a cascade) are solved
 // by one block per job in a single launch.
 constexpr long kCoarsePixels = 64L * 64L;
-// CGLS levels of at least this many pixels update the solution every second
-// iteration (k_cg_b's lazy_u mode): it saves 8 bytes per pixel per pair of
-// iterations and costs one flush launch when the level ends.
+// CGLS levels of at least this many pixels defer their solution updates
+// (k_cg_b's lazy_u mode): pass B moves no u or p, and k_flush_u applies the
+// terms of up to kPRing - 1 iterations in one pass (reading u and their
+// directions once) -- 4 + 8 / (kPRing - 1) instead of 12 bytes per pixel and
+// iteration, for kPRing - 2 more direction buffers of the finest level's size.
 constexpr long kLazyPixels = 1024L * 1024L;
 // The threshold can be moved with EECMG_LAZY_MIN_PIXELS (tests use it to run
 // both update schedules on small images).
@@ -241,7 +243,7 @@ struct Plan {
   // device layout (byte offsets inside the job allocation)
   size_t off_gin = 0, off_uout = 0, off_part = 0, taps_bytes = 0;  // taps region at offset 0
   size_t off_g[kMaxLevels] = {}, off_u[kMaxLevels] = {}, off_taps[kMaxLevels] = {}, off_tapst[kMaxLevels] = {};
-  size_t off_work[7] = {};  // r0 r1 p0 p1 s q0 q1
+  size_t off_work[7] = {};  // r0 r1 p0 p1 s q0 q1 (p0, p1: the first direction slots)
   size_t bytes = 0;
   int max_tiles = 0;
   int coarse = 0;  // leading levels solved by the coarse-cascade kernel
@@ -301,8 +303,10 @@ static void default_params(eecmg_params* p) {
   p->stats = nullptr;
 }
 
+// defer_updates = false: no level defers its CGLS solution updates (two
+// direction buffers instead of kPRing; the results are the same bits).
 static int build_plan(int H, int W, const double* psf, int r, int L, const int* caps, double k,
-                      const eecmg_params* params, bool own_io, Plan& P) {
+                      const eecmg_params* params, bool own_io, Plan& P, bool defer_updates = true) {
   eecmg_params prm;
   if (params) {
     if (params->struct_size != sizeof(eecmg_params)) return fail(EECMG_EINVAL, "params->struct_size mismatch");
@@ -392,7 +396,8 @@ static int build_plan(int H, int W, const double* psf, int r, int L, const int* 
       lp.taps_t.assign(lp.psf.rbegin(), lp.psf.rend());
     } else {
       choose_variant(P.lv[l], P.f64, true);
-      P.lv[l].lazy = P.prm.smoother == EECMG_SMOOTHER_CGLS && (long)P.lv[l].h * P.lv[l].w >= lazy_min_pixels();
+      P.lv[l].lazy = defer_updates && P.prm.smoother == EECMG_SMOOTHER_CGLS &&
+                     (long)P.lv[l].h * P.lv[l].w >= lazy_min_pixels();
     }
     P.off_taps[l] = take(P.lv[l].taps.size() * P.esz);
     P.off_tapst[l] = take(P.lv[l].taps_t.size() * P.esz);
@@ -431,7 +436,14 @@ static int build_plan(int H, int W, const double* psf, int r, int L, const int* 
     P.off_u[l] = take((size_t)lp.h * lp.pitch * P.esz);
   }
   const size_t fine = (size_t)P.lv[L - 1].h * P.lv[L - 1].pitch * P.esz;
-  for (int i = 0; i < 7; ++i) P.off_work[i] = take(fine);
+  // r, r', s, q, q', then the direction slots, evenly spaced: two, or
+  // kPRing when a level defers its solution updates
+  for (int i : {0, 1, 4, 5, 6}) P.off_work[i] = take(fine);
+  bool any_lazy = false;
+  for (int l = 0; l < L; ++l) any_lazy = any_lazy || P.lv[l].lazy;
+  P.off_work[2] = take(fine);
+  P.off_work[3] = take(fine);
+  for (int i = 2; i < (any_lazy ? kPRing : 2); ++i) take(fine);
   P.off_part = take((size_t)P.max_tiles * kNPart * sizeof(double));
   P.bytes = off;
   return EECMG_OK;
@@ -1576,6 +1588,22 @@ class Engine {
           fin_b.insert(fin_b.end(), g.js.begin(), g.js.end());
       }
       launch_fin(kCgFinB, fin_b);
+      // a deferred-update level whose iteration closes a group of kPRing - 1
+      // terms applies them before the next pass A reuses the oldest slot
+      for (int f64 = 0; f64 < 2; ++f64) {
+        std::vector<Job*> fj;
+        std::vector<int> fk;
+        for (auto& kv : groups) {
+          if (kv.first.first != EECMG_SMOOTHER_CGLS || (kv.first.second >= 100000) != (f64 != 0)) continue;
+          const Group& g = kv.second;
+          for (size_t i = 0; i < g.js.size(); ++i)
+            if (lazy_level(g.js[i], g.js[i]->cur_level()) && g.ks[i] % (kPRing - 1) == kPRing - 2) {
+              fj.push_back(g.js[i]);
+              fk.push_back(g.ks[i]);
+            }
+        }
+        if (!fj.empty()) launch_group(kFlushU, fj, -1, f64 != 0, 0, -1, -1, nullptr, nullptr, 0, &fk);
+      }
       for (auto& kv : groups) {
         if (kv.first.first == EECMG_SMOOTHER_CGLS) continue;
         const bool f64 = kv.first.second >= 100000;
@@ -2027,6 +2055,11 @@ int eecmg_restore_dev_noalloc(const void* g_delta_dev, int H, int W, const doubl
   if (!ne) return rc;
   std::lock_guard<std::mutex> g(ne->mu);
   Engine& E = *ne->eng;
+  // without the direction ring if that is what makes the restore fit
+  if (job.plan.bytes > E.arena_capacity()) {
+    rc = build_plan(H, W, psf, psf_radius, n_levels, iters_per_level, k, params, false, job.plan, false);
+    if (rc) return rc;
+  }
   if (job.plan.bytes > E.arena_capacity())
     return fail(EECMG_EINVAL, "the restore needs " + std::to_string(job.plan.bytes) +
                                   " bytes of device scratch, more than the fixed region's " +

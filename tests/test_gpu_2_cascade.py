@@ -239,13 +239,15 @@ def test_host_restore_equals_dev(torch_cuda):
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-@pytest.mark.parametrize("caps", ["rule", "odd", "even"])
+@pytest.mark.parametrize("caps", ["rule", "odd", "even", "long"])
 def test_lazy_solution_update_is_bitwise_identical(torch_cuda, monkeypatch, prec, caps):
-    """Large CGLS levels update u every second iteration (a deferred term is
-    applied with the next one, or by a flush when the level stops).  Forced on
-    every level of a small cascade it must reproduce the per-iteration
-    schedule bit for bit, for odd and even iteration counts and for
-    data-dependent stops; so must the one-level smoother call."""
+    """Large CGLS levels defer their solution updates: pass A keeps the
+    directions in a ring of eight slots and a flush applies the terms of
+    seven iterations at once (after every seventh pass B, and when the level
+    stops).  Forced on every level of a small cascade it must reproduce the
+    per-iteration schedule bit for bit, for iteration counts below, at and
+    across the group size (one, two and three groups, complete or not) and
+    for data-dependent stops; so must the one-level smoother call."""
     t = torch_cuda
     p = synth.workload(3, H=200, W=160, n_levels=3, n_shapes=20, n_textures=2, precision=prec)
     g = t.from_numpy(p.g_delta.astype(_dt(prec))).to("cuda:0")
@@ -253,14 +255,15 @@ def test_lazy_solution_update_is_bitwise_identical(torch_cuda, monkeypatch, prec
     if caps == "rule":
         cl = None
     else:
-        cl = [3, 5, 7] if caps == "odd" else [2, 4, 6]
+        cl = {"odd": [3, 5, 7], "even": [2, 4, 6], "long": [9, 14, 17]}[caps]
         kw["stop_rule"] = False
     res = {}
     for mode, thr in (("lazy", "1"), ("eager", str(1 << 40))):
         monkeypatch.setenv("EECMG_LAZY_MIN_PIXELS", thr)
         u, st = eecmg.restore_dev(g, p.psf, 3, caps=cl, **kw)
         u0 = t.zeros_like(g)
-        _, su = eecmg.smoother_dev(g, u0, p.psf, 5 if caps != "even" else 4, precision=prec, delta=p.delta)
+        n1 = {"even": 4, "long": 15}.get(caps, 5)
+        _, su = eecmg.smoother_dev(g, u0, p.psf, n1, precision=prec, delta=p.delta)
         t.cuda.synchronize()
         res[mode] = (u.cpu().numpy(), st, u0.cpu().numpy(), su)
     np.testing.assert_array_equal(res["lazy"][0], res["eager"][0])
