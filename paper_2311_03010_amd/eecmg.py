@@ -74,8 +74,9 @@ def lib():
     sig = {
         "eecmg_params_default": [ctypes.POINTER(Params)],
         "eecmg_restore": [vp, i, i, dp, i, i, ip, d, ctypes.POINTER(Params), vp],
-        "eecmg_restore_dev": [vp, i, i, dp, i, i, ip, d, ctypes.POINTER(Params), vp, vp],
-        "eecmg_restore_dev_noalloc": [vp, i, i, dp, i, i, ip, d, ctypes.POINTER(Params), vp, vp],
+        # (the per-call device entry points take every pointer as an address)
+        "eecmg_restore_dev": [vp, i, i, vp, i, i, vp, d, vp, vp, vp],
+        "eecmg_restore_dev_noalloc": [vp, i, i, vp, i, i, vp, d, vp, vp, vp],
         "eecmg_restore_batch_dev": [i, ctypes.POINTER(vp), ip, ip, ctypes.POINTER(dp), ip, ip, ctypes.POINTER(ip), dp,
                                     ctypes.POINTER(Params), ctypes.POINTER(vp), vp],
         "eecmg_ctx_config_default": [ctypes.POINTER(CtxConfig)],
@@ -212,19 +213,36 @@ def restore_dev(g_delta, psf, n_levels, caps=None, k=10.0, out=None, stream=None
         raise ValueError(f"g_delta must be a contiguous {dt} CUDA tensor")
     if out is None:
         out = torch.empty_like(g_delta)
-    p = make_params(**kw)
+    p = _params_for(kw)
     st = Stats()
     st.struct_size = ctypes.sizeof(Stats)
-    p.stats = ctypes.cast(ctypes.pointer(st), ctypes.c_void_p)
+    p.stats = ctypes.addressof(st)
     psf, r = _psf_arr(psf)
     c = _caps_arr(caps, n_levels)
     fn = lib().eecmg_restore_dev_noalloc if noalloc else lib().eecmg_restore_dev
-    rc = fn(ctypes.c_void_p(g_delta.data_ptr()), g_delta.shape[0], g_delta.shape[1], _dptr(psf),
-                                 r, int(n_levels),
-                                 c.ctypes.data_as(ctypes.POINTER(ctypes.c_int)) if c is not None else None, float(k),
-                                 ctypes.byref(p), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
+    rc = fn(g_delta.data_ptr(), g_delta.shape[0], g_delta.shape[1], psf.__array_interface__["data"][0], r,
+            int(n_levels), c.__array_interface__["data"][0] if c is not None else None, float(k),
+            ctypes.addressof(p), out.data_ptr(), _stream_handle(stream))
     _check(rc)
     return out, st.to_dict()
+
+
+_PARAMS_CACHE = {}
+
+
+def _params_for(kw):
+    """A fresh eecmg_params struct for these keyword arguments (copied from a
+    cached one: filling the struct field by field costs more than the copy)."""
+    try:
+        key = tuple(sorted(kw.items()))
+        t = _PARAMS_CACHE.get(key)
+    except TypeError:  # an unhashable value: no caching
+        return make_params(**kw)
+    if t is None:
+        t = make_params(**kw)
+        if len(_PARAMS_CACHE) < 256:
+            _PARAMS_CACHE[key] = t
+    return Params.from_buffer_copy(t)
 
 
 def _override_params(p, kv):
