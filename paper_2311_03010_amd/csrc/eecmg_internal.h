@@ -77,7 +77,7 @@ struct JobDesc {
   int32_t cap, level;
   int32_t stop_rule, smoother;
   int32_t cascade, pm_steps;
-  int32_t coarse_levels;  // level 0 only: leading levels solved by the coarse kernel
+  int32_t coarse_levels;  // level 0 only: leading levels solved by the restriction launch's head block
   int32_t zero_u;         // bit l: level l's smoother starts from zero (no transfer into it)
   int32_t lazy_u;         // CGLS: u updated by k_flush_u from a ring of kPRing directions (see k_cg_b)
   int32_t fold_a;         // CGLS pass B may compute alpha itself (when its launch says so)

@@ -58,7 +58,7 @@ struct XArgs {
 // (exact for quadratics), 3 v1 - 3 v2 + v3 as two explicit FMAs: left to
 // itself the compiler may contract either product, differently from one
 // inlined call to the next, so the same node could round differently in the
-// coarse kernel and in the engine's transfer kernels.
+// coarse cascade and in the engine's transfer kernels.
 __device__ __forceinline__ double qx3(double v1, double v2, double v3) { return fma(3.0, v1, fma(-3.0, v2, v3)); }
 
 // Pi correction d(a,b) = uB(2a,2b) - uA(a,b) on the level-(l-1) grid, with one

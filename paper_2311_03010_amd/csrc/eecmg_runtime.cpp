@@ -246,7 +246,7 @@ struct Plan {
   size_t off_work[7] = {};  // r0 r1 p0 p1 s q0 q1 (p0, p1: the first direction slots)
   size_t bytes = 0;
   int max_tiles = 0;
-  int coarse = 0;  // leading levels solved by the coarse-cascade kernel
+  int coarse = 0;  // leading levels solved by the restriction launch (one block per job)
 };
 
 // Economic iteration counts (Section 2): for l > L/2,
@@ -377,7 +377,7 @@ static int build_plan(int H, int W, const double* psf, int r, int L, const int* 
   // solve order
   P.order.clear();
   for (int l = 0; l < L; ++l) P.order.push_back(l);
-  // leading small levels go to the coarse-cascade kernel (full taps)
+  // leading small levels go to the one-block coarse cascade (full taps)
   P.coarse = 0;
   while (P.coarse < L && (long)P.lv[P.coarse].h * P.lv[P.coarse].w <= kCoarsePixels) P.coarse += 1;
   // tiles and layout

@@ -1,5 +1,5 @@
 """GPU parity against the oracle for the slices of the method that run on the
-multi-level engine rather than inside the one-block coarse kernel:
+multi-level engine rather than inside the one-block coarse cascade:
   - Algorithm 1 (IECMG-L with the linear prolongation of eq. 15, IECMG-P with
     the quadratic interpolation of Section 3.2) on cascades whose levels
     exceed 64^2, CGLS and MR;
@@ -73,7 +73,7 @@ def _gpu(t, p, prec, **kw):
 @pytest.mark.parametrize("smoother", ["cgls", "mr"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_algorithm1_on_engine_levels(torch_cuda, cascade, smoother, prec):
-    # 257 x 190 with 4 levels: 33 x 24, 65 x 48 (coarse kernel), 129 x 95 and
+    # 257 x 190 with 4 levels: 33 x 24, 65 x 48 (coarse cascade), 129 x 95 and
     # 257 x 190 on the engine, ragged on both axes
     p = synth.workload(3, H=257, W=190, n_levels=4, n_shapes=30, n_textures=3, precision=prec)
     u, st = _gpu(torch_cuda, p, prec, smoother=smoother, cascade=cascade)
