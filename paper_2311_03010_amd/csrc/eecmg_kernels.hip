@@ -1037,32 +1037,60 @@ __device__ void coarse_cgls(const JobDesc& d) {
   SolverState* st = &state;
   __shared__ double sc[2];
   __shared__ int done;
+  // a one-tap blur (R = 0, the coarse levels of most PSFs) is pointwise:
+  // sweeps that only chain blurs then run as one, with the same expressions
+  // (the tap product as fma(w, x, 0), as the tap loop forms it), so the
+  // results are the same bits
+  const bool pw = R == 0;
+  const T w0 = tp[0], wt0 = tt[0];
   double v[2] = {0.0, 0.0};
-  coarse_sweep(n, w, P, [&](const Px (&px)[kCoarseU]) {
-    T hv[kCoarseU], gv[kCoarseU];
+  if (pw) {
+    coarse_sweep(n, w, P, [&](const Px (&px)[kCoarseU]) {
+      T gv[kCoarseU], uv[kCoarseU];
 #pragma unroll
-    for (int m = 0; m < kCoarseU; ++m) gv[m] = g[px[m].o];
-    coarse_conv(u, P, h, w, tp, R, px, hv);
-#pragma unroll
-    for (int m = 0; m < kCoarseU; ++m)
-      if (px[m].ok) {
-        const T rv = gv[m] - hv[m];
-        r[px[m].o] = rv;
-        v[0] += (double)rv * (double)rv;
+      for (int m = 0; m < kCoarseU; ++m) {
+        gv[m] = g[px[m].o];
+        uv[m] = u[px[m].o];
       }
-  });
-  __syncthreads();
-  coarse_sweep(n, w, P, [&](const Px (&px)[kCoarseU]) {
-    T sv[kCoarseU];
-    coarse_conv(r, P, h, w, tt, R, px, sv);
 #pragma unroll
-    for (int m = 0; m < kCoarseU; ++m)
-      if (px[m].ok) {
-        s[px[m].o] = sv[m];
-        p[px[m].o] = sv[m];
-        v[1] += (double)sv[m] * (double)sv[m];
-      }
-  });
+      for (int m = 0; m < kCoarseU; ++m)
+        if (px[m].ok) {
+          const T rv = gv[m] - fma(w0, uv[m], T(0));
+          const T sv = fma(wt0, rv, T(0));
+          r[px[m].o] = rv;
+          s[px[m].o] = sv;
+          p[px[m].o] = sv;
+          v[0] += (double)rv * (double)rv;
+          v[1] += (double)sv * (double)sv;
+        }
+    });
+  } else {
+    coarse_sweep(n, w, P, [&](const Px (&px)[kCoarseU]) {
+      T hv[kCoarseU], gv[kCoarseU];
+#pragma unroll
+      for (int m = 0; m < kCoarseU; ++m) gv[m] = g[px[m].o];
+      coarse_conv(u, P, h, w, tp, R, px, hv);
+#pragma unroll
+      for (int m = 0; m < kCoarseU; ++m)
+        if (px[m].ok) {
+          const T rv = gv[m] - hv[m];
+          r[px[m].o] = rv;
+          v[0] += (double)rv * (double)rv;
+        }
+    });
+    __syncthreads();
+    coarse_sweep(n, w, P, [&](const Px (&px)[kCoarseU]) {
+      T sv[kCoarseU];
+      coarse_conv(r, P, h, w, tt, R, px, sv);
+#pragma unroll
+      for (int m = 0; m < kCoarseU; ++m)
+        if (px[m].ok) {
+          s[px[m].o] = sv[m];
+          p[px[m].o] = sv[m];
+          v[1] += (double)sv[m] * (double)sv[m];
+        }
+    });
+  }
   coarse_reduce(v);
   if (threadIdx.x == 0) {
     fin_cg_init(d, st, v, false);
@@ -1071,7 +1099,7 @@ __device__ void coarse_cgls(const JobDesc& d) {
   __syncthreads();
   bool first = true;
   while (!done) {
-    if (!first) {
+    if (!first && !pw) {
       const T beta = (T)sc[1];
       coarse_sweep(n, w, P, [&](const Px (&px)[kCoarseU]) {
         T a[kCoarseU], b[kCoarseU];
@@ -1086,18 +1114,40 @@ __device__ void coarse_cgls(const JobDesc& d) {
       });
       __syncthreads();
     }
-    first = false;
     double e[1] = {0.0};
-    coarse_sweep(n, w, P, [&](const Px (&px)[kCoarseU]) {
-      T qv[kCoarseU];
-      coarse_conv(p, P, h, w, tp, R, px, qv);
+    if (pw) {
+      const bool upd = !first;
+      const T beta = upd ? (T)sc[1] : T(0);
+      coarse_sweep(n, w, P, [&](const Px (&px)[kCoarseU]) {
+        T a[kCoarseU], b[kCoarseU];
 #pragma unroll
-      for (int m = 0; m < kCoarseU; ++m)
-        if (px[m].ok) {
-          q[px[m].o] = qv[m];
-          e[0] += (double)qv[m] * (double)qv[m];
+        for (int m = 0; m < kCoarseU; ++m) {
+          a[m] = p[px[m].o];
+          b[m] = s[px[m].o];
         }
-    });
+#pragma unroll
+        for (int m = 0; m < kCoarseU; ++m)
+          if (px[m].ok) {
+            const T pv = upd ? fma(beta, a[m], b[m]) : a[m];
+            const T qv = fma(w0, pv, T(0));
+            if (upd) p[px[m].o] = pv;
+            q[px[m].o] = qv;
+            e[0] += (double)qv * (double)qv;
+          }
+      });
+    } else {
+      coarse_sweep(n, w, P, [&](const Px (&px)[kCoarseU]) {
+        T qv[kCoarseU];
+        coarse_conv(p, P, h, w, tp, R, px, qv);
+#pragma unroll
+        for (int m = 0; m < kCoarseU; ++m)
+          if (px[m].ok) {
+            q[px[m].o] = qv[m];
+            e[0] += (double)qv[m] * (double)qv[m];
+          }
+      });
+    }
+    first = false;
     coarse_reduce(e);
     if (threadIdx.x == 0) {
       fin_cg_a(d, st, e, false);
@@ -1124,19 +1174,26 @@ __device__ void coarse_cgls(const JobDesc& d) {
           r[px[m].o] = rn;
           u[px[m].o] = fma(alpha, pv[m], uv[m]);
           b[0] += (double)rn * (double)rn;
+          if (pw) {
+            const T sv = fma(wt0, rn, T(0));
+            s[px[m].o] = sv;
+            b[1] += (double)sv * (double)sv;
+          }
         }
     });
-    __syncthreads();
-    coarse_sweep(n, w, P, [&](const Px (&px)[kCoarseU]) {
-      T sv[kCoarseU];
-      coarse_conv(r, P, h, w, tt, R, px, sv);
+    if (!pw) {
+      __syncthreads();
+      coarse_sweep(n, w, P, [&](const Px (&px)[kCoarseU]) {
+        T sv[kCoarseU];
+        coarse_conv(r, P, h, w, tt, R, px, sv);
 #pragma unroll
-      for (int m = 0; m < kCoarseU; ++m)
-        if (px[m].ok) {
-          s[px[m].o] = sv[m];
-          b[1] += (double)sv[m] * (double)sv[m];
-        }
-    });
+        for (int m = 0; m < kCoarseU; ++m)
+          if (px[m].ok) {
+            s[px[m].o] = sv[m];
+            b[1] += (double)sv[m] * (double)sv[m];
+          }
+      });
+    }
     coarse_reduce(b);
     if (threadIdx.x == 0) {
       fin_cg_b(d, st, b, false);
