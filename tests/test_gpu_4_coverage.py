@@ -258,3 +258,42 @@ def test_served_step_with_both_precisions_and_every_coarse_layout(torch_cuda):
     for i in (1, 2):
         p, prec = cases[i]
         _check(p, prec, got[i][0], got[i][1], *_oracle(p, prec))
+
+
+# ------------------------------------------------- deferred updates, shared
+def test_deferred_updates_in_shared_launches_match_eager_plain(torch_cuda, monkeypatch):
+    """Deferred solution updates forced on every level, with iteration counts
+    below, at and across the seven-term flush groups, for several jobs that
+    share each launch (batched call and served context: launches whose jobs
+    flush at different iterations, and no folded finalizes): every result
+    equals the eager per-iteration update of the image restored alone, bit
+    for bit, with the same statistics."""
+    t = torch_cuda
+    cases = [(synth.workload(3, H=200, W=160, n_levels=3, n_shapes=20, n_textures=2), [2, 9, 14]),
+             (synth.workload(3, H=96, W=130, n_levels=3, n_shapes=10), [7, 3, 17]),
+             (synth.workload(2, H=150, W=120, n_levels=3, n_shapes=20), [1, 6, 8]),
+             (synth.workload(1, H=100, W=90, n_levels=3, n_shapes=10), [5, 13, 21])]
+    gs = [t.from_numpy(p.g_delta.astype(np.float32)).to("cuda:0") for p, _ in cases]
+    monkeypatch.setenv("EECMG_LAZY_MIN_PIXELS", str(1 << 40))
+    ref = []
+    for (p, cl), g in zip(cases, gs):
+        u, st = eecmg.restore_dev(g, p.psf, p.n_levels, caps=cl, precision="f32", delta=p.delta, stop_rule=False)
+        t.cuda.synchronize()
+        ref.append((u.cpu().numpy(), st))
+    monkeypatch.setenv("EECMG_LAZY_MIN_PIXELS", "1")
+    print("  batched, deferred updates on every level", flush=True)
+    outs, sts = eecmg.restore_batch_dev(gs, [p.psf for p, _ in cases], [p.n_levels for p, _ in cases],
+                                        caps=[cl for _, cl in cases], precision="f32",
+                                        params=[{"delta": p.delta, "stop_rule": False} for p, _ in cases])
+    t.cuda.synchronize()
+    for (ua, sa), ub, sb in zip(ref, outs, sts):
+        np.testing.assert_array_equal(ua, ub.cpu().numpy())
+        assert sa == sb
+    print("  served, deferred updates on every level", flush=True)
+    with eecmg.Context(hbm_budget_bytes=256 << 20, max_slots=8) as ctx:
+        reqs = [ctx.submit(p.g_delta.astype(np.float32), p.psf, p.n_levels, caps=cl, precision="f32",
+                           delta=p.delta, stop_rule=False) for p, cl in cases]
+        got = [ctx.wait(r) for r in reqs]
+    for (ua, sa), (ub, sb) in zip(ref, got):
+        np.testing.assert_array_equal(ua, ub)
+        assert sa == sb
