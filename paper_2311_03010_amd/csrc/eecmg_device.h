@@ -851,10 +851,6 @@ template <typename T>
 struct Two {
   T a, b;
 };
-template <typename T>
-struct Three {
-  T a, b, c;
-};
 
 // r = g - H u0, stored in r[0]; partial <r,r> in slot 1.  (CGLS and MR)
 template <typename T, typename P>
