@@ -226,8 +226,9 @@ def cascade_roofline(eecmg, restore_once, p, stats, steps, ms_step, copy_gbs):
     sizes = [tuple(s) for s in stats["sizes"]]
     esz = 8 if p.precision == "f64" else 4
     lb, rb = level_bytes(sizes, stats["iters"], esz)
-    coarse = 0
-    while coarse < len(sizes) and sizes[coarse][0] * sizes[coarse][1] <= 64 * 64:
+    coarse = 0  # the levels the library's one-block cascade solves (EECMG_COARSE_MAX_PIXELS)
+    coarse_px = int(os.environ.get("EECMG_COARSE_MAX_PIXELS", 64 * 64))
+    while coarse < len(sizes) and sizes[coarse][0] * sizes[coarse][1] <= coarse_px:
         coarse += 1
     eecmg.profile_reset()
     eecmg.profile_enable(True, min_pixels=0)

@@ -3,14 +3,15 @@
 The library picks, per level, the strip height of the streaming blur kernels
 (tall, usual or short strips, by how many strips the level yields), whether a
 level folds its finalize kernels into the smoother passes (by tile count),
-whether the CGLS solution update runs every second iteration (by level size),
+whether the CGLS solution updates are deferred to a flush (by level size),
+which leading levels the one-block coarse cascade solves (by level size),
 how many unconfirmed iterations the scheduler keeps queued per job, how many
 steps it keeps queued on the device before it issues the next one and over
 how many lanes (engines with their own streams) a batched call is split.
 Each choice is a threshold read from the environment when a restore is
 planned (EECMG_TALL_MIN_TILES, EECMG_SHORT_MAX_TILES, EECMG_FOLD_MAX_TILES,
-EECMG_FOLD_MAX_TILES_STREAM, EECMG_LAZY_MIN_PIXELS, EECMG_MAX_AHEAD,
-EECMG_PACE_STEPS, EECMG_BATCH_LANES).  This module times restores of
+EECMG_FOLD_MAX_TILES_STREAM, EECMG_LAZY_MIN_PIXELS, EECMG_COARSE_MAX_PIXELS,
+EECMG_MAX_AHEAD, EECMG_PACE_STEPS, EECMG_BATCH_LANES).  This module times restores of
 representative workloads -- the 4096^2 disk and 1024^2 Gaussian single
 images and a batch of images of the uneven set -- and walks the thresholds
 one at a time over a few candidates (coordinate descent, two passes),
@@ -21,9 +22,9 @@ JSON keyed by a hash of the library's sources and the device name, so a
 rebuilt library or another device tunes again.
 
 Only thresholds that leave every result unchanged within the library's
-parity bars are tuned: folding and the every-second-iteration update are
-bit-identical schedules, run-ahead, pacing and lanes only regroup jobs into
-launches, and the strip height only regroups the partial sums
+parity bars are tuned: folding and the deferred updates are bit-identical
+schedules, run-ahead, pacing and lanes only regroup jobs into launches, and
+the strip height and the coarse-cascade limit only regroup the partial sums
 of inner products (tests cover every choice against the oracle).
 """
 from __future__ import annotations
@@ -47,6 +48,7 @@ KNOBS = {
     "EECMG_FOLD_MAX_TILES": (4096, [0, 1024, 4096, 16384]),
     "EECMG_FOLD_MAX_TILES_STREAM": (1 << 30, [0, 512, 2048, 1 << 30]),
     "EECMG_LAZY_MIN_PIXELS": (1 << 20, [1 << 18, 1 << 20, 1 << 40]),
+    "EECMG_COARSE_MAX_PIXELS": (4096, [1024, 4096, 16384]),
     "EECMG_MAX_AHEAD": (2, [2, 3]),
     "EECMG_PACE_STEPS": (2, [0, 2, 3]),
     "EECMG_BATCH_LANES": (3, [1, 2, 3]),
@@ -139,7 +141,9 @@ def tune(torch, eecmg, synth, passes=2, min_gain=0.01, reps=5, log=None) -> dict
     candidate replaces the current setting when, timed against it, the
     geometric mean of the workloads' times drops by more than `min_gain` and
     no single workload gets slower by more than `min_gain` (so a gain on the
-    batches never costs the single large image, or the reverse)."""
+    batches never costs the single large image, or the reverse).  The result
+    is timed against the defaults once more and replaced by them unless it is
+    faster."""
     wl = _Workloads(torch, eecmg, synth)
     best = defaults()
     trials = 0
@@ -161,6 +165,13 @@ def tune(torch, eecmg, synth, passes=2, min_gain=0.01, reps=5, log=None) -> dict
         if not changed:
             break
     final = _ab(wl, best, defaults(), reps)
+    if best != defaults() and _geomean(final) >= 1.0:
+        # the descent's gains did not hold up against the defaults timed in
+        # turn once more: keep the defaults
+        if log:
+            log(f"autotune: tuned settings at {_geomean(final):.4f} of the defaults; keeping the defaults")
+        best = defaults()
+        final = {k: 1.0 for k in final}
     apply(best)
     times = wl.time(reps)
     return {"settings": best, "defaults": defaults(), "trials": trials,

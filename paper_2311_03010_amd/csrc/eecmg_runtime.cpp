@@ -102,8 +102,13 @@ static int sym_span_h(int R, bool disk, int a) {
 // faster: the 4096^2 restore -1.8%, four of them in a batch -2.1%.
 constexpr long kSmallLevelPixels = 512L * 512L;
 // Levels up to this many pixels (the leading ones of a cascade) are solved
-// by one block per job in a single launch.
+// by one block per job in a single launch (EECMG_COARSE_MAX_PIXELS moves the
+// limit; 32^2, 64^2 and 128^2 measured, 64^2 best on the 4096^2 restore).
 constexpr long kCoarsePixels = 64L * 64L;
+static long coarse_max_pixels() {
+  const char* e = std::getenv("EECMG_COARSE_MAX_PIXELS");
+  return e ? std::atol(e) : kCoarsePixels;
+}
 // CGLS levels of at least this many pixels defer their solution updates
 // (k_cg_b's lazy_u mode): pass B moves no u or p, and k_flush_u applies the
 // terms of up to kPRing - 1 iterations in one pass (reading u and their
@@ -379,7 +384,8 @@ static int build_plan(int H, int W, const double* psf, int r, int L, const int* 
   for (int l = 0; l < L; ++l) P.order.push_back(l);
   // leading small levels go to the one-block coarse cascade (full taps)
   P.coarse = 0;
-  while (P.coarse < L && (long)P.lv[P.coarse].h * P.lv[P.coarse].w <= kCoarsePixels) P.coarse += 1;
+  const long coarse_px = coarse_max_pixels();
+  while (P.coarse < L && (long)P.lv[P.coarse].h * P.lv[P.coarse].w <= coarse_px) P.coarse += 1;
   // tiles and layout
   const size_t pitch_elems = P.f64 ? 32 : 64;  // 256-byte rows
   size_t off = 0;

@@ -21,7 +21,8 @@ class _FakeWorkloads:
     # time of each workload as a function of the thresholds set in the
     # environment: separable, minimal at the chosen optimum
     optimum = {"EECMG_TALL_MIN_TILES": 4096, "EECMG_SHORT_MAX_TILES": 512, "EECMG_FOLD_MAX_TILES": 4096,
-               "EECMG_FOLD_MAX_TILES_STREAM": 512, "EECMG_LAZY_MIN_PIXELS": 1 << 20, "EECMG_MAX_AHEAD": 2,
+               "EECMG_FOLD_MAX_TILES_STREAM": 512, "EECMG_LAZY_MIN_PIXELS": 1 << 20,
+               "EECMG_COARSE_MAX_PIXELS": 1024, "EECMG_MAX_AHEAD": 2,
                "EECMG_PACE_STEPS": 3, "EECMG_BATCH_LANES": 2}
 
     def __init__(self, *a, **k):
@@ -73,3 +74,32 @@ def test_cache_used_only_for_the_same_sources_and_device(monkeypatch, tmp_path):
     cache.write_text(json.dumps(c))
     assert autotune.load_or_tune(FakeTorch, None, None, cache=str(cache))["source"] == "tuned"
     assert len(calls) == 2
+
+
+def test_defaults_kept_when_the_final_check_shows_no_gain(monkeypatch):
+    """A change accepted during the descent (its trial looked faster) is
+    dropped when the final comparison against the defaults is not faster."""
+    # one pass of the descent times every candidate but the current one
+    n_descent = sum(len([c for c in cands if c != dflt]) for dflt, cands in autotune.KNOBS.values())
+    calls = {"n": 0, "accepted": False}
+
+    def fake_ab(wl, a, b, reps):
+        calls["n"] += 1
+        gain = a == dict(autotune.defaults(), EECMG_PACE_STEPS=3) and b == autotune.defaults()
+        if gain and calls["n"] <= n_descent:
+            calls["accepted"] = True
+            return {"a": 0.95, "b": 0.96}  # looks faster in the descent
+        if gain:
+            return {"a": 1.01, "b": 1.0}   # ... but not in the final check
+        return {"a": 1.0, "b": 1.0}
+
+    class Flat(_FakeWorkloads):
+        def time(self, reps=5):
+            return {"a": 1.0, "b": 1.0}
+
+    monkeypatch.setattr(autotune, "_Workloads", Flat)
+    monkeypatch.setattr(autotune, "_ab", fake_ab)
+    res = autotune.tune(None, None, None, passes=1)
+    assert calls["accepted"] and calls["n"] == n_descent + 1
+    assert res["settings"] == autotune.defaults()
+    assert res["time_vs_defaults"] == 1.0
