@@ -939,71 +939,30 @@ __device__ __forceinline__ void coarse_sweep(int n, int w, int P, F body) {
 }
 
 // (H x)(i, j) = sum_{a,b} psf(a,b) x(i-a, j-b), zero outside the image, from
-// the full (2R+1)^2 taps (H^T: the flipped taps), for kCoarseU pixels, taps in
-// row-major order.  The loads of kCoarseTapChunk taps (from clamped, always
-// valid positions) are issued together before their products are summed.
-constexpr int kCoarseTapChunk = 2;
+// the full (2R+1)^2 taps (H^T: the flipped taps), for kCoarseU pixels: each
+// tap's loads (from clamped, always valid positions) are issued together.
 template <typename T>
 __device__ __forceinline__ void coarse_conv(const T* __restrict__ x, int pitch, int h, int w,
                                             const T* __restrict__ taps, int R, const Px (&px)[kCoarseU],
                                             T (&acc)[kCoarseU]) {
-  const int n = 2 * R + 1, nt = n * n;
+  const int n = 2 * R + 1;
 #pragma unroll
   for (int m = 0; m < kCoarseU; ++m) acc[m] = T(0);
-  int a = -R, b = -R;  // offsets of the chunk's first tap
-  for (int t0 = 0; t0 < nt; t0 += kCoarseTapChunk) {
-    T wt[kCoarseTapChunk];
-    T v[kCoarseTapChunk][kCoarseU];
-#pragma unroll
-    for (int c = 0; c < kCoarseTapChunk; ++c) {
-      const bool tv = t0 + c < nt;
-      wt[c] = taps[tv ? t0 + c : 0];
+  for (int a = -R; a <= R; ++a) {
+    for (int b = -R; b <= R; ++b) {
+      const T wt = taps[(a + R) * n + (b + R)];
+      T v[kCoarseU];
 #pragma unroll
       for (int m = 0; m < kCoarseU; ++m) {
         const int y = px[m].i - a, xx = px[m].j - b;
-        const bool in = tv && y >= 0 && y < h && xx >= 0 && xx < w;
+        const bool in = y >= 0 && y < h && xx >= 0 && xx < w;
         const T t = x[(size_t)min(max(y, 0), h - 1) * pitch + min(max(xx, 0), w - 1)];
-        v[c][m] = in ? t : T(0);
+        v[m] = in ? t : T(0);
       }
-      if (++b > R) {
-        b = -R;
-        ++a;
-      }
+#pragma unroll
+      for (int m = 0; m < kCoarseU; ++m) acc[m] = fma(wt, v[m], acc[m]);
     }
-#pragma unroll
-    for (int c = 0; c < kCoarseTapChunk; ++c)
-      if (t0 + c < nt) {
-#pragma unroll
-        for (int m = 0; m < kCoarseU; ++m) acc[m] = fma(wt[c], v[c][m], acc[m]);
-      }
   }
-}
-
-// The blur input of a coarse sweep, staged densely in LDS (pitch w) when the
-// blur has more than one tap and the level fits, so the tap loop reads LDS
-// instead of L2 (a 13 x 13 disk is 169 dependent rounds otherwise); else the
-// array itself.  Called by the whole block between sweeps.
-constexpr int kCoarseLdsPixels = 64 * 64;
-template <typename T>
-struct CoarseIn {
-  const T* x;
-  int pitch;
-};
-template <typename T>
-__device__ __noinline__ CoarseIn<T> coarse_in(const T* __restrict__ x, int pitch, int h, int w, int R) {
-  __shared__ T xs[kCoarseLdsPixels];
-  if (R == 0 || h * w > kCoarseLdsPixels) return {x, pitch};
-  __syncthreads();  // the previous sweep's readers of xs are done
-  coarse_sweep(h * w, w, pitch, [&](const Px (&px)[kCoarseU]) {
-    T v[kCoarseU];
-#pragma unroll
-    for (int m = 0; m < kCoarseU; ++m) v[m] = x[px[m].o];
-#pragma unroll
-    for (int m = 0; m < kCoarseU; ++m)
-      if (px[m].ok) xs[px[m].i * w + px[m].j] = v[m];
-  });
-  __syncthreads();
-  return {xs, w};
 }
 
 // One transfer stage over its destination grid, then a block barrier.  The
@@ -1106,12 +1065,11 @@ __device__ void coarse_cgls(const JobDesc& d) {
         }
     });
   } else {
-    const CoarseIn<T> cu = coarse_in(u, P, h, w, R);
     coarse_sweep(n, w, P, [&](const Px (&px)[kCoarseU]) {
       T hv[kCoarseU], gv[kCoarseU];
 #pragma unroll
       for (int m = 0; m < kCoarseU; ++m) gv[m] = g[px[m].o];
-      coarse_conv(cu.x, cu.pitch, h, w, tp, R, px, hv);
+      coarse_conv(u, P, h, w, tp, R, px, hv);
 #pragma unroll
       for (int m = 0; m < kCoarseU; ++m)
         if (px[m].ok) {
@@ -1121,10 +1079,9 @@ __device__ void coarse_cgls(const JobDesc& d) {
         }
     });
     __syncthreads();
-    const CoarseIn<T> cr = coarse_in(r, P, h, w, R);
     coarse_sweep(n, w, P, [&](const Px (&px)[kCoarseU]) {
       T sv[kCoarseU];
-      coarse_conv(cr.x, cr.pitch, h, w, tt, R, px, sv);
+      coarse_conv(r, P, h, w, tt, R, px, sv);
 #pragma unroll
       for (int m = 0; m < kCoarseU; ++m)
         if (px[m].ok) {
@@ -1179,10 +1136,9 @@ __device__ void coarse_cgls(const JobDesc& d) {
           }
       });
     } else {
-      const CoarseIn<T> cp = coarse_in(p, P, h, w, R);
       coarse_sweep(n, w, P, [&](const Px (&px)[kCoarseU]) {
         T qv[kCoarseU];
-        coarse_conv(cp.x, cp.pitch, h, w, tp, R, px, qv);
+        coarse_conv(p, P, h, w, tp, R, px, qv);
 #pragma unroll
         for (int m = 0; m < kCoarseU; ++m)
           if (px[m].ok) {
@@ -1227,10 +1183,9 @@ __device__ void coarse_cgls(const JobDesc& d) {
     });
     if (!pw) {
       __syncthreads();
-      const CoarseIn<T> cr = coarse_in(r, P, h, w, R);
       coarse_sweep(n, w, P, [&](const Px (&px)[kCoarseU]) {
         T sv[kCoarseU];
-        coarse_conv(cr.x, cr.pitch, h, w, tt, R, px, sv);
+        coarse_conv(r, P, h, w, tt, R, px, sv);
 #pragma unroll
         for (int m = 0; m < kCoarseU; ++m)
           if (px[m].ok) {
@@ -1263,12 +1218,11 @@ __device__ void coarse_mr(const JobDesc& d) {
   __shared__ double sc[1];
   __shared__ int done, pending;
   double v[1] = {0.0};
-  const CoarseIn<T> cu = coarse_in(u, P, h, w, R);
   coarse_sweep(n, w, P, [&](const Px (&px)[kCoarseU]) {
     T hv[kCoarseU], gv[kCoarseU];
 #pragma unroll
     for (int m = 0; m < kCoarseU; ++m) gv[m] = g[px[m].o];
-    coarse_conv(cu.x, cu.pitch, h, w, tp, R, px, hv);
+    coarse_conv(u, P, h, w, tp, R, px, hv);
 #pragma unroll
     for (int m = 0; m < kCoarseU; ++m)
       if (px[m].ok) {
@@ -1305,12 +1259,11 @@ __device__ void coarse_mr(const JobDesc& d) {
       __syncthreads();
     }
     double mm[3] = {0.0, 0.0, 0.0};
-    const CoarseIn<T> cr = coarse_in(r, P, h, w, R);
     coarse_sweep(n, w, P, [&](const Px (&px)[kCoarseU]) {
       T qv[kCoarseU], rc[kCoarseU];
 #pragma unroll
       for (int m = 0; m < kCoarseU; ++m) rc[m] = r[px[m].o];
-      coarse_conv(cr.x, cr.pitch, h, w, tp, R, px, qv);
+      coarse_conv(r, P, h, w, tp, R, px, qv);
 #pragma unroll
       for (int m = 0; m < kCoarseU; ++m)
         if (px[m].ok) {
