@@ -49,9 +49,10 @@ class Stats(ctypes.Structure):
 
     def to_dict(self):
         L = self.n_levels
-        return {"sizes": [(self.level_h[i], self.level_w[i]) for i in range(L)],
-                "radius": list(self.psf_radius[:L]), "caps": list(self.caps[:L]), "iters": list(self.iters[:L]),
-                "reason": list(self.stop_reason[:L]), "final_rms": list(self.final_rms[:L])}
+        # (slicing a ctypes array returns a list)
+        return {"sizes": list(zip(self.level_h[:L], self.level_w[:L])),
+                "radius": self.psf_radius[:L], "caps": self.caps[:L], "iters": self.iters[:L],
+                "reason": self.stop_reason[:L], "final_rms": self.final_rms[:L]}
 
 
 class CtxConfig(ctypes.Structure):
@@ -188,10 +189,17 @@ def restore(g_delta, psf, n_levels, caps=None, k=10.0, **kw):
 
 
 def _stream_handle(stream):
+    """The raw HIP stream of a torch stream, else of the current device's
+    current stream (read without building a torch.cuda.Stream object where
+    torch offers that)."""
     import torch
 
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return ctypes.c_void_p(s.cuda_stream)
+    if stream is not None:
+        return ctypes.c_void_p(stream.cuda_stream)
+    raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+    if raw is not None:
+        return ctypes.c_void_p(raw(torch.cuda.current_device()))
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
 def _torch_dtype(precision):
