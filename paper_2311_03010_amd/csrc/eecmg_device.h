@@ -540,6 +540,16 @@ struct NoInterior {
 
 constexpr int kPrefetch = 2;
 
+// Element offset of row y (uniform), hidden from the optimizer by an empty
+// asm statement (no instruction): otherwise it folds the per-step row
+// offsets of an unrolled row group into per-lane offsets that it keeps in
+// vector registers across the strip loop, and the streaming kernels spill.
+__device__ __forceinline__ unsigned row_offset(int y, int pitch) {
+  unsigned o = (unsigned)(y * pitch);
+  asm volatile("" : "+s"(o));
+  return o;
+}
+
 // none: the out-of-range element offset of the level's arrays (h x pitch).
 // Loads at none return 0 (combine(0) must be 0, the zero boundary), and
 // interior/emit receive none as the offset of pixels outside the image, so
@@ -548,6 +558,18 @@ constexpr int kPrefetch = 2;
 // direction only).  Strips of odd tile rows do, so two vertically adjacent
 // strips reach the rows their halos share at the same time and the second
 // read of those rows finds them in L2.
+// A strip whose rows, halo included, all lie inside the image skips the
+// per-row tests in the row groups between its first and its last.  The wave issues one
+// instruction at a time, and on levels with two waves per SIMD those tests
+// (a few scalar compares and selects per stream and row) are a large part
+// of what it issues.  Every access and result is the same either way.
+template <bool Tests>
+struct StripMode {
+  static constexpr bool kRows = Tests;   // test that rows lie in the image
+  static constexpr bool kSteps = Tests;  // test the step against the strip's phases
+};
+using StripAll = StripMode<true>;
+using StripInner = StripMode<false>;
 template <typename T, typename P, typename InF, typename CombF, typename IntLoadF, typename IntF, typename EmLoadF,
           typename EmF>
 __device__ __forceinline__ void stream_strip(const TileGeo& g, bool up, unsigned none, typename P::St& st, InF load_in,
@@ -583,28 +605,29 @@ __device__ __forceinline__ void stream_strip(const TileGeo& g, bool up, unsigned
   const int ybase = up ? g.y0 + TH + R - 1 : g.y0 - R, ystep = up ? -1 : 1;
   auto row_at = [&](int t) { return ybase + ystep * t; };
   auto out_at = [&](int t) { return ybase + ystep * (t - R); };
-  auto issue = [&](int t, VI& a, VI& b, VN& n, VE& e) {
+  // the tests a mode keeps (see StripMode); those it drops hold for its rows
+  auto issue = [&](int t, VI& a, VI& b, VN& n, VE& e, auto mode) {
+    using Md = decltype(mode);
     const int y = row_at(t);
-    const bool row_ok = t < LH && y >= 0 && y < g.h;
-    const unsigned base = (unsigned)(y * g.pitch);
+    const bool row_ok = (!Md::kSteps || t < LH) && (!Md::kRows || (y >= 0 && y < g.h));
+    const unsigned base = row_offset(y, g.pitch);
     a = load_in((row_ok && in1) ? base + (unsigned)c1 : none);
     b = load_in((row_ok && in2) ? base + (unsigned)c2 : none);
-    n = load_int((row_ok && t >= R && t < R + TH && inic) ? base + (unsigned)ic : none);
+    n = load_int((row_ok && (!Md::kSteps || (t >= R && t < R + TH)) && inic) ? base + (unsigned)ic : none);
     const int yo = out_at(t);
-    const bool emit_ok = t >= 2 * R && t < LH && yo < g.h;
-    e = load_em((emit_ok && inec) ? (unsigned)(yo * g.pitch + ec) : none);
+    const unsigned obase = row_offset(yo, g.pitch);
+    const bool emit_ok = (!Md::kSteps || (t >= 2 * R && t < LH)) && (!Md::kRows || yo < g.h);
+    e = load_em((emit_ok && inec) ? obase + (unsigned)ec : none);
   };
-#pragma unroll
-  for (int t = 0; t < D; ++t) issue(t, pa[t], pb[t], pn[t], pe[t]);
-#pragma unroll 1
-  for (int gi = 0; gi < NG; ++gi) {
+  auto group = [&](int gi, auto mode) __attribute__((always_inline)) {
+    using Md = decltype(mode);
 #pragma unroll
     for (int kg = 0; kg < GS; ++kg) {
       const int t = gi * GS + kg, k = kg % NW;  // k = t mod NW
       const VI a = pa[kg], b = pb[kg];
       const VN n = pn[kg];
       const VE e = pe[kg];
-      issue(t + D, pa[(kg + D) % GS], pb[(kg + D) % GS], pn[(kg + D) % GS], pe[(kg + D) % GS]);
+      issue(t + D, pa[(kg + D) % GS], pb[(kg + D) % GS], pn[(kg + D) % GS], pe[(kg + D) % GS], mode);
       const int y = row_at(t);
       const T v1 = combine(a);
       const T v2 = combine(b);
@@ -614,8 +637,9 @@ __device__ __forceinline__ void stream_strip(const TileGeo& g, bool up, unsigned
       // interior and emit run on every step (outside their rows with in =
       // false and offset none), so no memory operation sits in a branch
       {
-        const bool in = t >= R && t < R + TH && y < g.h && inic;
-        interior(in ? (unsigned)(y * g.pitch + ic) : none, lane >= R ? v1 : v2, in, n);
+        const unsigned base = row_offset(y, g.pitch);
+        const bool in = (!Md::kSteps || (t >= R && t < R + TH)) && (!Md::kRows || y < g.h) && inic;
+        interior(in ? base + (unsigned)ic : none, lane >= R ? v1 : v2, in, n);
       }
       wave_lds_sync();
       const T* row = rb + lane + R;
@@ -623,11 +647,28 @@ __device__ __forceinline__ void stream_strip(const TileGeo& g, bool up, unsigned
       const T out = P::step(st, row, k);
       {
         const int yo = out_at(t);
-        const bool in = t >= 2 * R && yo < g.h && inec;
-        emit(in ? (unsigned)(yo * g.pitch + ec) : none, out, in, cen[((k - R) % NW + NW) % NW], e);
+        const unsigned obase = row_offset(yo, g.pitch);
+        const bool in = (!Md::kSteps || t >= 2 * R) && (!Md::kRows || yo < g.h) && inec;
+        emit(in ? obase + (unsigned)ec : none, out, in, cen[((k - R) % NW + NW) % NW], e);
       }
     }
-  }
+  };
+  // Between the first and the last group every step lies past the strip's
+  // first 2R rows (GS > 2R), and its prefetch (D <= GS - R rows ahead) stays
+  // inside the interior rows, so no step test can fail there.
+  static_assert(GS > 2 * R && D + R <= GS, "strip phases must fit in one row group");
+  const bool inside = g.y0 - R >= 0 && g.y0 + TH + R <= g.h;
+  // groups [0, lo) and [hi, NG) with the tests, [lo, hi) without
+  const int lo = inside ? 1 : NG, hi = inside ? NG - 1 : NG;
+#pragma unroll
+  for (int t = 0; t < D; ++t) issue(t, pa[t], pb[t], pn[t], pe[t], StripAll{});
+  int gi = 0;
+#pragma unroll 1
+  for (; gi < lo; ++gi) group(gi, StripAll{});
+#pragma unroll 1
+  for (; gi < hi; ++gi) group(gi, StripInner{});
+#pragma unroll 1
+  for (; gi < NG; ++gi) group(gi, StripAll{});
 }
 
 // ---------------------------------------------------------------------------
