@@ -8,7 +8,9 @@ output or prefetch slot is reused while still pending, that every interior
 row is handled once, and that every LDS access lies inside the row buffer.
 Strips may also walk bottom-up: the row mapping then still visits every
 interior row once and completes every output row from the 2R + 1 input rows
-centred on it."""
+centred on it.  A strip whose rows all lie inside the image runs the row
+groups between its first and its last without the per-row tests: every one
+of those tests holds there, for every radius, strip height and direction."""
 import pytest
 
 KTH, KTW, PREFETCH = 32, 64, 2
@@ -20,11 +22,11 @@ def strip_group(R):
     return NW * ((4 + 2 * R) // NW)
 
 
-def strip_th(R, tall=False):
-    """Mirror of strip_th(): smallest height >= 32 (tall strips: >= 64) with
-    (height + 2R) a multiple of the group size."""
+def strip_th(R, tall=False, short=False):
+    """Mirror of strip_th(): smallest height >= 32 (tall strips: >= 64, short
+    strips: >= 8) with (height + 2R) a multiple of the group size."""
     GS = strip_group(R)
-    base = 2 * KTH if tall else KTH
+    base = 2 * KTH if tall else (KTH // 4 if short else KTH)
     return GS * ((base + 2 * R + GS - 1) // GS) - 2 * R
 
 
@@ -109,3 +111,37 @@ def test_strip_row_mapping(R, up, tall):
     for t in range(2 * R, LH):
         # the window of steps t - 2R .. t holds the rows out_at(t) - R .. out_at(t) + R
         assert sorted(row_at(u) for u in range(t - 2 * R, t + 1)) == list(range(out_at(t) - R, out_at(t) + R + 1))
+
+
+@pytest.mark.parametrize("mode", ["usual", "tall", "short"])
+@pytest.mark.parametrize("R", list(range(0, 13)))
+@pytest.mark.parametrize("up", [False, True])
+def test_inner_groups_need_no_tests(R, mode, up):
+    """Mirror of the tests stream_strip drops in the middle row groups of a
+    strip inside the image: the prefetch of row t + D (in the image, inside
+    the strip, interior-row load, output-row load) and the interior and
+    output stores of step t all hold for every step of groups 1 .. NG - 2."""
+    TH = strip_th(R, tall=mode == "tall", short=mode == "short")
+    LH, GS = TH + 2 * R, strip_group(R)
+    NG, D = LH // GS, min(GS, PREFETCH)
+    # the conditions the kernel asserts at compile time
+    assert GS > 2 * R and D + R <= GS
+    h = 7 * TH + 3  # a ragged image height
+    for y0 in range(0, h, TH):
+        inside = y0 - R >= 0 and y0 + TH + R <= h
+        ybase, ystep = (y0 + TH + R - 1, -1) if up else (y0 - R, 1)
+        row_at = lambda t: ybase + ystep * t
+        out_at = lambda t: ybase + ystep * (t - R)
+        rows = [row_at(t) for t in range(LH)]
+        assert inside == all(0 <= y < h for y in rows)
+        if not inside:
+            continue
+        for gi in range(1, NG - 1):
+            for kg in range(GS):
+                t, tp = gi * GS + kg, gi * GS + kg + D
+                row_ok = tp < LH and 0 <= row_at(tp) < h
+                assert row_ok
+                assert R <= tp < R + TH  # interior-row load of the prefetched row
+                assert tp >= 2 * R and tp < LH and out_at(tp) < h  # output-row load
+                assert R <= t < R + TH and row_at(t) < h  # interior store
+                assert t >= 2 * R and out_at(t) < h  # output store
