@@ -559,10 +559,10 @@ __device__ __forceinline__ unsigned row_offset(int y, int pitch) {
 // strips reach the rows their halos share at the same time and the second
 // read of those rows finds them in L2.
 // A strip whose rows, halo included, all lie inside the image skips the
-// per-row tests in the row groups between its first and its last.  The wave issues one
-// instruction at a time, and on levels with two waves per SIMD those tests
-// (a few scalar compares and selects per stream and row) are a large part
-// of what it issues.  Every access and result is the same either way.
+// per-row tests in the row groups between its first and its last: they are
+// a few scalar compares and selects per stream and row, about a quarter of
+// the instructions a wave issues per row.  Every access and result is the
+// same either way.
 template <bool Tests>
 struct StripMode {
   static constexpr bool kRows = Tests;   // test that rows lie in the image
