@@ -178,6 +178,38 @@ def test_short_strip_smoother_parity(torch_cuda, monkeypatch, psfname):
     assert _rel(res["short"][0], res["usual"][0]) <= 1e-5
 
 
+# ------------------------------------------------ strips inside the image
+@pytest.mark.parametrize("smoother", ["cgls", "mr"])
+@pytest.mark.parametrize("psfname", ["disk3", "symdisk3"])
+def test_f64_streaming_smoother_parity_on_a_ragged_level(torch_cuda, smoother, psfname):
+    """A 1100 x 1000 FP64 level runs the streaming kernels on usual strips
+    (uniform-disk and symmetric-disk policies): most strips lie inside the
+    image and walk their middle row groups without per-row tests, the
+    strips of the last strip row and column are ragged.  CGLS and MR from a
+    smoothed start match the FP64 oracle."""
+    H, W = 1100, 1000
+    rng = np.random.Generator(np.random.PCG64(H + W + len(psfname) + len(smoother)))
+    a = np.arange(-3, 4)
+    d2 = a[:, None] ** 2 + a[None, :] ** 2
+    symdisk = np.where(d2 <= 9, 1.0 / (1.0 + d2), 0.0)
+    psf = {"disk3": synth.disk_psf(3), "symdisk3": symdisk / symdisk.sum()}[psfname]
+    u_true = synth.scene(H, W, 60, rng)
+    g = synth.blur(u_true, psf) + rng.standard_normal((H, W))
+    u0 = synth.blur(g, synth.gaussian_psf(1.0, 2))
+    cap = 5
+    t = torch_cuda
+    print(f"  {smoother} {psfname} {H}x{W} f64", flush=True)
+    gd = t.from_numpy(g).to("cuda:0")
+    ud = t.from_numpy(u0).to("cuda:0")
+    u, st = eecmg.smoother_dev(gd, ud, psf, cap, precision="f64", smoother=smoother, stop_rule=False)
+    t.cuda.synchronize()
+    fn = oracle.cgls if smoother == "cgls" else oracle.mr
+    u_ref, it, hist, why = fn(g, psf, u0=u0, cap=cap, eps=GUARD["f64"])
+    print(f"  iters gpu={st['iters']} oracle={it} rel={_rel(u.cpu().numpy(), u_ref):.2e}", flush=True)
+    assert st["iters"] == it and st["reason"] == why
+    assert _rel(u.cpu().numpy(), u_ref) <= 1e-12
+
+
 # ------------------------------------------------------------ step pacing
 def test_step_pacing_depth_leaves_batched_results_bitwise_unchanged(torch_cuda, monkeypatch):
     """The scheduler's step pacing (how many steps it keeps queued on the
