@@ -924,14 +924,38 @@ __global__ __launch_bounds__(P::NT) __attribute__((amdgpu_waves_per_eu(P::kWaves
                     [&](T v, unsigned, int row) { gsh[row * P::TW + g.lane] = v; });
     __syncthreads();
     const int gx = g.x0 + g.lane;
+    constexpr int KV = P::TH / 4;  // output rows per thread: wave * KV + 0 .. KV - 1
+    T rk[KV];
     P::conv(tile, (const T*)d.taps, g.R, g.wave, g.lane, [&](int v, T acc) {
       const int gy = g.y0 + v;
       const T rv = gsh[v * P::TW + g.lane] - acc;
-      if (gy < g.h && gx < g.w) {
+      const bool in = gy < g.h && gx < g.w;
+      if (in) {
         r[(unsigned)(gy * g.pitch + gx)] = rv;
         part[0] += (double)rv * (double)rv;
       }
+      rk[v - g.wave * KV] = in ? rv : T(0);
     });
+    if ((ll.flags & kLaunchInitS) && g.R == 0) {
+      // one-tap blur: s = H^T r from the tile of r just formed, laid out and
+      // zero outside the image as k_cg_init2 would load it, by the same
+      // product in the same order (so the same bits as that kernel)
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < KV; ++v) tile[(g.wave * KV + v) * P::LW + g.lane] = rk[v];
+      __syncthreads();
+      auto s = gp<T>(d.s);
+      double both[2] = {part[0], 0.0};  // partials <r,r> (slot 1) and <s,s> (slot 2)
+      P::conv(tile, (const T*)d.taps_t, 0, g.wave, g.lane, [&](int v, T acc) {
+        const int gy = g.y0 + v;
+        if (gy < g.h && gx < g.w) {
+          s[(unsigned)(gy * g.pitch + gx)] = acc;
+          both[1] += (double)acc * (double)acc;
+        }
+      });
+      block_sum_store<P::NT, 2>(both, d.partials + (size_t)1 * d.pstride + L.t, d.pstride);
+      return;
+    }
   }
   block_sum_store<P::NT, 1>(part, d.partials + (size_t)1 * d.pstride + L.t, d.pstride);
 }

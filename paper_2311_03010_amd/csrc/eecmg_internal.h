@@ -131,7 +131,10 @@ __host__ __device__ inline uint64_t mirror_word(uint32_t tag, int32_t k, int32_t
 // entry e evaluates the finalize still owed before iteration kf[e] (the
 // previous pass B's, or at iteration 0 the initialisation's); kf[e] < 0: none
 // is owed.  Both only for jobs whose level has fold_a set.
-enum : int32_t { kLaunchFoldA = 1, kLaunchFoldB = 2 };
+// kLaunchInitS: the initialisation's first launch also forms s = H^T r for
+// the jobs whose level has a one-tap blur on the general tiles (their r needs
+// no halo), which then skip the second launch.
+enum : int32_t { kLaunchFoldA = 1, kLaunchFoldB = 2, kLaunchInitS = 4 };
 
 struct LaunchList {
   int32_t n;

@@ -1504,8 +1504,14 @@ class Engine {
       const bool f64 = kv.first.second >= 100000;
       const int rc = kv.first.second % 100000;
       if (kv.first.first == EECMG_SMOOTHER_CGLS) {
-        launch_group(kCgInit1, kv.second, -1, f64, rc, -1, -1);
-        launch_group(kCgInit2, kv.second, -1, f64, rc, -1, -1);
+        // a one-tap blur on the general tiles forms s in the first launch
+        const int kind = variant_kind(rc);
+        const bool general = kind == kConvGeneral || kind == kConvGenShort;
+        std::vector<Job*> need_s;
+        for (Job* j : kv.second)
+          if (!general || j->plan.lv[j->cur_level()].rad != 0) need_s.push_back(j);
+        launch_group(kCgInit1, kv.second, -1, f64, rc, -1, -1, nullptr, nullptr, general ? kLaunchInitS : 0);
+        if (!need_s.empty()) launch_group(kCgInit2, need_s, -1, f64, rc, -1, -1);
         for (Job* j : kv.second) {
           const LevelPlan& lp = j->plan.lv[j->cur_level()];
           if (lp.fold_a && lp.cap >= 1)
